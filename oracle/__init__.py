@@ -1,0 +1,188 @@
+"""Brute-force CPU oracle for the non-metric neighbour lists and Vicsek step.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package.  The GPU library
+never imports, links or calls it, and it shares no code with the GPU path.
+
+The arithmetic lives in ``nm_oracle.c`` (plain C, fp64, OpenMP over rows);
+this module only marshals numpy arrays through ctypes.  What each function
+computes, with the passage of arXiv:2103.10239 it follows:
+
+- ``knn``: the topological rule of Sec. III -- the k nearest neighbours of
+  every particle, by evaluating all N^2 pairs (the naive cost named in
+  Sec. I), ordered by (squared minimum-image distance, index).
+- ``metric_list``: the metric rule of Sec. III -- every j with distance at
+  most r_0, as CSR rows ordered the same way.
+- ``align_step``: Eq. (2) (alignment with vectorial noise, normalised) and
+  Eq. (1) (Euler move with the heading at time t), in fp64.
+- ``philox4x32_10`` / ``noise_word`` / ``noise_angle``: the counter-based
+  generator (Salmon et al., SC'11) that supplies the random unit vector of
+  Eq. (2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OK, E_INVAL, E_RANGE, E_CAPACITY, E_NOMEM = 0, -1, -2, -3, -4
+
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_vp = ctypes.c_void_p
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _build  # noqa: F401  (build on first use)
+        _build.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    lib.orc_philox4x32_10.restype = None
+    lib.orc_noise_word.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64]
+    lib.orc_noise_word.restype = ctypes.c_uint32
+    lib.orc_noise_angle.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64]
+    lib.orc_noise_angle.restype = ctypes.c_double
+    lib.orc_d2.argtypes = [ctypes.c_int32] * 5
+    lib.orc_d2.restype = ctypes.c_int64
+    lib.orc_knn.argtypes = [_i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                            _vp, ctypes.c_int32, _i32p, _vp]
+    lib.orc_knn.restype = ctypes.c_int
+    lib.orc_metric_count.argtypes = [_i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                     _vp, ctypes.c_int32, _i64p]
+    lib.orc_metric_count.restype = ctypes.c_int
+    lib.orc_metric_fill.argtypes = [_i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                    _vp, ctypes.c_int32, _i64p, _i32p, _vp]
+    lib.orc_metric_fill.restype = ctypes.c_int
+    lib.orc_align_step.argtypes = [_i32p, _i32p, _f32p, ctypes.c_int32, ctypes.c_int32,
+                                   _i32p, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                   ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint64,
+                                   _vp, ctypes.c_int32, _i32p, _i32p, _f32p]
+    lib.orc_align_step.restype = ctypes.c_int
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != OK:
+        raise OracleError(f"{what}: oracle status {rc}")
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _rows_arg(rows, n):
+    if rows is None:
+        return None, n, None
+    r = _i32(rows)
+    return r.ctypes.data_as(_vp), int(r.size), r
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle runs on."""
+    return int(_load().orc_num_threads())
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    """One Philox4x32-10 block: 4 counter words, 2 key words -> 4 words."""
+    out = np.zeros(4, dtype=np.uint32)
+    _load().orc_philox4x32_10(np.asarray(ctr, dtype=np.uint32), np.asarray(key, dtype=np.uint32), out)
+    return out
+
+
+def noise_word(seed: int, sys_id: int, step: int, i: int) -> int:
+    return int(_load().orc_noise_word(seed, sys_id, step, i))
+
+
+def noise_angle(seed: int, sys_id: int, step: int, i: int) -> float:
+    return float(_load().orc_noise_angle(seed, sys_id, step, i))
+
+
+def d2(xa: int, ya: int, xb: int, yb: int, box: int) -> int:
+    return int(_load().orc_d2(xa, ya, xb, yb, box))
+
+
+def knn(x, y, box: int, k: int, rows=None, with_d2: bool = True):
+    """k nearest neighbours (Sec. III), brute force.  Returns (nbr, d2)."""
+    x, y = _i32(x), _i32(y)
+    n = int(x.size)
+    rp, nr, _keep = _rows_arg(rows, n)
+    nbr = np.zeros(nr * k, dtype=np.int32)
+    dd = np.zeros(nr * k, dtype=np.int64) if with_d2 else None
+    rc = _load().orc_knn(x, y, n, box, k, rp, nr, nbr, dd.ctypes.data_as(_vp) if with_d2 else None)
+    _check(rc, "knn")
+    return nbr.reshape(nr, k), (dd.reshape(nr, k) if with_d2 else None)
+
+
+def metric_list(x, y, box: int, rc2: int, rows=None, with_d2: bool = True):
+    """Metric neighbour lists (Sec. III) as CSR.  Returns (offsets int64[n+1], idx, d2)."""
+    x, y = _i32(x), _i32(y)
+    n = int(x.size)
+    rp, nr, _keep = _rows_arg(rows, n)
+    counts = np.zeros(nr, dtype=np.int64)
+    _check(_load().orc_metric_count(x, y, n, box, rc2, rp, nr, counts), "metric_count")
+    offsets = np.zeros(nr + 1, dtype=np.int64)
+    np.cumsum(counts, out=offsets[1:])
+    nnz = int(offsets[-1])
+    idx = np.zeros(max(nnz, 1), dtype=np.int32)
+    dd = np.zeros(max(nnz, 1), dtype=np.int64) if with_d2 else None
+    rc = _load().orc_metric_fill(x, y, n, box, rc2, rp, nr, offsets, idx,
+                                 dd.ctypes.data_as(_vp) if with_d2 else None)
+    _check(rc, "metric_fill")
+    return offsets, idx[:nnz], (dd[:nnz] if with_d2 else None)
+
+
+def align_step(x, y, theta, box: int, nbr=None, offsets=None, idx=None, *, v0: int, eta: float,
+               seed: int, sys_id: int = 0, include_self: int = 1, step: int = 0, rows=None):
+    """Eq. (2) then Eq. (1) for each listed particle, fp64.
+
+    Neighbour lists are either ``nbr`` (int32[rows, k]) or CSR ``offsets`` +
+    ``idx``.  Returns (x', y', theta') for the listed rows.
+    """
+    x, y = _i32(x), _i32(y)
+    theta = np.ascontiguousarray(theta, dtype=np.float32)
+    n = int(x.size)
+    rp, nr, _keep = _rows_arg(rows, n)
+    if offsets is not None:
+        offs = np.ascontiguousarray(offsets, dtype=np.int64)
+        lst = _i32(idx) if idx is not None and len(idx) else np.zeros(1, dtype=np.int32)
+        offp, k = offs.ctypes.data_as(_vp), 0
+    else:
+        nb = _i32(nbr)
+        k = int(nb.shape[1]) if nb.ndim == 2 else int(nb.size // max(nr, 1))
+        lst = nb.reshape(-1) if nb.size else np.zeros(1, dtype=np.int32)
+        offp, offs = None, None
+    xo = np.zeros(nr, dtype=np.int32)
+    yo = np.zeros(nr, dtype=np.int32)
+    to = np.zeros(nr, dtype=np.float32)
+    rc = _load().orc_align_step(x, y, theta, n, box, lst, offp, k, v0, eta, seed, sys_id,
+                                include_self, step, rp, nr, xo, yo, to)
+    _check(rc, "align_step")
+    return xo, yo, to
+
+
+def step(x, y, theta, box: int, k: int, *, v0: int, eta: float, seed: int, sys_id: int = 0,
+         include_self: int = 1, step_index: int = 0):
+    """One full step of the fundamental loop (Alg. 1) in the topological model:
+    rebuild the k-NN lists from r(t), then Eq. (2) and Eq. (1) from time-t state."""
+    nbr, _ = knn(x, y, box, k, with_d2=False)
+    xo, yo, to = align_step(x, y, theta, box, nbr=nbr, v0=v0, eta=eta, seed=seed, sys_id=sys_id,
+                            include_self=include_self, step=step_index)
+    return nbr, xo, yo, to

@@ -1,0 +1,424 @@
+"""Pins for the brute-force oracle (CPU only).
+
+The oracle is the definition written out; these tests tie it to things other
+than itself: published known-answer vectors, hand-worked examples, closed
+forms (lattices, two-particle bisectors, global averages), exact symmetries
+of the periodic integer box, and an independent library routine (scipy's
+periodic k-d tree) for distances.  Each test names the passage of
+arXiv:2103.10239 (or of the generator's paper) it pins.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+from scipy.spatial import cKDTree
+
+import oracle
+from paper_2103_10239_amd import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+L = 1 << 20
+
+
+def _rows(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 (Salmon et al. SC'11) -> the random unit vector of Eq. (2)
+# --------------------------------------------------------------------------
+def test_philox_known_answers():
+    for row in _rows("philox4x32_10_kat.txt"):
+        v = [int(t, 16) for t in row]
+        got = oracle.philox4x32_10(v[0:4], v[4:6])
+        assert [int(g) for g in got] == v[6:10]
+
+
+def test_noise_counter_layout():
+    # Word (i mod 4) of the block at counter (i/4, step lo, step hi, sys_id), key = seed.
+    seed, sys_id = 0x0123456789ABCDEF, 77
+    for step in (0, 5, (1 << 32) + 3):
+        for i in (0, 1, 2, 3, 4, 9, 1_000_003):
+            blk = oracle.philox4x32_10([i // 4, step & 0xFFFFFFFF, step >> 32, sys_id],
+                                       [seed & 0xFFFFFFFF, seed >> 32])
+            assert oracle.noise_word(seed, sys_id, step, i) == int(blk[i % 4])
+
+
+def test_noise_angle_range_and_uniformity():
+    phis = np.array([oracle.noise_angle(0, 0, 1, i) for i in range(20000)])
+    assert phis.min() >= -math.pi and phis.max() < math.pi
+    # Kolmogorov-Smirnov against U[-pi, pi): D < 1.63/sqrt(n) at the 1% level.
+    s = np.sort((phis + math.pi) / (2 * math.pi))
+    n = s.size
+    d = max(np.max(np.arange(1, n + 1) / n - s), np.max(s - np.arange(n) / n))
+    assert d < 1.63 / math.sqrt(n)
+    # Delta-correlated in particle index and in time (Eq. 2): lag-1 correlations vanish.
+    nxt = np.array([oracle.noise_angle(0, 0, 2, i) for i in range(20000)])
+    assert abs(np.corrcoef(phis[:-1], phis[1:])[0, 1]) < 0.03
+    assert abs(np.corrcoef(phis, nxt)[0, 1]) < 0.03
+
+
+def test_noise_angle_endpoints():
+    # u = 0 gives exactly -pi; the map is monotone in u.
+    # Find the particle whose noise word is smallest among a few and check ordering.
+    ws = [(oracle.noise_word(3, 0, 0, i), oracle.noise_angle(3, 0, 0, i)) for i in range(64)]
+    ws.sort()
+    angles = [a for _, a in ws]
+    assert angles == sorted(angles)
+    for u, a in ws:
+        assert abs(a - (-math.pi + 2 * math.pi * u / 2**32)) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# Minimum-image squared distance (periodic box, boundary conditions of Sec. I)
+# --------------------------------------------------------------------------
+def test_min_image_closed_forms():
+    assert oracle.d2(0, 0, L - 1, 0, L) == 1
+    assert oracle.d2(0, 0, 0, L - 1, L) == 1
+    assert oracle.d2(0, 0, L // 2, 0, L) == (L // 2) ** 2      # delta = -L/2 exactly
+    assert oracle.d2(0, 0, L // 2 - 1, L // 2 - 1, L) == 2 * (L // 2 - 1) ** 2
+    assert oracle.d2(10, 20, 13, 24, L) == 25
+    assert oracle.d2(5, 5, 5, 5, L) == 0
+    # non-power-of-two box
+    assert oracle.d2(0, 0, 9, 0, 10) == 1
+    assert oracle.d2(0, 0, 5, 0, 10) == 25
+
+
+# --------------------------------------------------------------------------
+# Topological rule (Sec. III): the k nearest neighbours
+# --------------------------------------------------------------------------
+def _scipy_d2(x, y, k):
+    tree = cKDTree(np.stack([x, y], 1).astype(np.float64), boxsize=float(L))
+    d, _ = tree.query(np.stack([x, y], 1).astype(np.float64), k=k + 1)
+    return np.rint(d * d).astype(np.int64)
+
+
+@pytest.mark.parametrize("kind,n,k", [("uniform", 2000, 1), ("uniform", 2000, 7),
+                                      ("uniform", 1500, 20), ("clustered", 3000, 6),
+                                      ("clustered", 3000, 12)])
+def test_knn_distances_match_periodic_kdtree(kind, n, k):
+    gen = workloads.uniform if kind == "uniform" else workloads.clustered
+    x, y, _ = gen(n)
+    _, d2 = oracle.knn(x, y, L, k)
+    ref = _scipy_d2(x, y, k)
+    # The k+1 smallest distances over all points including self = {0} + the k neighbours.
+    mine = np.sort(np.concatenate([np.zeros((n, 1), np.int64), d2], 1), 1)
+    assert np.array_equal(mine, np.sort(ref, 1))
+
+
+def _lattice_expected(m, k):
+    """Closed form on an m x m lattice (spacing a): axis neighbours at a^2, then
+    diagonals at 2a^2; within a shell the smaller index comes first."""
+    out = []
+    for i in range(m * m):
+        r, c = divmod(i, m)
+        axis = sorted({((r + dr) % m) * m + (c + dc) % m for dr, dc in ((0, 1), (0, -1), (1, 0), (-1, 0))})
+        diag = sorted({((r + dr) % m) * m + (c + dc) % m for dr in (1, -1) for dc in (1, -1)})
+        out.append((axis + diag)[:k])
+    return np.array(out, dtype=np.int32)
+
+
+@pytest.mark.parametrize("k", [1, 4, 7, 8])
+def test_knn_lattice_ties(k):
+    m = 32
+    x, y, a = workloads.lattice(m)
+    nbr, d2 = oracle.knn(x, y, L, k)
+    assert np.array_equal(nbr, _lattice_expected(m, k))
+    exp_d2 = np.array([a * a] * min(k, 4) + [2 * a * a] * max(0, k - 4), dtype=np.int64)
+    assert np.array_equal(d2, np.broadcast_to(exp_d2, d2.shape))
+
+
+def test_knn_wrap_pair():
+    nbr, d2 = oracle.knn([0, L - 1], [0, 0], L, 1)
+    assert nbr.tolist() == [[1], [0]] and d2.tolist() == [[1], [1]]
+
+
+def test_knn_nonreciprocal_worked_example():
+    rows = _rows("nonreciprocal_k1.txt")
+    x = [int(r[1]) for r in rows]
+    nbr, d2 = oracle.knn(x, [0] * len(x), L, 1)
+    assert nbr[:, 0].tolist() == [int(r[2]) for r in rows]
+    assert d2[:, 0].tolist() == [int(r[3]) for r in rows]
+    assert nbr[0, 0] == 1 and nbr[1, 0] == 2          # 0 -> 1 but not 1 -> 0
+
+
+def test_knn_all_duplicates():
+    n, k = 40, 39
+    nbr, d2 = oracle.knn([123] * n, [456] * n, L, k)
+    for i in range(n):
+        assert nbr[i].tolist() == [j for j in range(n) if j != i]
+    assert not d2.any()
+
+
+@pytest.mark.parametrize("k", [3, 7])
+def test_knn_exact_symmetries(k):
+    x, y, _ = workloads.clustered(1500)
+    base, _ = oracle.knn(x, y, L, k)
+    tx, ty = 123457, 987
+    shifted, _ = oracle.knn((x.astype(np.int64) + tx) % L, (y.astype(np.int64) + ty) % L, L, k)
+    rot, _ = oracle.knn((L - y.astype(np.int64)) % L, x, L, k)           # 90 degree rotation
+    refl, _ = oracle.knn((L - x.astype(np.int64)) % L, y, L, k)          # mirror x -> -x
+    assert np.array_equal(base, shifted)
+    assert np.array_equal(base, rot)
+    assert np.array_equal(base, refl)
+
+
+def _check_knn_invariants(x, y, k, nbr, d2):
+    n = len(x)
+    x = np.asarray(x, np.int64)
+    y = np.asarray(y, np.int64)
+    for i in range(n):
+        row = nbr[i].tolist()
+        assert len(set(row)) == k and i not in row
+        dx = (x - x[i] + L // 2) % L - L // 2
+        dy = (y - y[i] + L // 2) % L - L // 2
+        all_d2 = dx * dx + dy * dy
+        assert np.array_equal(d2[i], all_d2[nbr[i]])
+        keys = list(zip(d2[i].tolist(), row))
+        assert keys == sorted(keys) and len(set(keys)) == k
+        others = [(int(all_d2[j]), j) for j in range(n) if j != i and j not in row]
+        if others:
+            assert max(keys) < min(others)
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(2, 60).flatmap(lambda n: st.tuples(
+    st.lists(st.integers(0, L - 1), min_size=n, max_size=n),
+    st.lists(st.integers(0, L - 1), min_size=n, max_size=n),
+    st.integers(1, n - 1), st.booleans())))
+def test_knn_invariants_property(args):
+    xs, ys, k, squeeze = args
+    if squeeze:  # force many duplicates and ties
+        xs = [v % 4 * 1000 for v in xs]
+        ys = [v % 3 * 1000 for v in ys]
+    nbr, d2 = oracle.knn(xs, ys, L, k)
+    _check_knn_invariants(xs, ys, k, nbr, d2)
+
+
+def test_knn_sampled_rows_equal_full():
+    x, y, _ = workloads.uniform(3000)
+    full, fd2 = oracle.knn(x, y, L, 7)
+    rows = np.array([0, 17, 2999, 1500, 17])
+    part, pd2 = oracle.knn(x, y, L, 7, rows=rows)
+    assert np.array_equal(part, full[rows]) and np.array_equal(pd2, fd2[rows])
+
+
+def test_knn_rejects_bad_args():
+    with pytest.raises(oracle.OracleError):
+        oracle.knn([0, 1], [0, 1], L, 2)           # k >= n
+    with pytest.raises(oracle.OracleError):
+        oracle.knn([0, L], [0, 1], L, 1)           # coordinate outside [0, L)
+
+
+def test_knn_not_symmetric_on_clustered_input():
+    x, y, _ = workloads.clustered(4000)
+    nbr, _ = oracle.knn(x, y, L, 6)
+    pairs = {(i, int(j)) for i in range(len(x)) for j in nbr[i]}
+    assert any((j, i) not in pairs for (i, j) in pairs)
+
+
+# --------------------------------------------------------------------------
+# Metric rule (Sec. III): every pair within r_0
+# --------------------------------------------------------------------------
+def _csr_rows(offsets, idx):
+    return [idx[offsets[i]:offsets[i + 1]].tolist() for i in range(len(offsets) - 1)]
+
+
+@pytest.mark.parametrize("kind,n,mean", [("uniform", 3000, 7.0), ("clustered", 3000, 3.0)])
+def test_metric_matches_periodic_ball_query(kind, n, mean):
+    gen = workloads.uniform if kind == "uniform" else workloads.clustered
+    x, y, _ = gen(n)
+    rc2 = workloads.rc2_for_mean(n, mean)
+    offsets, idx, d2 = oracle.metric_list(x, y, L, rc2)
+    tree = cKDTree(np.stack([x, y], 1).astype(np.float64), boxsize=float(L))
+    balls = tree.query_ball_point(np.stack([x, y], 1).astype(np.float64), r=math.sqrt(rc2 + 0.5))
+    rows = _csr_rows(offsets, idx)
+    for i in range(n):
+        assert sorted(rows[i]) == sorted(j for j in balls[i] if j != i)
+        keys = list(zip(d2[offsets[i]:offsets[i + 1]].tolist(), rows[i]))
+        assert keys == sorted(keys)
+        assert all(dd <= rc2 for dd, _ in keys)
+
+
+def test_metric_lists_are_symmetric():
+    x, y, _ = workloads.clustered(3000)
+    offsets, idx, _ = oracle.metric_list(x, y, L, workloads.rc2_for_mean(3000, 5.0))
+    rows = [set(r) for r in _csr_rows(offsets, idx)]
+    for i, r in enumerate(rows):
+        for j in r:
+            assert i in rows[j]
+
+
+def test_metric_lattice_shells():
+    x, y, a = workloads.lattice(32)
+    offsets, idx, _ = oracle.metric_list(x, y, L, a * a)
+    assert np.array_equal(offsets, np.arange(0, 4 * 1024 + 1, 4))
+    assert np.array_equal(idx.reshape(-1, 4), _lattice_expected(32, 4))
+    offsets, idx, _ = oracle.metric_list(x, y, L, a * a - 1)
+    assert not offsets.any() and idx.size == 0
+    offsets, _, _ = oracle.metric_list(x, y, L, 2 * a * a)
+    assert np.array_equal(np.diff(offsets), np.full(1024, 8))
+
+
+def test_metric_contains_knn_at_kth_radius():
+    x, y, _ = workloads.uniform(1500)
+    nbr, d2 = oracle.knn(x, y, L, 7)
+    rows = np.array([3, 99, 1000])
+    for r in rows:
+        offs, idx, _ = oracle.metric_list(x, y, L, int(d2[r, -1]), rows=[r])
+        assert set(nbr[r].tolist()) <= set(idx.tolist())
+        assert idx[:7].tolist() == nbr[r].tolist()
+
+
+# --------------------------------------------------------------------------
+# Alignment, Eq. (2), and the Euler move, Eq. (1)
+# --------------------------------------------------------------------------
+def _wrap_angle(a):
+    return (np.asarray(a, np.float64) + np.pi) % (2 * np.pi) - np.pi
+
+
+def test_three_particle_worked_step():
+    rows = _rows("three_particle_step.txt")
+    x = [int(r[1]) for r in rows]
+    y = [int(r[2]) for r in rows]
+    th = np.array([float(r[3]) for r in rows], np.float32)
+    nbr = np.array([[int(r[4])] for r in rows], np.int32)
+    xo, yo, to = oracle.align_step(x, y, th, L, nbr=nbr, v0=64, eta=0.0, seed=0)
+    assert xo.tolist() == [int(r[5]) for r in rows]
+    assert yo.tolist() == [int(r[6]) for r in rows]
+    assert np.abs(_wrap_angle(to - np.array([float(r[7]) for r in rows]))).max() < 1e-6
+    # the worked lists are the oracle's own k = 1 lists here
+    nn, _ = oracle.knn(x, y, L, 1)
+    assert np.array_equal(nn, nbr)
+
+
+def test_align_equal_headings_fixed_point():
+    x, y, _ = workloads.uniform(500)
+    th = np.full(500, 0.7, np.float32)
+    nbr, _ = oracle.knn(x, y, L, 7)
+    _, _, to = oracle.align_step(x, y, th, L, nbr=nbr, v0=64, eta=0.0, seed=0)
+    assert np.array_equal(to, th)
+
+
+def test_align_two_particle_bisector():
+    th = np.array([0.3, 1.1], np.float32)
+    xo, yo, to = oracle.align_step([0, 5000], [0, 0], th, L, nbr=[[1], [0]], v0=64, eta=0.0, seed=0)
+    bis = (float(th[0]) + float(th[1])) / 2
+    assert abs(to[0] - bis) < 1e-7 and abs(to[1] - bis) < 1e-7
+    # without the particle's own heading each one copies the other (dropped self-term check)
+    _, _, to2 = oracle.align_step([0, 5000], [0, 0], th, L, nbr=[[1], [0]], v0=64, eta=0.0, seed=0,
+                                  include_self=0)
+    assert to2[0] == th[1] and to2[1] == th[0]
+
+
+def test_align_all_to_all_is_global_mean_direction():
+    n = 64
+    x, y, th = workloads.uniform(n)
+    nbr, _ = oracle.knn(x, y, L, n - 1)
+    _, _, to = oracle.align_step(x, y, th, L, nbr=nbr, v0=64, eta=0.0, seed=0)
+    mean_dir = math.atan2(np.sin(th.astype(np.float64)).sum(), np.cos(th.astype(np.float64)).sum())
+    assert np.abs(_wrap_angle(to - mean_dir)).max() < 1e-6
+
+
+def test_align_rotation_equivariance():
+    n = 800
+    x, y, th = workloads.uniform(n)
+    nbr, _ = oracle.knn(x, y, L, 7)
+    _, _, t0 = oracle.align_step(x, y, th, L, nbr=nbr, v0=64, eta=0.0, seed=0)
+    alpha = 0.5
+    _, _, t1 = oracle.align_step(x, y, (th + alpha).astype(np.float32), L, nbr=nbr, v0=64, eta=0.0,
+                                 seed=0)
+    assert np.abs(_wrap_angle(t1 - t0 - alpha)).max() < 2e-6
+
+
+def test_align_noise_dominates():
+    n = 300
+    x, y, th = workloads.uniform(n)
+    nbr, _ = oracle.knn(x, y, L, 7)
+    _, _, to = oracle.align_step(x, y, th, L, nbr=nbr, v0=64, eta=1e6, seed=9, step=4, sys_id=2)
+    phi = np.array([oracle.noise_angle(9, 2, 4, i) for i in range(n)])
+    assert np.abs(_wrap_angle(to - phi)).max() < 1e-5
+
+
+def test_align_empty_list_zero_vector_keeps_heading():
+    th = np.array([0.25, -2.0], np.float32)
+    offsets = np.zeros(3, np.int64)
+    _, _, to = oracle.align_step([0, 500000], [0, 0], th, L, offsets=offsets, idx=[], v0=64, eta=0.0,
+                                 seed=0, include_self=0)
+    assert np.array_equal(to, th)
+    # isolated particle, no self term, with noise: the new heading is the noise angle
+    _, _, to = oracle.align_step([0, 500000], [0, 0], th, L, offsets=offsets, idx=[], v0=64, eta=0.2,
+                                 seed=11, step=3, include_self=0)
+    phi = [oracle.noise_angle(11, 0, 3, i) for i in range(2)]
+    assert np.abs(_wrap_angle(to - np.array(phi))).max() < 1e-6
+
+
+def test_move_closed_forms():
+    th = np.array([0.0, np.float32(np.pi / 2), np.float32(np.pi), 0.0, np.float32(-np.pi / 2)], np.float32)
+    x = [100, 100, 100, L - 10, 5]
+    y = [200, 200, 200, 7, 3]
+    nbr = np.zeros((5, 0), np.int32)
+    xo, yo, _ = oracle.align_step(x, y, th, L, nbr=nbr, v0=64, eta=0.0, seed=0)
+    assert xo.tolist() == [164, 100, 36, 54, 5]
+    assert yo.tolist() == [200, 264, 200, 7, L - 61]
+
+
+def test_move_keeps_unit_speed():
+    n = 5000
+    rng = np.random.default_rng(0)
+    th = rng.uniform(-np.pi, np.pi, n).astype(np.float32)
+    x = np.full(n, L // 2, np.int32)
+    y = np.full(n, L // 2, np.int32)
+    for v0 in (1, 64, 1000):
+        xo, yo, _ = oracle.align_step(x, y, th, L, nbr=np.zeros((n, 0), np.int32), v0=v0, eta=0.0, seed=0)
+        sp = np.hypot(xo.astype(np.float64) - L // 2, yo.astype(np.float64) - L // 2)
+        assert np.abs(sp - v0).max() <= math.sqrt(0.5) + 1e-12
+
+
+def test_new_heading_is_finite_unit_direction():
+    x, y, th = workloads.clustered(2000)
+    nbr, _ = oracle.knn(x, y, L, 12)
+    _, _, to = oracle.align_step(x, y, th, L, nbr=nbr, v0=64, eta=0.2, seed=0)
+    assert np.isfinite(to).all() and np.abs(to).max() <= np.float32(np.pi)
+
+
+def test_step_moves_with_old_heading():
+    # Alg. 1 / Eq. (1): the position update uses n_i(t), not the freshly aligned heading.
+    x, y = [0, 3000], [0, 0]
+    th = np.array([0.0, np.float32(np.pi / 2)], np.float32)
+    nbr, xo, yo, to = oracle.step(x, y, th, L, 1, v0=64, eta=0.0, seed=0)
+    assert xo.tolist() == [64, 3000] and yo.tolist() == [0, 64]
+    assert abs(to[0] - np.pi / 4) < 1e-6 and abs(to[1] - np.pi / 4) < 1e-6
+
+
+def test_metric_mode_alignment_uses_csr_rows():
+    n = 1200
+    x, y, th = workloads.uniform(n)
+    rc2 = workloads.rc2_for_mean(n, 7.0)
+    offsets, idx, _ = oracle.metric_list(x, y, L, rc2)
+    xo, yo, to = oracle.align_step(x, y, th, L, offsets=offsets, idx=idx, v0=64, eta=0.2, seed=1)
+    # same result as the fixed-k path on rows that happen to have exactly k entries
+    k = 7
+    sel = np.where(np.diff(offsets) == k)[0]
+    assert sel.size > 10
+    nb = np.stack([idx[offsets[i]:offsets[i] + k] for i in sel])
+    xr, yr, tr = oracle.align_step(x, y, th, L, nbr=nb, v0=64, eta=0.2, seed=1, rows=sel)
+    assert np.array_equal(xr, xo[sel]) and np.array_equal(yr, yo[sel]) and np.array_equal(tr, to[sel])
+
+
+@pytest.mark.parametrize("include_self,k", [(0, 1), (1, 1), (0, 3), (1, 3)])
+def test_align_half_angle_identity(include_self, k):
+    # Every heading is 0, so the average of Eq. (2) is exactly (1, 0) whatever m is; with
+    # eta = 1 the new heading is arg((1, 0) + xi) = phi / 2 (half-angle identity).  A wrong
+    # neighbour count m scales the average and breaks the identity.
+    n = k + 1
+    x = [i * 1000 for i in range(n)]
+    th = np.zeros(n, np.float32)
+    nbr, _ = oracle.knn(x, [0] * n, L, k)
+    _, _, to = oracle.align_step(x, [0] * n, th, L, nbr=nbr, v0=64, eta=1.0, seed=21, step=8,
+                                 include_self=include_self)
+    phi = np.array([oracle.noise_angle(21, 0, 8, i) for i in range(n)])
+    assert np.abs(_wrap_angle(to - phi / 2)).max() < 1e-6
