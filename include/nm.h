@@ -1,0 +1,173 @@
+/*
+ * nm.h -- C ABI of the MI355X (gfx950) library for non-metric neighbour
+ * lists and the Vicsek alignment step.
+ *
+ * Method: D. M. Sussman, "Non-metric interaction rules in models of active
+ * matter", arXiv:2103.10239.  One time step of the fundamental loop (Alg. 1)
+ * rebuilds the neighbour lists and applies the interactions:
+ *   - cell lists make neighbour finding O(N) and parallel (Sec. I);
+ *   - topological neighbours: the k nearest of each particle (Sec. III);
+ *   - metric neighbours: every particle within r_0 (Sec. III);
+ *   - alignment with vectorial noise, Eq. (2), and the Euler move, Eq. (1).
+ *
+ * Conventions (readings of points the paper leaves open):
+ *   - 2D periodic square box of side L; coordinates are int32 in [0, L);
+ *     L is a power of two, 2 <= L <= 2^20; distances use the minimum image
+ *     with each axis offset in [-L/2, L/2), squared distances are exact
+ *     integers (int64).
+ *   - Neighbours are ordered by the pair (d^2, j): ties at equal distance go
+ *     to the smaller particle index.  A particle is never its own neighbour;
+ *     coincident particles (d^2 = 0) are valid neighbours.
+ *   - The metric rule is inclusive: d^2 <= rc2.
+ *   - Eq. (2): theta'_i = arg(eta * xi_i + (1/m_i) sum_j n_j), where the sum
+ *     runs over the list of i plus i itself when include_self = 1
+ *     (m_i = |list| + include_self).  If the argument is exactly the zero
+ *     vector, theta'_i = theta_i.  xi_i = (cos phi_i, sin phi_i) with
+ *     phi_i = (u_i * 2^-32) * 2pi - pi (fp64, each operation rounded), and
+ *     u_i is word (i mod 4) of Philox4x32-10 (Salmon et al., SC'11) at
+ *     counter (i / 4, step mod 2^32, step >> 32, sys_id), key (seed mod 2^32,
+ *     seed >> 32).
+ *   - Eq. (1) with the heading at time t and dt = 1:
+ *     x'_i = (x_i + rint(v0 cos theta_i)) mod L, likewise y with sin,
+ *     rint rounding half to even, evaluated in fp64.
+ *   - Headings are fp32; neighbour lists and positions are exact, headings
+ *     agree with an fp64 evaluation of Eq. (2) to well within 1e-5 rad.
+ *
+ * Memory and ownership.  Every pointer argument named x, y, theta, nbr, d2,
+ * offsets, idx, *_out or ws is a DEVICE pointer owned by the caller; nm_grid
+ * and nm_params are HOST pointers read during the call only.  `stream` is a
+ * hipStream_t (0 = the null stream).  Calls enqueue work on `stream` and
+ * return without synchronising unless documented otherwise; they never
+ * allocate device memory.  Host-detectable argument errors return NM_E_INVAL
+ * before anything is enqueued.  Data-dependent errors found on the device
+ * (a coordinate outside [0, L), an out-of-range neighbour index, a metric
+ * list over capacity) are recorded in the workspace's error word and
+ * reported by nm_check(); the affected outputs are then unspecified.  Calls
+ * that share a workspace must be ordered on one stream; calls with distinct
+ * workspaces are independent.
+ */
+#ifndef NM_H_
+#define NM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes returned by every call (no exceptions cross the ABI). */
+#define NM_OK 0
+#define NM_E_INVAL (-1)    /* invalid argument (host) or index/grid mismatch (device) */
+#define NM_E_RANGE (-2)    /* a coordinate outside [0, L) reached the device          */
+#define NM_E_CAPACITY (-3) /* metric list longer than the caller's capacity           */
+#define NM_E_NOMEM (-4)    /* served form: a job can never fit the memory budget      */
+#define NM_E_DEVICE (-5)   /* HIP launch/runtime failure                              */
+
+/* Largest k the topological search supports (register-resident lists). */
+#define NM_MAX_K 32
+
+/* Geometry of one system's cell grid (Sec. I: a grid of cells of width w). */
+typedef struct nm_grid {
+  int32_t n;      /* particles, 2 <= n <= 2^24                                     */
+  int32_t box;    /* L, power of two in [2, 2^20]                                  */
+  int32_t cell_w; /* w, power of two in [1, L]; (L/w)^2 <= 2^28 cells              */
+  int32_t flags;  /* reserved, must be 0                                           */
+} nm_grid;
+
+/* Parameters of Eq. (1) and Eq. (2). */
+typedef struct nm_params {
+  int32_t box;          /* L, same rules as nm_grid.box                            */
+  int32_t v0;           /* displacement per step in grid units, |v0| < L/2         */
+  float eta;            /* noise strength, finite and >= 0                         */
+  int32_t include_self; /* 1: own heading joins the average, 0: it does not       */
+  uint64_t seed;        /* Philox key                                              */
+  uint32_t sys_id;      /* Philox counter word 3 (system identity)                 */
+  uint32_t reserved;    /* must be 0                                               */
+} nm_params;
+
+/* Human-readable name of a status code (static string). */
+const char* nm_status_str(int status);
+
+/* Bytes of device workspace a grid needs (cell table, sorted particle copy,
+ * scan state, error word).  Returns < 0 (an NM_E_* code) if the grid is
+ * invalid.  The workspace must be 256-byte aligned (hipMalloc/torch are). */
+int64_t nm_workspace_bytes(const nm_grid* g);
+
+/* A cell width for n particles in a box of side L: the power of two w that
+ * puts about `per_cell` particles in a cell on average (uniform density).
+ * Host-only helper; the batched/served forms refine it by measurement. */
+int32_t nm_suggest_cell_w(int32_t n, int32_t box, double per_cell);
+
+/* Prepare a freshly allocated workspace: zero the cell histogram and stamp
+ * the header.  Call once per workspace (and again after reuse for another
+ * grid).  Enqueued on `stream`. */
+int nm_workspace_init(const nm_grid* g, void* ws, size_t ws_bytes, void* stream);
+
+/* Cell binning (Sec. I, cell lists): counting sort of the particles by cell.
+ *   x, y   int32[n]  positions at time t, each in [0, L)
+ *   ws     workspace of nm_workspace_bytes(g) bytes, initialised
+ * Writes the per-cell start table and a cell-ordered copy of the particles
+ * into `ws`.  Particles with a coordinate outside [0, L) are left out and
+ * flag NM_E_RANGE. */
+int nm_build_cells(const nm_grid* g, const int32_t* x, const int32_t* y, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* Topological neighbour list (Sec. III, "the k nearest neighbours"), from
+ * the cells built by nm_build_cells/nm_step on the same grid.
+ *   k      1 <= k <= min(NM_MAX_K, n - 1)
+ *   nbr    int32[n * k], row i = the k nearest neighbours of particle i,
+ *          ascending by (d^2, j), indices in the caller's particle order
+ *   d2     int64[n * k] or NULL: the matching squared distances */
+int nm_knn(const nm_grid* g, const void* ws, int32_t k, int32_t* nbr, int64_t* d2,
+           void* stream);
+
+/* Metric neighbour list (Sec. III, "all pairs within r_0") as CSR rows in
+ * the caller's particle order, each row ascending by (d^2, j).
+ *   rc2      r_0^2 in grid units^2, 0 <= rc2 < 2^40
+ *   offsets  int32[n + 1]: always written; offsets[n] = nnz
+ *   idx      int32[cap] or NULL.  NULL: count pass only.  Otherwise rows are
+ *            filled if nnz <= cap; if nnz > cap nothing is written to idx and
+ *            NM_E_CAPACITY is recorded (and returned when nnz_host != NULL)
+ *   nnz_host host int64* or NULL.  Non-NULL: the call synchronises `stream`
+ *            and stores nnz there (the two-call protocol: count, allocate,
+ *            fill).  NULL: no synchronisation.
+ * nnz must stay below 2^31 (else NM_E_CAPACITY). */
+int nm_metric_list(const nm_grid* g, void* ws, int64_t rc2, int32_t* offsets, int32_t* idx,
+                   int64_t cap, int64_t* nnz_host, void* stream);
+
+/* Alignment and move for every particle, Eq. (2) then Eq. (1), from time-t
+ * state (Alg. 1: lists and headings at t give theta(t+1); positions at t
+ * and headings at t give r(t+1)).
+ *   x, y, theta     int32/int32/fp32 [n], time t
+ *   nbr             fixed-k lists int32[n * k] (offsets == NULL), k >= 0, or
+ *                   CSR column indices int32[nnz_cap] (offsets != NULL)
+ *   offsets         int32[n + 1] CSR row starts, or NULL
+ *   nnz_cap         length of the CSR index array (ignored for fixed k)
+ *   x_out, y_out, theta_out  [n], time t+1; must not alias the inputs
+ * Neighbour indices outside [0, n) or malformed CSR rows are skipped and
+ * flag NM_E_INVAL in `ws_err` (a workspace, or NULL to skip reporting). */
+int nm_align_step(const int32_t* x, const int32_t* y, const float* theta, int32_t n,
+                  const int32_t* nbr, const int32_t* offsets, int32_t k, int64_t nnz_cap,
+                  const nm_params* p, uint64_t step, int32_t* x_out, int32_t* y_out,
+                  float* theta_out, void* ws_err, void* stream);
+
+/* One full step of the topological model (Alg. 1): cell binning, k-NN lists
+ * and the fused alignment + move, in three kernels.  Same arguments and
+ * results as nm_build_cells + nm_knn + nm_align_step(include the same k),
+ * bit for bit in the lists and positions.  The cells left in `ws` describe
+ * the time-t positions and can feed nm_metric_list / nm_knn afterwards.
+ *   p->box must equal g->box. */
+int nm_step(const nm_grid* g, const int32_t* x, const int32_t* y, const float* theta,
+            int32_t k, const nm_params* p, uint64_t step, void* ws, size_t ws_bytes,
+            int32_t* nbr, int32_t* x_out, int32_t* y_out, float* theta_out, void* stream);
+
+/* Synchronise `stream`, return the first error recorded in `ws` since the
+ * last check (NM_OK if none) and clear it. */
+int nm_check(void* ws, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NM_H_ */

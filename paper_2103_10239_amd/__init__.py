@@ -1,0 +1,11 @@
+"""MI355X (gfx950) non-metric neighbour lists and Vicsek alignment.
+
+Implements the data-parallel hot path of one time step of the fundamental
+simulation loop in D. M. Sussman, "Non-metric interaction rules in models of
+active matter" (arXiv:2103.10239): cell binning, k-nearest (topological) and
+cutoff (metric) neighbour lists, and the alignment / move of Eq. (2) and
+Eq. (1), as hand-written HIP kernels behind the C ABI of include/nm.h.
+"""
+from . import nm, workloads  # noqa: F401
+from .nm import (Grid, NMError, Params, System, Workspace, align_step, build_cells, check, knn,  # noqa: F401
+                 make_params, metric_list, step, suggest_cell_w)

@@ -1,0 +1,231 @@
+// cells.hip -- cell binning (Sec. I: partition the box into a grid of cells
+// so that neighbour finding only looks at nearby cells).
+//
+// Counting sort in three kernels:
+//   bin_count   per particle: cell id, rank inside the cell (atomic histogram)
+//   scan        exclusive prefix sum of the histogram -> cell start table,
+//               single pass with decoupled look-back; clears the histogram
+//   bin_scatter per particle: write (x, y, index, noise word) to its slot in
+//               cell order; the fused step also stores (cos, sin) of the
+//               heading in fp64 and draws the Philox noise word here, where
+//               four consecutive particles share one Philox block.
+#include "nm_internal.h"
+
+namespace nm {
+
+namespace {
+
+constexpr unsigned long long kFlagAgg = 1ull << 62;     // tile aggregate available
+constexpr unsigned long long kFlagPrefix = 2ull << 62;  // inclusive prefix available
+constexpr unsigned long long kValueMask = (1ull << 62) - 1ull;
+constexpr int kSpinLimit = 1 << 22;
+
+__device__ void reset_scan(ScanState* st, int nb) {
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) st->flags[t] = 0ull;
+  if (threadIdx.x == 0) st->ticket = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ws_init(DevWs w) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < w.C; c += stride)
+    w.count[c] = 0;
+  if (blockIdx.x == 0) {
+    reset_scan(w.scan_c, w.nb_scan_c);
+    reset_scan(w.scan_m, w.nb_scan_m);
+    if (threadIdx.x == 0) {
+      w.hdr->magic = kMagic;
+      w.hdr->err = 0;
+      w.hdr->n = w.n;
+      w.hdr->box = w.box;
+      w.hdr->cell_w = w.cell_w;
+      w.hdr->built = 0u;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* __restrict__ x,
+                                                      const int32_t* __restrict__ y, DevWs w) {
+  if (blockIdx.x == 0) {
+    reset_scan(w.scan_c, w.nb_scan_c);
+    if (threadIdx.x == 0) {
+      if (w.hdr->magic != kMagic || w.hdr->n != w.n || w.hdr->box != w.box ||
+          w.hdr->cell_w != w.cell_w)
+        set_err(w.hdr, NM_E_INVAL);
+      w.hdr->built = 0u;
+    }
+  }
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= w.n) return;
+  const int xi = x[i], yi = y[i];
+  if (static_cast<uint32_t>(xi) >= static_cast<uint32_t>(w.box) ||
+      static_cast<uint32_t>(yi) >= static_cast<uint32_t>(w.box)) {
+    set_err(w.hdr, NM_E_RANGE);
+    w.rank[i] = -1;
+    return;
+  }
+  const int64_t c = static_cast<int64_t>(yi >> w.log2_w) * w.G + (xi >> w.log2_w);
+  w.rank[i] = atomicAdd(&w.count[c], 1);
+}
+
+// Exclusive prefix sum of in[0, m) into out[0, m], out[m] = total.  `in` may
+// alias `out`.  With clear_in (and in != out) the input is zeroed after it
+// is read.  Tiles take increasing tickets, so every predecessor of a tile is
+// already running when the tile waits on it: the look-back always ends.
+__global__ __launch_bounds__(kBlock) void k_scan(int32_t* in, int32_t* out, int64_t m,
+                                                 ScanState* st, WsHeader* hdr, int clear_in) {
+  __shared__ uint32_t s_tile;
+  __shared__ long long s_wave[kBlock / 64];
+  __shared__ long long s_prefix;
+  if (threadIdx.x == 0) s_tile = atomicAdd(&st->ticket, 1u);
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const int64_t base = static_cast<int64_t>(tile) * kScanTile + threadIdx.x * kScanItems;
+
+  int32_t v[kScanItems];
+  long long sum = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const int64_t idx = base + j;
+    v[j] = idx < m ? in[idx] : 0;
+    sum += v[j];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  long long incl = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const long long t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) s_wave[wave] = incl;
+  __syncthreads();
+  long long wave_off = 0, agg = 0;
+#pragma unroll
+  for (int q = 0; q < kBlock / 64; ++q) {
+    if (q < wave) wave_off += s_wave[q];
+    agg += s_wave[q];
+  }
+  if (threadIdx.x == 0) {
+    unsigned long long* flags = st->flags;
+    long long prefix = 0;
+    if (tile == 0) {
+      __hip_atomic_store(&flags[0], kFlagPrefix | static_cast<unsigned long long>(agg),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(&flags[tile], kFlagAgg | static_cast<unsigned long long>(agg),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int j = static_cast<int>(tile) - 1;
+      int spins = 0;
+      while (true) {
+        const unsigned long long f =
+            __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((f & ~kValueMask) == 0ull) {
+          if (++spins > kSpinLimit) {
+            set_err(hdr, NM_E_DEVICE);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        prefix += static_cast<long long>(f & kValueMask);
+        if ((f & ~kValueMask) == kFlagPrefix || j == 0) break;
+        --j;
+      }
+      __hip_atomic_store(&flags[tile], kFlagPrefix | static_cast<unsigned long long>(prefix + agg),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_prefix = prefix;
+    if ((prefix + agg) > 0x7FFFFFFFll) set_err(hdr, NM_E_CAPACITY);
+  }
+  __syncthreads();
+  long long run = s_prefix + wave_off + (incl - sum);
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const int64_t idx = base + j;
+    if (idx < m) {
+      out[idx] = static_cast<int32_t>(run);
+      if (clear_in) in[idx] = 0;
+    }
+    run += v[j];
+  }
+  const int64_t ntiles = (m + kScanTile - 1) / kScanTile;
+  if (threadIdx.x == 0 && static_cast<int64_t>(tile) == (ntiles > 0 ? ntiles - 1 : 0))
+    out[m] = static_cast<int32_t>(s_prefix + agg);
+}
+
+template <bool kFused>
+__global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restrict__ x,
+                                                        const int32_t* __restrict__ y,
+                                                        const float* __restrict__ theta, DevWs w,
+                                                        uint32_t step_lo, uint32_t step_hi,
+                                                        uint32_t sys_id, uint32_t seed_lo,
+                                                        uint32_t seed_hi) {
+  const WsHeader* h = w.hdr;
+  if (h->magic != kMagic || h->n != w.n || h->box != w.box || h->cell_w != w.cell_w) return;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int i0 = 4 * t;
+  if (i0 >= w.n) return;
+  uint4 noise = make_uint4(0u, 0u, 0u, 0u);
+  if (kFused) noise = Philox::block(make_uint4(static_cast<uint32_t>(t), step_lo, step_hi, sys_id),
+                                    seed_lo, seed_hi);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = i0 + q;
+    if (i >= w.n) break;
+    const int r = w.rank[i];
+    if (r < 0) continue;
+    const int xi = x[i], yi = y[i];
+    const int64_t c = static_cast<int64_t>(yi >> w.log2_w) * w.G + (xi >> w.log2_w);
+    const int pos = w.start[c] + r;
+    if (static_cast<uint32_t>(pos) >= static_cast<uint32_t>(w.n)) {  // inconsistent table
+      set_err(w.hdr, NM_E_INVAL);
+      continue;
+    }
+    w.sorted[pos] = make_int4(xi, yi, i, static_cast<int>(uint4_word(noise, q)));
+    if (kFused) {
+      double sn, cs;
+      sincos(static_cast<double>(theta[i]), &sn, &cs);
+      w.cs[pos] = make_double2(cs, sn);
+    }
+  }
+  if (t == 0) w.hdr->built = kBuilt;
+}
+
+}  // namespace
+
+hipError_t launch_ws_init(const DevWs& w, hipStream_t s) {
+  const int64_t want = (w.C + kBlock - 1) / kBlock;
+  const int blocks = static_cast<int>(want < 4096 ? (want > 0 ? want : 1) : 4096);
+  hipLaunchKernelGGL(k_ws_init, dim3(blocks), dim3(kBlock), 0, s, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_build(const DevWs& w, const int32_t* x, const int32_t* y, const float* theta,
+                        const nm_params* p, uint64_t step, hipStream_t s) {
+  const int nb = (w.n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_bin_count, dim3(nb), dim3(kBlock), 0, s, x, y, w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan, dim3(w.nb_scan_c), dim3(kBlock), 0, s, w.count, w.start, w.C, w.scan_c,
+                     w.hdr, 1);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nq = (w.n + 4 * kBlock - 1) / (4 * kBlock);
+  if (theta != nullptr && p != nullptr) {
+    hipLaunchKernelGGL(k_bin_scatter<true>, dim3(nq), dim3(kBlock), 0, s, x, y, theta, w,
+                       static_cast<uint32_t>(step), static_cast<uint32_t>(step >> 32), p->sys_id,
+                       static_cast<uint32_t>(p->seed), static_cast<uint32_t>(p->seed >> 32));
+  } else {
+    hipLaunchKernelGGL(k_bin_scatter<false>, dim3(nq), dim3(kBlock), 0, s, x, y, theta, w, 0u, 0u,
+                       0u, 0u, 0u);
+  }
+  return hipGetLastError();
+}
+
+// Shared with the metric list: prefix sum over the row lengths.
+hipError_t launch_scan_rows(int32_t* data, int64_t m, ScanState* st, int nb, WsHeader* hdr,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(nb), dim3(kBlock), 0, s, data, data, m, st, hdr, 0);
+  return hipGetLastError();
+}
+
+}  // namespace nm

@@ -1,0 +1,131 @@
+// metric.hip -- metric neighbour lists (Sec. III: "all pairs of particles
+// within some distance r_0 count as neighbours"), built from the same cells
+// as the topological lists, as CSR rows in the caller's particle order.
+//
+// Three kernels: count the row lengths (one lane per query, cell order),
+// prefix-sum them into the row offsets (the scan of cells.hip), and fill the
+// rows.  Rows must be ascending by (d^2, index), so the fill pass selects the
+// row in chunks of kChunk keys: each pass walks the same cells and keeps the
+// kChunk smallest keys above the last key already written.
+#include "nm_internal.h"
+
+namespace nm {
+
+namespace {
+
+constexpr int kChunk = 16;
+
+__device__ __forceinline__ bool ws_ready(const DevWs& w) {
+  const WsHeader* h = w.hdr;
+  return h->built == kBuilt && h->n == w.n && h->box == w.box && h->cell_w == w.cell_w;
+}
+
+// Visit every particle t != s of the cells that can hold a point within rc2
+// of the query; f(t, d2, index) is called for those with d2 <= rc2.
+template <class F>
+__device__ __forceinline__ void for_each_within(const DevWs& w, int s, int qx, int qy,
+                                                long long rc2, int total, F&& f) {
+  const int sh = 32 - w.log2_box;
+  const int cw = 1 << w.log2_w;
+  const int gm = w.G - 1;
+  const QueryGeom q(qx, qy, w);
+  for (int r = 0; r <= q.rmax; ++r) {
+    for_ring(r, q.lo, q.hi, [&](int dx, int dy) {
+      const long long gx = axis_gap(dx, q.ox, cw, sh);
+      const long long gy = axis_gap(dy, q.oy, cw, sh);
+      if (gx * gx + gy * gy > rc2) return;
+      const int64_t c = static_cast<int64_t>((q.hy + dy) & gm) * w.G + ((q.hx + dx) & gm);
+      const int beg = w.start[c];
+      const int end = min(w.start[c + 1], total);
+      for (int t = beg; t < end; ++t) {
+        if (t == s) continue;
+        const int4 e = w.sorted[t];
+        const int ex = wrap_axis(e.x - qx, sh);
+        const int ey = wrap_axis(e.y - qy, sh);
+        const long long d2 = static_cast<long long>(ex) * ex + static_cast<long long>(ey) * ey;
+        if (d2 <= rc2) f(t, d2, e.z);
+      }
+    });
+    if (rc2 < q.ring_bound(r, cw)) break;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_metric_count(DevWs w, long long rc2,
+                                                         int32_t* __restrict__ offsets) {
+  if (blockIdx.x == 0) {
+    for (int t = threadIdx.x; t < w.nb_scan_m; t += blockDim.x) w.scan_m->flags[t] = 0ull;
+    if (threadIdx.x == 0) w.scan_m->ticket = 0u;
+  }
+  if (!ws_ready(w)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) set_err(w.hdr, NM_E_INVAL);
+    return;
+  }
+  const int total = min(w.start[w.C], w.n);
+  const int s = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (s >= total) return;
+  const int4 q = w.sorted[s];
+  int cnt = 0;
+  for_each_within(w, s, q.x, q.y, rc2, total, [&](int, long long, int) { ++cnt; });
+  offsets[q.z] = cnt;
+}
+
+__global__ __launch_bounds__(kBlock) void k_metric_fill(DevWs w, long long rc2,
+                                                        const int32_t* __restrict__ offsets,
+                                                        int32_t* __restrict__ idx, long long cap) {
+  if (!ws_ready(w)) return;
+  const long long nnz = offsets[w.n];
+  if (nnz > cap || nnz < 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) set_err(w.hdr, NM_E_CAPACITY);
+    return;
+  }
+  const int total = min(w.start[w.C], w.n);
+  const int s = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (s >= total) return;
+  const int4 q = w.sorted[s];
+  const long long base = offsets[q.z];
+  const long long m = static_cast<long long>(offsets[q.z + 1]) - base;
+  if (base < 0 || m < 0 || base + m > nnz) {
+    set_err(w.hdr, NM_E_INVAL);
+    return;
+  }
+  long long written = 0;
+  unsigned long long last = 0ull;  // every real key is >= 1
+  while (written < m) {
+    const int need = static_cast<int>(min<long long>(kChunk, m - written));
+    TopK<kChunk, false> top;
+    top.init(need);
+    for_each_within(w, s, q.x, q.y, rc2, total, [&](int t, long long d2, int j) {
+      const unsigned long long kk = pack_key(d2, j);
+      if (kk > last && kk < top.worst()) top.push(kk, t);
+    });
+    if (top.worst() == ~0ull) {  // row shorter than counted: inconsistent input
+      set_err(w.hdr, NM_E_INVAL);
+      return;
+    }
+    int32_t* out = idx + base + written;
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t)
+      if (t >= kChunk - need) out[t - (kChunk - need)] = key_index(top.key[t]);
+    written += need;
+    last = top.worst();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_metric_count(const DevWs& w, long long rc2, int32_t* offsets, hipStream_t s) {
+  const int nb = (w.n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_metric_count, dim3(nb), dim3(kBlock), 0, s, w, rc2, offsets);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_scan_rows(offsets, w.n, w.scan_m, w.nb_scan_m, w.hdr, s);
+}
+
+hipError_t launch_metric_fill(const DevWs& w, long long rc2, const int32_t* offsets, int32_t* idx,
+                              long long cap, hipStream_t s) {
+  const int nb = (w.n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_metric_fill, dim3(nb), dim3(kBlock), 0, s, w, rc2, offsets, idx, cap);
+  return hipGetLastError();
+}
+
+}  // namespace nm

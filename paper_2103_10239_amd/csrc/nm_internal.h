@@ -1,0 +1,265 @@
+// nm_internal.h -- device-side building blocks shared by the HIP kernels.
+//
+// Layout of the caller-owned workspace (all offsets 256-byte aligned):
+//   header      WsHeader: magic, error word, grid echo, build stamp
+//   scan_cells  ScanState for the cell-histogram prefix sum
+//   scan_metric ScanState for the metric-list row-length prefix sum
+//   count       int32[C]     per-cell histogram (kept zero between builds)
+//   start       int32[C + 1] first cell-ordered slot of each cell
+//   rank        int32[n]     slot of each particle inside its cell
+//   sorted      int4[n]      cell-ordered (x, y, particle index, noise word)
+//   cs          double2[n]   cell-ordered (cos theta, sin theta), fused step only
+// C = G^2 cells, G = L / w.  Cells are numbered row-major: c = cy * G + cx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "../../include/nm.h"
+
+namespace nm {
+
+constexpr int kBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+constexpr uint32_t kMagic = 0x4E4D5753u;  // "NMWS"
+constexpr uint32_t kBuilt = 0x42554C54u;  // "BULT"
+constexpr int kKeyIndexBits = 24;         // particle index field of a search key
+constexpr int kMaxParticles = 1 << kKeyIndexBits;
+
+struct WsHeader {
+  uint32_t magic;
+  int32_t err;
+  int32_t n, box, cell_w;
+  uint32_t built;
+  int32_t pad[58];
+};
+static_assert(sizeof(WsHeader) == 256, "header is one 256-byte block");
+
+struct ScanState {
+  uint32_t ticket;
+  uint32_t pad[63];
+  unsigned long long flags[1];  // one word per tile (flexible)
+};
+
+// Host-computed view of a workspace, passed to kernels by value.
+struct DevWs {
+  WsHeader* hdr;
+  ScanState* scan_c;
+  ScanState* scan_m;
+  int32_t* count;
+  int32_t* start;
+  int32_t* rank;
+  int4* sorted;
+  double2* cs;
+  int32_t n;
+  int32_t box;
+  int32_t cell_w;
+  int32_t log2_box;
+  int32_t log2_w;
+  int32_t G;
+  int32_t nb_scan_c;
+  int32_t nb_scan_m;
+  int64_t C;
+};
+
+struct Layout {
+  int64_t off_scan_c, off_scan_m, off_count, off_start, off_rank, off_sorted, off_cs, total;
+  int32_t log2_box, log2_w, G, nb_scan_c, nb_scan_m;
+  int64_t C;
+};
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void set_err(WsHeader* h, int code) {
+  if (h) atomicCAS(&h->err, 0, code);
+}
+
+// Signed offset congruent to d modulo L = 2^(32 - sh), in [-L/2, L/2).
+__device__ __forceinline__ int wrap_axis(int d, int sh) {
+  return static_cast<int>(static_cast<uint32_t>(d) << sh) >> sh;
+}
+
+// Smallest |offset| (minimum image) from a query at offset o inside its own
+// cell to any point of the cell `dc` columns away (cells of width w).
+__device__ __forceinline__ int axis_gap(int dc, int o, int w, int sh) {
+  if (dc == 0) return 0;
+  const int a = dc * w - o;
+  const int b = a + w - 1;
+  return min(abs(wrap_axis(a, sh)), abs(wrap_axis(b, sh)));
+}
+
+// Map a hardware block id to a logical tile so that each of the 8 XCDs (which
+// receive blocks round-robin) walks one contiguous stretch of the cell-ordered
+// particles: neighbouring queries then share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = b & 7, t = b >> 3;
+  return x * q + min(x, r) + t;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11).
+// Ten rounds; each round multiplies words 0 and 2 by fixed odd constants,
+// swaps the halves and folds in the round key; the key advances by a Weyl
+// sequence between rounds.
+// ---------------------------------------------------------------------------
+struct Philox {
+  static constexpr uint32_t kMulA = 0xD2511F53u;
+  static constexpr uint32_t kMulB = 0xCD9E8D57u;
+  static constexpr uint32_t kWeylA = 0x9E3779B9u;
+  static constexpr uint32_t kWeylB = 0xBB67AE85u;
+
+  __device__ static uint4 block(uint4 c, uint32_t ka, uint32_t kb) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+      const uint32_t hA = __umulhi(kMulA, c.x), lA = kMulA * c.x;
+      const uint32_t hB = __umulhi(kMulB, c.z), lB = kMulB * c.z;
+      c = make_uint4(hB ^ c.y ^ ka, lB, hA ^ c.w ^ kb, lA);
+      ka += kWeylA;
+      kb += kWeylB;
+    }
+    return c;
+  }
+};
+
+__device__ __forceinline__ uint32_t uint4_word(uint4 v, int q) {
+  return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+}
+
+// Noise angle phi = (u 2^-32) 2pi - pi, each fp64 operation rounded separately
+// (the library is compiled with -ffp-contract=off, so no fused multiply-add).
+__device__ __forceinline__ double noise_angle(uint32_t u) {
+  const double unit = static_cast<double>(u) * 0x1p-32;  // exact
+  const double turn = unit * 6.283185307179586;           // fp64(2 pi)
+  return turn - 3.141592653589793;                        // fp64(pi)
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident sorted list of the KMAX smallest 64-bit keys.  The first
+// KMAX - k entries hold the sentinel 0 (below every real key, which is >= 1),
+// so the last k entries act as a sorted list of length k with its largest
+// element at a fixed register, keys[KMAX - 1].
+// ---------------------------------------------------------------------------
+// With kSlots, each key carries the cell-ordered slot of its particle along.
+template <int KMAX, bool kSlots = false>
+struct TopK {
+  unsigned long long key[KMAX];
+  int32_t slot[kSlots ? KMAX : 1];
+
+  __device__ void init(int k) {
+#pragma unroll
+    for (int t = 0; t < KMAX; ++t) key[t] = (t < KMAX - k) ? 0ull : ~0ull;
+#pragma unroll
+    for (int t = 0; t < (kSlots ? KMAX : 1); ++t) slot[t] = -1;
+  }
+  __device__ unsigned long long worst() const { return key[KMAX - 1]; }
+
+  // Insert (kk, s) and drop the largest entry.  Caller ensures kk < worst().
+  __device__ void push(unsigned long long kk, int32_t s) {
+#pragma unroll
+    for (int t = KMAX - 1; t > 0; --t) {
+      const bool shift = kk < key[t - 1];
+      const bool here = kk < key[t];
+      const unsigned long long nk = shift ? key[t - 1] : (here ? kk : key[t]);
+      if constexpr (kSlots) slot[t] = shift ? slot[t - 1] : (here ? s : slot[t]);
+      key[t] = nk;
+    }
+    if (kk < key[0]) {
+      key[0] = kk;
+      if constexpr (kSlots) slot[0] = s;
+    }
+  }
+};
+
+// Search key of a candidate: (d^2, index) packed so that integer order is the
+// lexicographic order; +1 keeps 0 free for the sentinel.  d^2 <= 2^39 for
+// L <= 2^20, so the packed value stays below 2^64.
+__device__ __forceinline__ unsigned long long pack_key(long long d2, int32_t j) {
+  return ((static_cast<unsigned long long>(d2) << kKeyIndexBits) |
+          static_cast<unsigned long long>(j)) + 1ull;
+}
+__device__ __forceinline__ int32_t key_index(unsigned long long kk) {
+  return static_cast<int32_t>((kk - 1ull) & ((1ull << kKeyIndexBits) - 1ull));
+}
+__device__ __forceinline__ long long key_d2(unsigned long long kk) {
+  return static_cast<long long>((kk - 1ull) >> kKeyIndexBits);
+}
+__device__ __forceinline__ long long key_bound_d2(unsigned long long kk) {
+  // d^2 of the current worst key, or "infinite" while the list is not full.
+  return kk == ~0ull ? (1ll << 62) : key_d2(kk);
+}
+
+// ---------------------------------------------------------------------------
+// Ring walk over the cell grid.  Ring r holds the 8r cells at Chebyshev
+// distance r from the home cell (one cell for r = 0), walked once around the
+// perimeter from (-r, -r).  Offsets outside one window [lo, hi] of G
+// consecutive values per axis are skipped, so that no cell is visited twice
+// when rings wrap around the periodic box.  `visit(dx, dy)` has a single call
+// site, which keeps one inlined copy of the candidate loop.
+// ---------------------------------------------------------------------------
+template <class Visit>
+__device__ __forceinline__ void for_ring(int r, int lo, int hi, Visit&& visit) {
+  const int ncell = r == 0 ? 1 : 8 * r;
+  int dx = -r, dy = -r, sx = 1, sy = 0, left = 2 * r;
+#pragma unroll 1
+  for (int q = 0; q < ncell; ++q) {
+    if (dx >= lo && dx <= hi && dy >= lo && dy <= hi) visit(dx, dy);
+    dx += sx;
+    dy += sy;
+    if (--left == 0) {
+      left = 2 * r;
+      const int t = sx;
+      sx = -sy;
+      sy = t;
+    }
+  }
+}
+
+// Query geometry derived from its position.
+struct QueryGeom {
+  int hx, hy, ox, oy, edge, lo, hi, rmax;
+  __device__ QueryGeom(int qx, int qy, const DevWs& w) {
+    const int cw = 1 << w.log2_w;
+    hx = qx >> w.log2_w;
+    hy = qy >> w.log2_w;
+    ox = qx & (cw - 1);
+    oy = qy & (cw - 1);
+    edge = min(min(ox, cw - 1 - ox), min(oy, cw - 1 - oy));
+    lo = -(w.G >> 1);
+    hi = w.G - 1 - (w.G >> 1);
+    rmax = max(-lo, hi);
+  }
+  // Lower bound on d^2 of any particle outside rings 0..r.
+  __device__ long long ring_bound(int r, int cw) const {
+    const long long b = static_cast<long long>(r) * cw + edge + 1;
+    return b * b;
+  }
+};
+
+// Host-side helpers (abi.hip).
+bool make_layout(const nm_grid* g, Layout* out);
+DevWs dev_ws(const nm_grid* g, const Layout& lay, void* ws);
+
+// Launchers implemented in the kernel files.
+hipError_t launch_ws_init(const DevWs& w, hipStream_t s);
+hipError_t launch_build(const DevWs& w, const int32_t* x, const int32_t* y, const float* theta,
+                        const nm_params* p, uint64_t step, hipStream_t s);
+hipError_t launch_knn(const DevWs& w, int k, int32_t* nbr, long long* d2, hipStream_t s);
+hipError_t launch_knn_align(const DevWs& w, int k, const nm_params* p, const float* theta,
+                            int32_t* nbr, int32_t* x_out, int32_t* y_out, float* theta_out,
+                            hipStream_t s);
+hipError_t launch_metric_count(const DevWs& w, long long rc2, int32_t* offsets, hipStream_t s);
+hipError_t launch_metric_fill(const DevWs& w, long long rc2, const int32_t* offsets, int32_t* idx,
+                              long long cap, hipStream_t s);
+hipError_t launch_scan_rows(int32_t* data, int64_t m, ScanState* st, int nb, WsHeader* hdr,
+                            hipStream_t s);
+hipError_t launch_align(const int32_t* x, const int32_t* y, const float* theta, int32_t n,
+                        const int32_t* nbr, const int32_t* offsets, int32_t k, long long nnz_cap,
+                        const nm_params* p, uint64_t step, int32_t* x_out, int32_t* y_out,
+                        float* theta_out, WsHeader* err_hdr, hipStream_t s);
+
+}  // namespace nm

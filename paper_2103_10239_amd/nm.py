@@ -1,0 +1,254 @@
+"""ctypes binding of libnm.so (include/nm.h): argument marshalling only.
+
+Every step of the neighbour-list / Vicsek path runs in the HIP kernels of
+libnm.so; this module checks tensor shapes and dtypes, passes raw device
+pointers and torch's current HIP stream, and turns status codes into
+exceptions.  PyTorch supplies device memory and streams, nothing else.  There
+is no fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnm.so")
+
+NM_OK, NM_E_INVAL, NM_E_RANGE, NM_E_CAPACITY, NM_E_NOMEM, NM_E_DEVICE = 0, -1, -2, -3, -4, -5
+NM_MAX_K = 32
+
+_c_i32, _c_i64, _c_u32, _c_u64, _vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                       ctypes.c_uint64, ctypes.c_void_p)
+
+
+class NMError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+
+
+class Grid(ctypes.Structure):
+    """nm_grid: n particles, box side L, cell width w (powers of two)."""
+    _fields_ = [("n", _c_i32), ("box", _c_i32), ("cell_w", _c_i32), ("flags", _c_i32)]
+
+
+class Params(ctypes.Structure):
+    """nm_params: Eq. (1) and Eq. (2) parameters and the Philox identity."""
+    _fields_ = [("box", _c_i32), ("v0", _c_i32), ("eta", ctypes.c_float), ("include_self", _c_i32),
+                ("seed", _c_u64), ("sys_id", _c_u32), ("reserved", _c_u32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libnm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; "
+                          "g.build()'` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    gp, pp = ctypes.POINTER(Grid), ctypes.POINTER(Params)
+    L.nm_status_str.argtypes, L.nm_status_str.restype = [ctypes.c_int], ctypes.c_char_p
+    L.nm_workspace_bytes.argtypes, L.nm_workspace_bytes.restype = [gp], _c_i64
+    L.nm_suggest_cell_w.argtypes = [_c_i32, _c_i32, ctypes.c_double]
+    L.nm_suggest_cell_w.restype = _c_i32
+    L.nm_workspace_init.argtypes = [gp, _vp, ctypes.c_size_t, _vp]
+    L.nm_build_cells.argtypes = [gp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.nm_knn.argtypes = [gp, _vp, _c_i32, _vp, _vp, _vp]
+    L.nm_metric_list.argtypes = [gp, _vp, _c_i64, _vp, _vp, _c_i64, ctypes.POINTER(_c_i64), _vp]
+    L.nm_align_step.argtypes = [_vp, _vp, _vp, _c_i32, _vp, _vp, _c_i32, _c_i64, pp, _c_u64,
+                                _vp, _vp, _vp, _vp, _vp]
+    L.nm_step.argtypes = [gp, _vp, _vp, _vp, _c_i32, pp, _c_u64, _vp, ctypes.c_size_t, _vp, _vp,
+                          _vp, _vp, _vp]
+    L.nm_check.argtypes = [_vp, _vp]
+    for f in ("nm_workspace_init", "nm_build_cells", "nm_knn", "nm_metric_list", "nm_align_step",
+              "nm_step", "nm_check"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def status_str(status: int) -> str:
+    try:
+        return lib().nm_status_str(status).decode()
+    except ImportError:
+        return str(status)
+
+
+def _ok(rc: int, what: str) -> None:
+    if rc != NM_OK:
+        raise NMError(rc, what)
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, numel: int | None, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} needs {numel} elements, has {t.numel()}")
+    return t.data_ptr()
+
+
+def suggest_cell_w(n: int, box: int, per_cell: float = 2.0) -> int:
+    return int(lib().nm_suggest_cell_w(n, box, per_cell))
+
+
+def make_params(box: int, v0: int = 64, eta: float = 0.2, include_self: int = 1, seed: int = 0,
+                sys_id: int = 0) -> Params:
+    return Params(box, v0, eta, include_self, seed, sys_id, 0)
+
+
+class Workspace:
+    """Device workspace of one system's cell grid (owned by torch)."""
+
+    def __init__(self, n: int, box: int, cell_w: int | None = None, device="cuda"):
+        if cell_w is None:
+            cell_w = suggest_cell_w(n, box)
+        self.grid = Grid(n, box, cell_w, 0)
+        nbytes = int(lib().nm_workspace_bytes(ctypes.byref(self.grid)))
+        if nbytes < 0:
+            raise NMError(nbytes, f"workspace_bytes(n={n}, box={box}, cell_w={cell_w})")
+        self.device = torch.device(device)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.nbytes = nbytes
+        _ok(lib().nm_workspace_init(ctypes.byref(self.grid), self.ptr, nbytes, _stream(self.device)),
+            "workspace_init")
+
+    @property
+    def ptr(self) -> int:
+        return self.buf.data_ptr()
+
+    @property
+    def n(self) -> int:
+        return self.grid.n
+
+
+def build_cells(ws: Workspace, x: torch.Tensor, y: torch.Tensor) -> None:
+    n = ws.n
+    _ok(lib().nm_build_cells(ctypes.byref(ws.grid), _dev(x, torch.int32, n, "x"),
+                             _dev(y, torch.int32, n, "y"), ws.ptr, ws.nbytes, _stream(ws.device)),
+        "build_cells")
+
+
+def knn(ws: Workspace, k: int, nbr: torch.Tensor | None = None, d2: torch.Tensor | None = None,
+        with_d2: bool = False):
+    n = ws.n
+    if nbr is None:
+        nbr = torch.empty((n, k), dtype=torch.int32, device=ws.device)
+    if with_d2 and d2 is None:
+        d2 = torch.empty((n, k), dtype=torch.int64, device=ws.device)
+    _ok(lib().nm_knn(ctypes.byref(ws.grid), ws.ptr, k, _dev(nbr, torch.int32, n * k, "nbr"),
+                     _dev(d2, torch.int64, n * k, "d2") if d2 is not None else None,
+                     _stream(ws.device)), "knn")
+    return nbr, d2
+
+
+def metric_list(ws: Workspace, rc2: int, offsets: torch.Tensor | None = None,
+                idx: torch.Tensor | None = None, cap: int | None = None):
+    """CSR metric lists.  Without idx: two-call protocol (count, allocate, fill),
+    synchronising once.  With idx (capacity `cap`): one call, no synchronisation;
+    an overflow is reported by check()."""
+    n = ws.n
+    if offsets is None:
+        offsets = torch.empty(n + 1, dtype=torch.int32, device=ws.device)
+    op = _dev(offsets, torch.int32, n + 1, "offsets")
+    s = _stream(ws.device)
+    if idx is None:
+        nnz = _c_i64(0)
+        _ok(lib().nm_metric_list(ctypes.byref(ws.grid), ws.ptr, rc2, op, None, 0, ctypes.byref(nnz), s),
+            "metric_list(count)")
+        idx = torch.empty(max(int(nnz.value), 1), dtype=torch.int32, device=ws.device)
+        _ok(lib().nm_metric_list(ctypes.byref(ws.grid), ws.ptr, rc2, op, idx.data_ptr(), idx.numel(),
+                                 ctypes.byref(nnz), s), "metric_list(fill)")
+        return offsets, idx[:int(nnz.value)]
+    cap = idx.numel() if cap is None else cap
+    _ok(lib().nm_metric_list(ctypes.byref(ws.grid), ws.ptr, rc2, op, _dev(idx, torch.int32, cap, "idx"),
+                             cap, None, s), "metric_list")
+    return offsets, idx
+
+
+def align_step(x, y, theta, params: Params, step: int, nbr=None, offsets=None, idx=None,
+               out=None, ws: Workspace | None = None):
+    """Eq. (2) + Eq. (1) for every particle from a fixed-k list (nbr [n, k]) or CSR
+    (offsets [n+1], idx).  Returns (x', y', theta')."""
+    n = int(x.numel())
+    dev = x.device
+    if out is None:
+        out = (torch.empty_like(x), torch.empty_like(y), torch.empty_like(theta))
+    xo, yo, to = out
+    if offsets is not None:
+        k, cap = 0, int(idx.numel())
+        lst = _dev(idx, torch.int32, None, "idx") if cap else None
+        offp = _dev(offsets, torch.int32, n + 1, "offsets")
+    else:
+        k = int(nbr.shape[1]) if nbr.dim() == 2 else int(nbr.numel() // max(n, 1))
+        lst = _dev(nbr, torch.int32, n * k, "nbr") if k else None
+        offp, cap = None, 0
+    _ok(lib().nm_align_step(_dev(x, torch.int32, n, "x"), _dev(y, torch.int32, n, "y"),
+                            _dev(theta, torch.float32, n, "theta"), n, lst, offp, k, cap,
+                            ctypes.byref(params), step, _dev(xo, torch.int32, n, "x_out"),
+                            _dev(yo, torch.int32, n, "y_out"), _dev(to, torch.float32, n, "theta_out"),
+                            ws.ptr if ws is not None else None, _stream(dev)), "align_step")
+    return xo, yo, to
+
+
+def step(ws: Workspace, x, y, theta, k: int, params: Params, step_index: int, nbr, x_out, y_out,
+         theta_out) -> None:
+    """One fused step (Alg. 1): cells, k-NN lists, Eq. (2) and Eq. (1)."""
+    n = ws.n
+    _ok(lib().nm_step(ctypes.byref(ws.grid), _dev(x, torch.int32, n, "x"), _dev(y, torch.int32, n, "y"),
+                      _dev(theta, torch.float32, n, "theta"), k, ctypes.byref(params), step_index,
+                      ws.ptr, ws.nbytes, _dev(nbr, torch.int32, n * k, "nbr"),
+                      _dev(x_out, torch.int32, n, "x_out"), _dev(y_out, torch.int32, n, "y_out"),
+                      _dev(theta_out, torch.float32, n, "theta_out"), _stream(ws.device)), "step")
+
+
+def check(ws: Workspace) -> int:
+    """Synchronise and return (and clear) the first device-side error, NM_OK if none."""
+    return int(lib().nm_check(ws.ptr, _stream(ws.device)))
+
+
+@dataclass
+class System:
+    """One simulated system resident on the device: double-buffered state,
+    its workspace and its k-NN list."""
+    ws: Workspace
+    k: int
+    params: Params
+    x: torch.Tensor
+    y: torch.Tensor
+    theta: torch.Tensor
+    nbr: torch.Tensor
+    step_index: int = 0
+
+    @classmethod
+    def create(cls, x, y, theta, k: int, params: Params, cell_w: int | None = None, device="cuda"):
+        n = int(len(x))
+        dev = torch.device(device)
+        ws = Workspace(n, params.box, cell_w, dev)
+        t = lambda a, dt: torch.as_tensor(a, dtype=dt).to(dev).contiguous()
+        sysm = cls(ws, k, params, t(x, torch.int32), t(y, torch.int32), t(theta, torch.float32),
+                   torch.empty((n, k), dtype=torch.int32, device=dev))
+        sysm._back = (torch.empty_like(sysm.x), torch.empty_like(sysm.y), torch.empty_like(sysm.theta))
+        return sysm
+
+    def step(self) -> None:
+        xo, yo, to = self._back
+        step(self.ws, self.x, self.y, self.theta, self.k, self.params, self.step_index, self.nbr,
+             xo, yo, to)
+        self._back = (self.x, self.y, self.theta)
+        self.x, self.y, self.theta = xo, yo, to
+        self.step_index += 1

@@ -1,0 +1,94 @@
+"""The C ABI library loads on the host and exports what include/nm.h declares;
+host-side argument checks reject bad input before anything reaches a device.
+(No compute calls here: these tests run without a GPU.)"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2103_10239_amd import nm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(nm_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = nm.lib()
+    declared = _declared()
+    assert {"nm_build_cells", "nm_knn", "nm_metric_list", "nm_align_step", "nm_step"} <= declared
+    for name in sorted(declared):
+        assert hasattr(lib, name), f"{name} declared but not exported"
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert nm.status_str(code) not in ("", "unknown status")
+    assert nm.status_str(7) == "unknown status"
+
+
+@pytest.mark.parametrize("n,box,w", [(1, 1 << 20, 1024), (1 << 20, 1000, 8), (1 << 20, 1 << 21, 1024),
+                                     (1 << 20, 1 << 20, 3), (1 << 20, 1 << 20, 1 << 21),
+                                     (1 << 25, 1 << 20, 1024), (1 << 20, 1 << 20, 1)])
+def test_invalid_grids_rejected(n, box, w):
+    g = nm.Grid(n, box, w, 0)
+    assert nm.lib().nm_workspace_bytes(ctypes.byref(g)) == nm.NM_E_INVAL
+
+
+def test_workspace_size_grows_with_cells_and_particles():
+    b = lambda n, w: nm.lib().nm_workspace_bytes(ctypes.byref(nm.Grid(n, 1 << 20, w, 0)))
+    assert b(1 << 20, 1024) > b(1 << 20, 2048) > 0
+    assert b(1 << 21, 2048) > b(1 << 20, 2048)
+
+
+def test_suggest_cell_w():
+    assert nm.suggest_cell_w(1 << 20, 1 << 20, 1.0) == 1024
+    assert nm.suggest_cell_w(1 << 20, 1 << 20, 4.0) == 2048
+    assert nm.suggest_cell_w(2, 1 << 20, 2.0) == 1 << 20
+    w = nm.suggest_cell_w(1 << 24, 1 << 20, 0.01)
+    assert ((1 << 20) // w) ** 2 <= 1 << 28
+
+
+def test_host_checks_return_before_any_launch():
+    lib = nm.lib()
+    g = nm.Grid(1024, 1 << 20, 1 << 15, 0)
+    fake = ctypes.c_void_p(256)  # never dereferenced: every call below fails validation first
+    # k out of range
+    assert lib.nm_knn(ctypes.byref(g), fake, 0, fake, None, None) == nm.NM_E_INVAL
+    assert lib.nm_knn(ctypes.byref(g), fake, 33, fake, None, None) == nm.NM_E_INVAL
+    # workspace too small / misaligned
+    assert lib.nm_build_cells(ctypes.byref(g), fake, fake, fake, 16, None) == nm.NM_E_INVAL
+    assert lib.nm_build_cells(ctypes.byref(g), fake, fake, ctypes.c_void_p(300), 1 << 30, None) == nm.NM_E_INVAL
+    # metric radius out of range
+    assert lib.nm_metric_list(ctypes.byref(g), fake, -1, fake, None, 0, None, None) == nm.NM_E_INVAL
+    # bad parameters: box not a power of two, |v0| >= L/2, negative eta, reserved != 0
+    for p in (nm.Params(1000, 64, 0.2, 1, 0, 0, 0), nm.Params(1 << 20, 1 << 19, 0.2, 1, 0, 0, 0),
+              nm.Params(1 << 20, 64, -0.1, 1, 0, 0, 0), nm.Params(1 << 20, 64, 0.2, 1, 0, 0, 1),
+              nm.Params(1 << 20, 64, float("nan"), 1, 0, 0, 0), nm.Params(1 << 20, 64, 0.2, 2, 0, 0, 0)):
+        assert lib.nm_align_step(fake, fake, fake, 16, fake, None, 7, 0, ctypes.byref(p), 0,
+                                 ctypes.c_void_p(512), ctypes.c_void_p(768), ctypes.c_void_p(1024),
+                                 None, None) == nm.NM_E_INVAL
+    p = nm.Params(1 << 20, 64, 0.2, 1, 0, 0, 0)
+    # outputs aliasing inputs
+    assert lib.nm_align_step(fake, ctypes.c_void_p(512), ctypes.c_void_p(768), 16, fake, None, 7, 0,
+                             ctypes.byref(p), 0, fake, ctypes.c_void_p(900), ctypes.c_void_p(1000),
+                             None, None) == nm.NM_E_INVAL
+    # fused step: p.box must equal grid box
+    p2 = nm.Params(1 << 19, 64, 0.2, 1, 0, 0, 0)
+    assert lib.nm_step(ctypes.byref(g), fake, fake, fake, 7, ctypes.byref(p2), 0, fake, 1 << 30, fake,
+                       fake, fake, fake, None) == nm.NM_E_INVAL
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+    with pytest.raises((TypeError, ImportError)):
+        nm._dev(torch.zeros(4, dtype=torch.int32), torch.int32, 4, "x")

@@ -1,0 +1,323 @@
+"""Parity of the HIP path (through the C ABI) with the brute-force oracle.
+
+Bar: neighbour lists, squared distances, CSR metric lists and positions
+bit-exact; headings within 1e-5 rad (one step from the same state).  Small
+and mid sizes are compared element by element over every particle (spanning
+many 256-lane tiles, with ragged tails); the full benchmark sizes are
+compared on sampled rows that the oracle brute-forces one by one, plus
+invariants checked over every row on the device.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2103_10239_amd as nm
+from paper_2103_10239_amd import workloads
+
+pytestmark = pytest.mark.gpu
+L = workloads.BOX
+TOL = 1e-5
+
+
+def _dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).to("cuda")
+
+
+def _angle_err(a, b):
+    d = np.asarray(a, np.float64) - np.asarray(b, np.float64)
+    return np.abs(np.remainder(d + np.pi, 2 * np.pi) - np.pi)
+
+
+def _gen(kind, n):
+    if kind == "uniform":
+        return workloads.uniform(n)
+    if kind == "clustered":
+        return workloads.clustered(n)
+    if kind == "squeezed":  # many exact duplicates and distance ties
+        x, y, th = workloads.uniform(n)
+        return (x % 7) * 1000, (y % 5) * 1000, th
+    raise ValueError(kind)
+
+
+def _gpu_knn(x, y, k, w):
+    ws = nm.Workspace(len(x), L, w)
+    nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+    nbr, d2 = nm.knn(ws, k, with_d2=True)
+    assert nm.check(ws) == 0
+    return nbr.cpu().numpy(), d2.cpu().numpy(), ws
+
+
+KNN_CASES = [
+    ("uniform", 1024, 7, 2048), ("uniform", 1024, 7, 1024), ("uniform", 1024, 7, L),
+    ("uniform", 1024, 7, L // 2), ("uniform", 1024, 7, 256), ("uniform", 2, 1, L // 4),
+    ("uniform", 3, 2, 1024), ("uniform", 33, 32, 4096), ("uniform", 257, 1, 8192),
+    ("uniform", 4097, 12, 2048), ("uniform", 20013, 20, 2048), ("uniform", 20013, 32, 4096),
+    ("clustered", 8191, 6, 2048), ("clustered", 8191, 12, 1024), ("clustered", 20013, 20, 4096),
+    ("squeezed", 3000, 7, 1024), ("squeezed", 3000, 16, 4096),
+]
+
+
+@pytest.mark.parametrize("kind,n,k,w", KNN_CASES)
+def test_knn_matches_oracle(kind, n, k, w):
+    x, y, _ = _gen(kind, n)
+    nbr, d2, _ = _gpu_knn(x, y, k, w)
+    rn, rd = oracle.knn(x, y, L, k)
+    assert np.array_equal(nbr, rn)
+    assert np.array_equal(d2, rd)
+
+
+@pytest.mark.parametrize("k", [1, 4, 7, 8])
+@pytest.mark.parametrize("wdiv", [1, 2, 4])
+def test_knn_lattice_ties(k, wdiv):
+    x, y, a = workloads.lattice(32)
+    nbr, d2, _ = _gpu_knn(x, y, k, a // wdiv if wdiv > 1 else a)
+    rn, rd = oracle.knn(x, y, L, k)
+    assert np.array_equal(nbr, rn) and np.array_equal(d2, rd)
+
+
+def test_knn_all_coincident():
+    n = 33
+    nbr, d2, _ = _gpu_knn([777] * n, [4242] * n, 32, 1024)
+    assert not d2.any()
+    for i in range(n):
+        assert nbr[i].tolist() == [j for j in range(n) if j != i]
+
+
+def test_knn_wrap_pair():
+    nbr, d2, _ = _gpu_knn([0, L - 1], [5, 5], 1, 1024)
+    assert nbr.tolist() == [[1], [0]] and d2.tolist() == [[1], [1]]
+
+
+def _gpu_metric(x, y, rc2, w):
+    ws = nm.Workspace(len(x), L, w)
+    nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+    offs, idx = nm.metric_list(ws, rc2)
+    assert nm.check(ws) == 0
+    return offs.cpu().numpy().astype(np.int64), idx.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind,n,mean,w", [("uniform", 4097, 7.0, 1024), ("uniform", 4097, 7.0, 4096),
+                                           ("clustered", 8191, 3.0, 2048), ("squeezed", 3000, 1.0, 1024),
+                                           ("uniform", 2, 1.0, L // 4)])
+def test_metric_matches_oracle(kind, n, mean, w):
+    x, y, _ = _gen(kind, n)
+    rc2 = workloads.rc2_for_mean(n, mean)
+    offs, idx = _gpu_metric(x, y, rc2, w)
+    ro, ri, _ = oracle.metric_list(x, y, L, rc2)
+    assert np.array_equal(offs, ro)
+    assert np.array_equal(idx, ri)
+
+
+@pytest.mark.parametrize("shell", [(1, 0), (1, -1), (2, 0), (0, 0)])
+def test_metric_lattice_shells(shell):
+    x, y, a = workloads.lattice(32)
+    rc2 = shell[0] * a * a + shell[1]
+    offs, idx = _gpu_metric(x, y, rc2, a)
+    ro, ri, _ = oracle.metric_list(x, y, L, rc2)
+    assert np.array_equal(offs, ro) and np.array_equal(idx, ri)
+
+
+def test_metric_long_rows_use_several_chunks():
+    # 60 coincident points plus a far group: rows of 59 entries need four selection passes.
+    x = np.array([1000] * 60 + list(range(500000, 500040)), np.int32)
+    y = np.array([2000] * 60 + [7] * 40, np.int32)
+    offs, idx = _gpu_metric(x, y, 50 ** 2, 1024)
+    ro, ri, _ = oracle.metric_list(x, y, L, 50 ** 2)
+    assert np.array_equal(offs, ro) and np.array_equal(idx, ri)
+
+
+@pytest.mark.parametrize("include_self", [0, 1])
+@pytest.mark.parametrize("eta,seed,step,sys_id", [(0.2, 0, 0, 0), (0.7, (1 << 40) + 5, (1 << 33) + 9, 3),
+                                                  (0.0, 1, 2, 0)])
+def test_align_step_matches_oracle(include_self, eta, seed, step, sys_id):
+    n, k = 4097, 7
+    x, y, th = workloads.uniform(n)
+    rn, _ = oracle.knn(x, y, L, k)
+    p = nm.make_params(L, v0=64, eta=eta, include_self=include_self, seed=seed, sys_id=sys_id)
+    xo, yo, to = nm.align_step(_dev(x, torch.int32), _dev(y, torch.int32), _dev(th, torch.float32), p,
+                               step, nbr=_dev(rn, torch.int32))
+    torch.cuda.synchronize()
+    rx, ry, rt = oracle.align_step(x, y, th, L, nbr=rn, v0=64, eta=eta, seed=seed, sys_id=sys_id,
+                                   include_self=include_self, step=step)
+    assert np.array_equal(xo.cpu().numpy(), rx) and np.array_equal(yo.cpu().numpy(), ry)
+    assert _angle_err(to.cpu().numpy(), rt).max() <= TOL
+
+
+@pytest.mark.parametrize("include_self", [0, 1])
+def test_align_step_metric_mode(include_self):
+    n = 4097
+    x, y, th = workloads.clustered(n)
+    rc2 = workloads.rc2_for_mean(n, 2.0)
+    ro, ri, _ = oracle.metric_list(x, y, L, rc2)
+    assert (np.diff(ro) == 0).any()  # some isolated particles
+    p = nm.make_params(L, v0=-37, eta=0.3, include_self=include_self, seed=12)
+    ws = nm.Workspace(n, L, 2048)
+    xo, yo, to = nm.align_step(_dev(x, torch.int32), _dev(y, torch.int32), _dev(th, torch.float32), p, 5,
+                               offsets=_dev(ro, torch.int32), idx=_dev(ri, torch.int32), ws=ws)
+    assert nm.check(ws) == 0
+    rx, ry, rt = oracle.align_step(x, y, th, L, offsets=ro, idx=ri, v0=-37, eta=0.3, seed=12,
+                                   include_self=include_self, step=5)
+    assert np.array_equal(xo.cpu().numpy(), rx) and np.array_equal(yo.cpu().numpy(), ry)
+    assert _angle_err(to.cpu().numpy(), rt).max() <= TOL
+
+
+@pytest.mark.parametrize("kind,n,k,w", [("uniform", 1024, 7, 2048), ("clustered", 8191, 12, 2048),
+                                        ("uniform", 20013, 20, 1024), ("uniform", 2, 1, L // 2),
+                                        ("squeezed", 3000, 7, 2048)])
+def test_fused_step_matches_oracle(kind, n, k, w):
+    x, y, th = _gen(kind, n)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    sysm = nm.System.create(x, y, th, k, p, cell_w=w)
+    sysm.step()
+    assert nm.check(sysm.ws) == 0
+    rn, rx, ry, rt = oracle.step(x, y, th, L, k, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    assert np.array_equal(sysm.nbr.cpu().numpy(), rn)
+    assert np.array_equal(sysm.x.cpu().numpy(), rx) and np.array_equal(sysm.y.cpu().numpy(), ry)
+    assert _angle_err(sysm.theta.cpu().numpy(), rt).max() <= TOL
+
+
+def test_fused_step_equals_separate_calls():
+    n, k = 20013, 7
+    x, y, th = workloads.clustered(n)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=3, sys_id=1)
+    X, Y, T = _dev(x, torch.int32), _dev(y, torch.int32), _dev(th, torch.float32)
+    ws = nm.Workspace(n, L, 2048)
+    nbr = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    out = (torch.empty_like(X), torch.empty_like(Y), torch.empty_like(T))
+    nm.step(ws, X, Y, T, k, p, 11, nbr, *out)
+    ws2 = nm.Workspace(n, L, 1024)
+    nm.build_cells(ws2, X, Y)
+    nbr2, _ = nm.knn(ws2, k)
+    xo, yo, to = nm.align_step(X, Y, T, p, 11, nbr=nbr2)
+    assert nm.check(ws) == 0 and nm.check(ws2) == 0
+    assert torch.equal(nbr, nbr2) and torch.equal(out[0], xo) and torch.equal(out[1], yo)
+    assert torch.equal(out[2], to)
+
+
+def test_trajectory_each_step_matches_oracle_from_gpu_state():
+    n, k = 4096, 7
+    x, y, th = workloads.uniform(n)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    sysm = nm.System.create(x, y, th, k, p, cell_w=2048)
+    for _ in range(6):
+        sx, sy, st = sysm.x.cpu().numpy(), sysm.y.cpu().numpy(), sysm.theta.cpu().numpy()
+        t = sysm.step_index
+        sysm.step()
+        rn, rx, ry, rt = oracle.step(sx, sy, st, L, k, v0=64, eta=0.2, seed=workloads.NOISE_SEED,
+                                     step_index=t)
+        assert np.array_equal(sysm.nbr.cpu().numpy(), rn)
+        assert np.array_equal(sysm.x.cpu().numpy(), rx) and np.array_equal(sysm.y.cpu().numpy(), ry)
+        assert _angle_err(sysm.theta.cpu().numpy(), rt).max() <= TOL
+    assert nm.check(sysm.ws) == 0
+
+
+def test_steps_are_deterministic():
+    n, k = 65536, 7
+    x, y, th = workloads.clustered(n)
+    p = nm.make_params(L, seed=5)
+    outs = []
+    for _ in range(2):
+        s = nm.System.create(x, y, th, k, p, cell_w=2048)
+        for _ in range(3):
+            s.step()
+        outs.append((s.nbr.clone(), s.x.clone(), s.y.clone(), s.theta.clone()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
+def _device_invariants(x, y, nbr, k):
+    """Every row: k distinct indices, no self, ascending by (d^2, j)."""
+    n = x.numel()
+    i = torch.arange(n, device="cuda").unsqueeze(1)
+    nb = nbr.long()
+    assert bool((nb >= 0).all()) and bool((nb < n).all()) and not bool((nb == i).any())
+    dx = (x[nb] - x.unsqueeze(1)).long()
+    dy = (y[nb] - y.unsqueeze(1)).long()
+    dx = (dx + L // 2) % L - L // 2
+    dy = (dy + L // 2) % L - L // 2
+    key = (dx * dx + dy * dy) * (1 << 24) + nb
+    assert bool((key[:, 1:] > key[:, :-1]).all())
+
+
+def _sample_rows(n, count, seed):
+    rng = np.random.default_rng(seed)
+    return np.unique(rng.integers(0, n, size=count)).astype(np.int32)
+
+
+def test_full_size_uniform_1m_sampled():
+    n, k = 1 << 20, 7
+    rc2 = workloads.rc2_for_mean(n, 7.0)
+    x, y, th = workloads.uniform(n)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    sysm = nm.System.create(x, y, th, k, p, cell_w=2048)
+    sysm.step()
+    offs, idx = nm.metric_list(sysm.ws, rc2)
+    assert nm.check(sysm.ws) == 0
+    assert rc2 == 2336407
+    _device_invariants(_dev(x, torch.int32), _dev(y, torch.int32), sysm.nbr, k)
+    rows = _sample_rows(n, 1000, 7)
+    rn, _ = oracle.knn(x, y, L, k, rows=rows, with_d2=False)
+    assert np.array_equal(sysm.nbr[torch.as_tensor(rows).long().cuda()].cpu().numpy(), rn)
+    rx, ry, rt = oracle.align_step(x, y, th, L, nbr=rn, v0=64, eta=0.2, seed=workloads.NOISE_SEED,
+                                   rows=rows)
+    sel = torch.as_tensor(rows).long().cuda()
+    assert np.array_equal(sysm.x[sel].cpu().numpy(), rx) and np.array_equal(sysm.y[sel].cpu().numpy(), ry)
+    assert _angle_err(sysm.theta[sel].cpu().numpy(), rt).max() <= TOL
+    ro, ri, _ = oracle.metric_list(x, y, L, rc2, rows=rows, with_d2=False)
+    offs_np, idx_np = offs.cpu().numpy(), idx.cpu().numpy()
+    got = np.concatenate([idx_np[offs_np[r]:offs_np[r + 1]] for r in rows])
+    assert np.array_equal(np.diff(ro), offs_np[rows + 1] - offs_np[rows])
+    assert np.array_equal(got, ri)
+    assert abs(offs_np[-1] / n - 7.0) < 0.05  # mean metric degree of the chosen r_c
+
+
+@pytest.mark.parametrize("k", [6, 12, 20])
+def test_full_size_clustered_4m_sampled(k):
+    n = 1 << 22
+    x, y, th = workloads.clustered(n)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    sysm = nm.System.create(x, y, th, k, p, cell_w=nm.suggest_cell_w(n, L, 1.0))
+    sysm.step()
+    assert nm.check(sysm.ws) == 0
+    _device_invariants(_dev(x, torch.int32), _dev(y, torch.int32), sysm.nbr, k)
+    rows = _sample_rows(n, 300, k)
+    rn, _ = oracle.knn(x, y, L, k, rows=rows, with_d2=False)
+    sel = torch.as_tensor(rows).long().cuda()
+    assert np.array_equal(sysm.nbr[sel].cpu().numpy(), rn)
+    rx, ry, rt = oracle.align_step(x, y, th, L, nbr=rn, v0=64, eta=0.2, seed=workloads.NOISE_SEED,
+                                   rows=rows)
+    assert np.array_equal(sysm.x[sel].cpu().numpy(), rx) and np.array_equal(sysm.y[sel].cpu().numpy(), ry)
+    assert _angle_err(sysm.theta[sel].cpu().numpy(), rt).max() <= TOL
+
+
+def test_range_error_is_reported():
+    n = 1000
+    x, y, th = workloads.uniform(n)
+    x[17] = L  # outside [0, L)
+    ws = nm.Workspace(n, L, 2048)
+    nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+    nm.knn(ws, 7)
+    assert nm.check(ws) == nm.NM_E_RANGE
+    assert nm.check(ws) == 0  # cleared
+
+
+def test_metric_capacity_overflow_is_reported():
+    n = 4097
+    x, y, _ = workloads.uniform(n)
+    ws = nm.Workspace(n, L, 2048)
+    nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+    small = torch.empty(100, dtype=torch.int32, device="cuda")
+    nm.metric_list(ws, workloads.rc2_for_mean(n, 7.0), idx=small)
+    assert nm.check(ws) == nm.NM_E_CAPACITY
+
+
+def test_grid_mismatch_is_reported():
+    n = 1000
+    x, y, _ = workloads.uniform(n)
+    ws = nm.Workspace(n, L, 2048)
+    nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+    other = nm.Workspace(n, L, 4096)
+    other.buf = ws.buf  # same memory, different grid description
+    nm.knn(other, 7)
+    assert nm.check(ws) == nm.NM_E_INVAL
