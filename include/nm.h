@@ -152,15 +152,29 @@ int nm_align_step(const int32_t* x, const int32_t* y, const float* theta, int32_
                   const nm_params* p, uint64_t step, int32_t* x_out, int32_t* y_out,
                   float* theta_out, void* ws_err, void* stream);
 
-/* One full step of the topological model (Alg. 1): cell binning, k-NN lists
- * and the fused alignment + move, in three kernels.  Same arguments and
- * results as nm_build_cells + nm_knn + nm_align_step(include the same k),
- * bit for bit in the lists and positions.  The cells left in `ws` describe
- * the time-t positions and can feed nm_metric_list / nm_knn afterwards.
- *   p->box must equal g->box. */
+/* One full step of the topological model (Alg. 1) = nm_bin_step followed by
+ * nm_knn_align.  Same results as nm_build_cells + nm_knn + nm_align_step
+ * with the same k and parameters: identical lists, positions and headings.
+ * The cells left in `ws` describe the time-t positions and can feed
+ * nm_metric_list / nm_knn afterwards.  p->box must equal g->box. */
 int nm_step(const nm_grid* g, const int32_t* x, const int32_t* y, const float* theta,
             int32_t k, const nm_params* p, uint64_t step, void* ws, size_t ws_bytes,
             int32_t* nbr, int32_t* x_out, int32_t* y_out, float* theta_out, void* stream);
+
+/* First stage of nm_step: the cell binning of nm_build_cells, which in the
+ * same pass stores, beside each particle's cell-ordered copy, its Philox
+ * noise word for `step` (Eq. 2) and the fp64 unit vector of its heading.
+ *   theta  fp32[n], headings at time t */
+int nm_bin_step(const nm_grid* g, const int32_t* x, const int32_t* y, const float* theta,
+                const nm_params* p, uint64_t step, void* ws, size_t ws_bytes, void* stream);
+
+/* Second stage of nm_step: the k-NN lists (as nm_knn) fused with Eq. (2) and
+ * Eq. (1) for every particle, from cells written by nm_bin_step with the
+ * same parameters.  `theta` is the time-t heading array given to nm_bin_step
+ * (read only where the alignment vector is exactly zero).  Outputs as nm_step. */
+int nm_knn_align(const nm_grid* g, const void* ws, int32_t k, const nm_params* p,
+                 const float* theta, int32_t* nbr, int32_t* x_out, int32_t* y_out,
+                 float* theta_out, void* stream);
 
 /* Synchronise `stream`, return the first error recorded in `ws` since the
  * last check (NM_OK if none) and clear it. */

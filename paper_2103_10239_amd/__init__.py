@@ -7,5 +7,6 @@ cutoff (metric) neighbour lists, and the alignment / move of Eq. (2) and
 Eq. (1), as hand-written HIP kernels behind the C ABI of include/nm.h.
 """
 from . import nm, workloads  # noqa: F401
-from .nm import (Grid, NMError, Params, System, Workspace, align_step, build_cells, check, knn,  # noqa: F401
-                 make_params, metric_list, step, suggest_cell_w)
+from .nm import (NM_E_CAPACITY, NM_E_DEVICE, NM_E_INVAL, NM_E_NOMEM, NM_E_RANGE, NM_MAX_K,  # noqa: F401
+                 NM_OK, Grid, NMError, Params, System, Workspace, align_step, bin_step, build_cells,
+                 check, knn, knn_align, make_params, metric_list, step, suggest_cell_w)

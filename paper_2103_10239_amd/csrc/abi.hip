@@ -201,6 +201,31 @@ int nm_align_step(const int32_t* x, const int32_t* y, const float* theta, int32_
                                 theta_out, static_cast<WsHeader*>(ws_err), as_stream(stream)));
 }
 
+int nm_bin_step(const nm_grid* g, const int32_t* x, const int32_t* y, const float* theta,
+                const nm_params* p, uint64_t step, void* ws, size_t ws_bytes, void* stream) {
+  Layout lay;
+  if (!ws_ok(g, ws, ws_bytes, &lay) || !params_ok(p) || p->box != g->box) return NM_E_INVAL;
+  if (x == nullptr || y == nullptr || theta == nullptr) return NM_E_INVAL;
+  return status_of(launch_build(dev_ws(g, lay, ws), x, y, theta, p, step, as_stream(stream)));
+}
+
+int nm_knn_align(const nm_grid* g, const void* ws, int32_t k, const nm_params* p,
+                 const float* theta, int32_t* nbr, int32_t* x_out, int32_t* y_out,
+                 float* theta_out, void* stream) {
+  Layout lay;
+  if (!make_layout(g, &lay) || ws == nullptr || !params_ok(p) || p->box != g->box)
+    return NM_E_INVAL;
+  if (theta == nullptr || nbr == nullptr || x_out == nullptr || y_out == nullptr ||
+      theta_out == nullptr)
+    return NM_E_INVAL;
+  if (k < 1 || k > NM_MAX_K || k > g->n - 1) return NM_E_INVAL;
+  const void* outs[3] = {x_out, y_out, theta_out};
+  for (const void* b : outs)
+    if (b == theta) return NM_E_INVAL;
+  return status_of(launch_knn_align(dev_ws(g, lay, const_cast<void*>(ws)), k, p, theta, nbr, x_out,
+                                    y_out, theta_out, as_stream(stream)));
+}
+
 int nm_step(const nm_grid* g, const int32_t* x, const int32_t* y, const float* theta, int32_t k,
             const nm_params* p, uint64_t step, void* ws, size_t ws_bytes, int32_t* nbr,
             int32_t* x_out, int32_t* y_out, float* theta_out, void* stream) {
@@ -215,11 +240,9 @@ int nm_step(const nm_grid* g, const int32_t* x, const int32_t* y, const float* t
   for (const void* a : ins)
     for (const void* b : outs)
       if (a == b) return NM_E_INVAL;
-  const DevWs w = dev_ws(g, lay, ws);
-  hipStream_t s = as_stream(stream);
-  hipError_t e = launch_build(w, x, y, theta, p, step, s);
-  if (e != hipSuccess) return NM_E_DEVICE;
-  return status_of(launch_knn_align(w, k, p, theta, nbr, x_out, y_out, theta_out, s));
+  const int rc = nm_bin_step(g, x, y, theta, p, step, ws, ws_bytes, stream);
+  if (rc != NM_OK) return rc;
+  return nm_knn_align(g, ws, k, p, theta, nbr, x_out, y_out, theta_out, stream);
 }
 
 int nm_check(void* ws, void* stream) {

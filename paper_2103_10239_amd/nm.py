@@ -66,9 +66,11 @@ def lib():
                                 _vp, _vp, _vp, _vp, _vp]
     L.nm_step.argtypes = [gp, _vp, _vp, _vp, _c_i32, pp, _c_u64, _vp, ctypes.c_size_t, _vp, _vp,
                           _vp, _vp, _vp]
+    L.nm_bin_step.argtypes = [gp, _vp, _vp, _vp, pp, _c_u64, _vp, ctypes.c_size_t, _vp]
+    L.nm_knn_align.argtypes = [gp, _vp, _c_i32, pp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.nm_check.argtypes = [_vp, _vp]
     for f in ("nm_workspace_init", "nm_build_cells", "nm_knn", "nm_metric_list", "nm_align_step",
-              "nm_step", "nm_check"):
+              "nm_step", "nm_bin_step", "nm_knn_align", "nm_check"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -214,6 +216,26 @@ def step(ws: Workspace, x, y, theta, k: int, params: Params, step_index: int, nb
                       ws.ptr, ws.nbytes, _dev(nbr, torch.int32, n * k, "nbr"),
                       _dev(x_out, torch.int32, n, "x_out"), _dev(y_out, torch.int32, n, "y_out"),
                       _dev(theta_out, torch.float32, n, "theta_out"), _stream(ws.device)), "step")
+
+
+def bin_step(ws: Workspace, x, y, theta, params: Params, step_index: int) -> None:
+    """First stage of step(): cell binning plus the per-particle noise word and
+    fp64 heading unit vector for this step."""
+    n = ws.n
+    _ok(lib().nm_bin_step(ctypes.byref(ws.grid), _dev(x, torch.int32, n, "x"),
+                          _dev(y, torch.int32, n, "y"), _dev(theta, torch.float32, n, "theta"),
+                          ctypes.byref(params), step_index, ws.ptr, ws.nbytes, _stream(ws.device)),
+        "bin_step")
+
+
+def knn_align(ws: Workspace, k: int, params: Params, theta, nbr, x_out, y_out, theta_out) -> None:
+    """Second stage of step(): k-NN lists fused with Eq. (2) and Eq. (1)."""
+    n = ws.n
+    _ok(lib().nm_knn_align(ctypes.byref(ws.grid), ws.ptr, k, ctypes.byref(params),
+                           _dev(theta, torch.float32, n, "theta"), _dev(nbr, torch.int32, n * k, "nbr"),
+                           _dev(x_out, torch.int32, n, "x_out"), _dev(y_out, torch.int32, n, "y_out"),
+                           _dev(theta_out, torch.float32, n, "theta_out"), _stream(ws.device)),
+        "knn_align")
 
 
 def check(ws: Workspace) -> int:
