@@ -72,7 +72,9 @@ typedef struct nm_grid {
   int32_t n;      /* particles, 2 <= n <= 2^24                                     */
   int32_t box;    /* L, power of two in [2, 2^20]                                  */
   int32_t cell_w; /* w, power of two in [1, L]; (L/w)^2 <= 2^28 cells              */
-  int32_t flags;  /* reserved, must be 0                                           */
+  int32_t block;  /* k-NN fast-path block side in cells: 0 = chosen from n, L, w   */
+                  /* and k; 3..8 = that side; -1 = exact ring search only.  The   */
+                  /* lists are identical for every choice; only speed differs.    */
 } nm_grid;
 
 /* Parameters of Eq. (1) and Eq. (2). */

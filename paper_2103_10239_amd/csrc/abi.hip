@@ -38,7 +38,7 @@ bool params_ok(const nm_params* p) {
 }  // namespace
 
 bool make_layout(const nm_grid* g, Layout* out) {
-  if (g == nullptr || g->flags != 0) return false;
+  if (g == nullptr || g->block < -1 || g->block > kMaxB || (g->block > 0 && g->block < 3)) return false;
   if (g->n < 2 || g->n > kMaxParticles) return false;
   if (!is_pow2(g->box) || g->box < 2 || g->box > (1 << 20)) return false;
   if (!is_pow2(g->cell_w) || g->cell_w > g->box) return false;
@@ -155,7 +155,7 @@ int nm_knn(const nm_grid* g, const void* ws, int32_t k, int32_t* nbr, int64_t* d
   Layout lay;
   if (!make_layout(g, &lay) || ws == nullptr || nbr == nullptr) return NM_E_INVAL;
   if (k < 1 || k > NM_MAX_K || k > g->n - 1) return NM_E_INVAL;
-  return status_of(launch_knn(dev_ws(g, lay, const_cast<void*>(ws)), k, nbr,
+  return status_of(launch_knn(dev_ws(g, lay, const_cast<void*>(ws)), k, g->block, nbr,
                               reinterpret_cast<long long*>(d2), as_stream(stream)));
 }
 
@@ -222,8 +222,8 @@ int nm_knn_align(const nm_grid* g, const void* ws, int32_t k, const nm_params* p
   const void* outs[3] = {x_out, y_out, theta_out};
   for (const void* b : outs)
     if (b == theta) return NM_E_INVAL;
-  return status_of(launch_knn_align(dev_ws(g, lay, const_cast<void*>(ws)), k, p, theta, nbr, x_out,
-                                    y_out, theta_out, as_stream(stream)));
+  return status_of(launch_knn_align(dev_ws(g, lay, const_cast<void*>(ws)), k, g->block, p, theta,
+                                    nbr, x_out, y_out, theta_out, as_stream(stream)));
 }
 
 int nm_step(const nm_grid* g, const int32_t* x, const int32_t* y, const float* theta, int32_t k,

@@ -69,8 +69,12 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* __restrict_
 
 // Exclusive prefix sum of in[0, m) into out[0, m], out[m] = total.  `in` may
 // alias `out`.  With clear_in (and in != out) the input is zeroed after it
-// is read.  Tiles take increasing tickets, so every predecessor of a tile is
-// already running when the tile waits on it: the look-back always ends.
+// is read.  Single pass with decoupled look-back: each tile publishes its
+// aggregate, then the first wave of the tile inspects 64 predecessor tiles at
+// a time, adding aggregates until it meets a published inclusive prefix.
+// Tiles take increasing tickets, so every predecessor of a tile is already
+// running when the tile waits on it: the look-back always ends (a bounded
+// spin records NM_E_DEVICE instead of waiting forever).
 __global__ __launch_bounds__(kBlock) void k_scan(int32_t* in, int32_t* out, int64_t m,
                                                  ScanState* st, WsHeader* hdr, int clear_in) {
   __shared__ uint32_t s_tile;
@@ -104,37 +108,53 @@ __global__ __launch_bounds__(kBlock) void k_scan(int32_t* in, int32_t* out, int6
     if (q < wave) wave_off += s_wave[q];
     agg += s_wave[q];
   }
-  if (threadIdx.x == 0) {
+  if (wave == 0) {
     unsigned long long* flags = st->flags;
     long long prefix = 0;
     if (tile == 0) {
-      __hip_atomic_store(&flags[0], kFlagPrefix | static_cast<unsigned long long>(agg),
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0)
+        __hip_atomic_store(&flags[0], kFlagPrefix | static_cast<unsigned long long>(agg),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      __hip_atomic_store(&flags[tile], kFlagAgg | static_cast<unsigned long long>(agg),
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      int j = static_cast<int>(tile) - 1;
+      if (lane == 0)
+        __hip_atomic_store(&flags[tile], kFlagAgg | static_cast<unsigned long long>(agg),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int top = static_cast<int>(tile) - 1;  // predecessor seen by lane 0
       int spins = 0;
       while (true) {
+        const int j = top - lane;
+        // Tiles before tile 0 do not exist: read them as a prefix of 0.
         const unsigned long long f =
-            __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((f & ~kValueMask) == 0ull) {
+            j >= 0 ? __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                   : kFlagPrefix;
+        const unsigned long long state = f & ~kValueMask;
+        const unsigned long long pending = __ballot(state == 0ull);
+        const unsigned long long done = __ballot(state == kFlagPrefix);
+        const int p = done ? __ffsll(static_cast<long long>(done)) - 1 : 64;
+        const unsigned long long upto = p >= 63 ? ~0ull : ((2ull << p) - 1ull);
+        if (pending & upto) {
           if (++spins > kSpinLimit) {
-            set_err(hdr, NM_E_DEVICE);
+            if (lane == 0) set_err(hdr, NM_E_DEVICE);
             break;
           }
           __builtin_amdgcn_s_sleep(1);
           continue;
         }
-        prefix += static_cast<long long>(f & kValueMask);
-        if ((f & ~kValueMask) == kFlagPrefix || j == 0) break;
-        --j;
+        long long part = lane <= p ? static_cast<long long>(f & kValueMask) : 0ll;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+        prefix += part;
+        if (p < 64) break;
+        top -= 64;
       }
-      __hip_atomic_store(&flags[tile], kFlagPrefix | static_cast<unsigned long long>(prefix + agg),
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0)
+        __hip_atomic_store(&flags[tile], kFlagPrefix | static_cast<unsigned long long>(prefix + agg),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    s_prefix = prefix;
-    if ((prefix + agg) > 0x7FFFFFFFll) set_err(hdr, NM_E_CAPACITY);
+    if (lane == 0) {
+      s_prefix = prefix;
+      if ((prefix + agg) > 0x7FFFFFFFll) set_err(hdr, NM_E_CAPACITY);
+    }
   }
   __syncthreads();
   long long run = s_prefix + wave_off + (incl - sum);

@@ -1,12 +1,19 @@
-// metric.hip -- metric neighbour lists (Sec. III: "all pairs of particles
-// within some distance r_0 count as neighbours"), built from the same cells
-// as the topological lists, as CSR rows in the caller's particle order.
+// metric.hip -- metric neighbour lists (Sec. III: all pairs of particles
+// within a distance r_0 count as neighbours), from the same cells as the
+// topological lists, as CSR rows in the caller's particle order, each row
+// ascending by (d^2, index).
 //
 // Three kernels: count the row lengths (one lane per query, cell order),
 // prefix-sum them into the row offsets (the scan of cells.hip), and fill the
-// rows.  Rows must be ascending by (d^2, index), so the fill pass selects the
-// row in chunks of kChunk keys: each pass walks the same cells and keeps the
-// kChunk smallest keys above the last key already written.
+// rows.  The fill selects a row in chunks of kChunk keys: each pass over the
+// candidates keeps the kChunk smallest keys above the last key written.
+//
+// Fast path: when a B x B block of cells around the query contains the whole
+// disk of radius r_c (odd B, centred), the lane scans just that block, and
+// the fill uses the 32-bit keys and branch-free insertion network of the k-NN
+// fast path; the row is certified when no two of its entries have the same
+// d^2 >> sh.  Otherwise (or when certification fails) the lane walks rings of
+// cells with exact 64-bit keys.
 #include "nm_internal.h"
 
 namespace nm {
@@ -20,8 +27,8 @@ __device__ __forceinline__ bool ws_ready(const DevWs& w) {
   return h->built == kBuilt && h->n == w.n && h->box == w.box && h->cell_w == w.cell_w;
 }
 
-// Visit every particle t != s of the cells that can hold a point within rc2
-// of the query; f(t, d2, index) is called for those with d2 <= rc2.
+// Exact walk: every particle t != s of the cells that can hold a point within
+// rc2 of the query; f(t, d2, index) for those with d2 <= rc2.
 template <class F>
 __device__ __forceinline__ void for_each_within(const DevWs& w, int s, int qx, int qy,
                                                 long long rc2, int total, F&& f) {
@@ -50,7 +57,12 @@ __device__ __forceinline__ void for_each_within(const DevWs& w, int s, int qx, i
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_metric_count(DevWs w, long long rc2,
+__device__ __forceinline__ uint32_t d2_32(int x, int y, int qx, int qy) {
+  const int dx = x - qx, dy = y - qy;
+  return static_cast<uint32_t>(__mul24(dx, dx)) + static_cast<uint32_t>(__mul24(dy, dy));
+}
+
+__global__ __launch_bounds__(kBlock) void k_metric_count(DevWs w, FastCfg f, long long rc2,
                                                          int32_t* __restrict__ offsets) {
   if (blockIdx.x == 0) {
     for (int t = threadIdx.x; t < w.nb_scan_m; t += blockDim.x) w.scan_m->flags[t] = 0ull;
@@ -65,11 +77,63 @@ __global__ __launch_bounds__(kBlock) void k_metric_count(DevWs w, long long rc2,
   if (s >= total) return;
   const int4 q = w.sorted[s];
   int cnt = 0;
-  for_each_within(w, s, q.x, q.y, rc2, total, [&](int, long long, int) { ++cnt; });
+  bool fast = false;
+  if (f.B > 0) {
+    BlockSegs sg;
+    long long bound;
+    int ncand;
+    const uint32_t r32 = static_cast<uint32_t>(rc2);
+    fast = scan_block(w, f, s, q.x, q.y, total, sg, bound, ncand,
+                      [&](int x, int y, int qx, int qy, int) { cnt += d2_32(x, y, qx, qy) <= r32; });
+    fast = fast && rc2 < bound;
+  }
+  if (!fast) {
+    cnt = 0;
+    for_each_within(w, s, q.x, q.y, rc2, total, [&](int, long long, int) { ++cnt; });
+  }
   offsets[q.z] = cnt;
 }
 
-__global__ __launch_bounds__(kBlock) void k_metric_fill(DevWs w, long long rc2,
+// Fill the row of query s through the fast block; false if not certified.
+__device__ __forceinline__ bool fill_fast(const DevWs& w, const FastCfg& f, int s, int qx, int qy,
+                                          long long rc2, int total, long long m,
+                                          int32_t* __restrict__ out) {
+  const uint32_t r32 = static_cast<uint32_t>(rc2);
+  const int sh = f.sh;
+  uint32_t last = 0u;
+  long long written = 0;
+  uint32_t prev_d = 0xFFFFFFFFu;  // d^2 >> sh of the last entry written
+  while (written < m) {
+    const int need = static_cast<int>(min<long long>(kChunk, m - written));
+    uint32_t key[kChunk];
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) key[t] = (t < kChunk - need) ? 0u : kKey32Inf;
+    BlockSegs sg;
+    long long bound;
+    int ncand;
+    const bool ok = scan_block(w, f, s, qx, qy, total, sg, bound, ncand,
+                               [&](int x, int y, int qxi, int qyi, int ord) {
+                                 const uint32_t d2 = d2_32(x, y, qxi, qyi);
+                                 const uint32_t kk = ((d2 >> sh) << 8) | static_cast<uint32_t>(ord);
+                                 net_insert(key, (d2 <= r32 && kk > last) ? kk : kKey32Inf);
+                               });
+    if (!ok || ncand > 255 || rc2 >= bound || key[kChunk - 1] == kKey32Inf) return false;
+    bool good = prev_d == 0xFFFFFFFFu || key32_d(key[kChunk - need]) != prev_d;
+#pragma unroll
+    for (int t = 0; t < kChunk - 1; ++t)
+      if (t >= kChunk - need) good = good && key32_d(key[t]) != key32_d(key[t + 1]);
+    if (!good) return false;
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t)
+      if (t >= kChunk - need) out[written + t - (kChunk - need)] = w.sorted[seg_slot(sg, key32_ord(key[t]))].z;
+    written += need;
+    last = key[kChunk - 1];
+    prev_d = key32_d(last);
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_metric_fill(DevWs w, FastCfg f, long long rc2,
                                                         const int32_t* __restrict__ offsets,
                                                         int32_t* __restrict__ idx, long long cap) {
   if (!ws_ready(w)) return;
@@ -88,6 +152,8 @@ __global__ __launch_bounds__(kBlock) void k_metric_fill(DevWs w, long long rc2,
     set_err(w.hdr, NM_E_INVAL);
     return;
   }
+  int32_t* out = idx + base;
+  if (m == 0 || (f.B > 0 && fill_fast(w, f, s, q.x, q.y, rc2, total, m, out))) return;
   long long written = 0;
   unsigned long long last = 0ull;  // every real key is >= 1
   while (written < m) {
@@ -102,20 +168,38 @@ __global__ __launch_bounds__(kBlock) void k_metric_fill(DevWs w, long long rc2,
       set_err(w.hdr, NM_E_INVAL);
       return;
     }
-    int32_t* out = idx + base + written;
 #pragma unroll
     for (int t = 0; t < kChunk; ++t)
-      if (t >= kChunk - need) out[t - (kChunk - need)] = key_index(top.key[t]);
+      if (t >= kChunk - need) out[written + t - (kChunk - need)] = key_index(top.key[t]);
     written += need;
     last = top.worst();
   }
+}
+
+// Block of odd side B centred on the home cell that contains the disk of
+// radius r_c for every query: (B - 1) / 2 cells >= r_c + 1.
+FastCfg metric_cfg(const DevWs& w, long long rc2) {
+  FastCfg f{0, 0};
+  const double rc = sqrt(static_cast<double>(rc2));
+  const int cw = 1 << w.log2_w;
+  const int half = static_cast<int>(ceil((rc + 1.0) / cw));
+  const int B = 2 * half + 1;
+  if (B > kMaxB || B + 2 > w.G) return f;
+  const long long ext = static_cast<long long>(half + 1) * cw;
+  if (ext >= 32768) return f;
+  int sh = 0;
+  while ((rc2 >> sh) >= (1ll << 24) - 1) ++sh;
+  f.B = B;
+  f.sh = sh;
+  return f;
 }
 
 }  // namespace
 
 hipError_t launch_metric_count(const DevWs& w, long long rc2, int32_t* offsets, hipStream_t s) {
   const int nb = (w.n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_metric_count, dim3(nb), dim3(kBlock), 0, s, w, rc2, offsets);
+  hipLaunchKernelGGL(k_metric_count, dim3(nb), dim3(kBlock), 0, s, w, metric_cfg(w, rc2), rc2,
+                     offsets);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_scan_rows(offsets, w.n, w.scan_m, w.nb_scan_m, w.hdr, s);
@@ -124,7 +208,8 @@ hipError_t launch_metric_count(const DevWs& w, long long rc2, int32_t* offsets, 
 hipError_t launch_metric_fill(const DevWs& w, long long rc2, const int32_t* offsets, int32_t* idx,
                               long long cap, hipStream_t s) {
   const int nb = (w.n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_metric_fill, dim3(nb), dim3(kBlock), 0, s, w, rc2, offsets, idx, cap);
+  hipLaunchKernelGGL(k_metric_fill, dim3(nb), dim3(kBlock), 0, s, w, metric_cfg(w, rc2), rc2,
+                     offsets, idx, cap);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@
 namespace nm {
 
 constexpr int kBlock = 256;
-constexpr int kScanItems = 8;
+constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr uint32_t kMagic = 0x4E4D5753u;  // "NMWS"
 constexpr uint32_t kBuilt = 0x42554C54u;  // "BULT"
@@ -240,7 +240,132 @@ struct QueryGeom {
   }
 };
 
-// Host-side helpers (abi.hip).
+// ---------------------------------------------------------------------------
+// Fast-path search block.  A B x B block of cells chosen around the query:
+// for odd B centred on its home cell, for even B shifted toward the half of
+// the home cell that holds the query, so the query sits near the block
+// centre.  Each of the B cell rows is one contiguous range of cell-ordered
+// slots (the block may wrap around the box in y, not in x); the home row is
+// split around the query's own slot.  Candidates get 32-bit keys
+//   (d^2 >> sh) << 8 | ordinal,   ordinal = 1 + position in the scan,
+// and every candidate goes through a branch-free insertion network.  The
+// result is exact, and is used, when the block holds fewer than 255
+// candidates, the k+1 smallest keys have distinct d^2 >> sh fields, and the
+// k-th squared distance is strictly below the squared distance from the
+// query to the nearest cell outside the block.  Otherwise the caller runs the
+// exact ring search.
+// ---------------------------------------------------------------------------
+constexpr int kMaxB = 8;
+constexpr int kMaxSeg = kMaxB + 1;
+constexpr uint32_t kKey32Inf = 0xFFFFFFFFu;
+
+struct FastCfg {
+  int B;   // block side in cells; 0 disables the fast path
+  int sh;  // right shift of d^2 so that every block distance fits 24 bits
+};
+
+// Segment r holds block row r; segment kMaxB holds the part of the home row
+// after the query's own slot.  Unused segments have cum = INT_MAX.
+struct BlockSegs {
+  int beg[kMaxSeg];  // first slot of each scanned range
+  int cum[kMaxSeg];  // ordinal of that range's first candidate
+};
+
+__device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+// Branch-free insertion of kk into an ascending list of KT keys whose first
+// entries may be the sentinel 0: key[t] <- med3(key[t-1], kk, key[t]).
+template <int KT>
+__device__ __forceinline__ void net_insert(uint32_t (&key)[KT], uint32_t kk) {
+#pragma unroll
+  for (int t = KT - 1; t > 0; --t) key[t] = umed3(key[t - 1], kk, key[t]);
+  key[0] = min(key[0], kk);
+}
+
+__device__ __forceinline__ uint32_t key32_d(uint32_t kk) { return kk >> 8; }
+__device__ __forceinline__ int key32_ord(uint32_t kk) { return static_cast<int>(kk & 0xFFu); }
+
+// Slot of the candidate with scan ordinal `ord` (1-based): it lies in the
+// segment with the largest first ordinal not above `ord`.
+__device__ __forceinline__ int seg_slot(const BlockSegs& b, int ord) {
+  int slot = -1, best = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxSeg; ++i) {
+    if (ord >= b.cum[i] && b.cum[i] >= best) {
+      best = b.cum[i];
+      slot = b.beg[i] + (ord - b.cum[i]);
+    }
+  }
+  return slot;
+}
+
+// Scan the fast-path block of query (slot s, position qx, qy).  Runs `visit`
+// on every candidate as visit(x, y, qx_image, qy_image, ordinal).  Returns
+// false if the block wraps in x (the caller then uses the exact search);
+// `bound` receives the squared distance to the nearest cell outside.
+template <class Visit>
+__device__ __forceinline__ bool scan_block(const DevWs& w, const FastCfg& f, int s, int qx, int qy,
+                                           int total, BlockSegs& sg, long long& bound, int& ncand,
+                                           Visit&& visit) {
+  const int G = w.G, L = w.box, cw = 1 << w.log2_w;
+  const int hx = qx >> w.log2_w, hy = qy >> w.log2_w;
+  const int ox = qx & (cw - 1), oy = qy & (cw - 1);
+  const int half = f.B >> 1;
+  const int lo_x = (f.B & 1) ? -half : -half + (ox >= (cw >> 1) ? 1 : 0);
+  const int lo_y = (f.B & 1) ? -half : -half + (oy >= (cw >> 1) ? 1 : 0);
+  const int hi_x = lo_x + f.B - 1, hi_y = lo_y + f.B - 1;
+  if (hx + lo_x < 0 || hx + hi_x >= G) return false;
+  const int gl = ox - lo_x * cw + 1, gr = (hi_x + 1) * cw - ox;
+  const int gd = oy - lo_y * cw + 1, gu = (hi_y + 1) * cw - oy;
+  const long long m = min(min(gl, gr), min(gd, gu));
+  bound = m * m;
+  const int2* pos = reinterpret_cast<const int2*>(w.sorted);
+  int ord = 1;
+  sg.beg[kMaxB] = 0;
+  sg.cum[kMaxB] = 0x7FFFFFFF;
+#pragma unroll
+  for (int r = 0; r < kMaxB; ++r) {
+    sg.beg[r] = 0;
+    sg.cum[r] = 0x7FFFFFFF;
+    if (r < f.B) {
+      int cy = hy + lo_y + r, sy = qy;
+      if (cy < 0) {
+        cy += G;
+        sy = qy + L;
+      } else if (cy >= G) {
+        cy -= G;
+        sy = qy - L;
+      }
+      const int64_t row = static_cast<int64_t>(cy) * G + hx;
+      const int a = w.start[row + lo_x];
+      const int e = min(w.start[row + hi_x + 1], total);
+      const bool home = (lo_y + r) == 0;
+      const int e1 = home ? s : e;  // the home row is scanned as [a, s) and (s, e)
+      sg.beg[r] = a;
+      sg.cum[r] = ord;
+      for (int t = a; t < e1; ++t, ++ord) {
+        const int2 p = pos[2 * t];
+        visit(p.x, p.y, qx, sy, ord);
+      }
+      if (home) {
+        sg.beg[kMaxB] = s + 1;
+        sg.cum[kMaxB] = ord;
+        for (int t = s + 1; t < e; ++t, ++ord) {
+          const int2 p = pos[2 * t];
+          visit(p.x, p.y, qx, sy, ord);
+        }
+      }
+    }
+  }
+  ncand = ord - 1;
+  return true;
+}
+
+// Host-side helpers (abi.hip).// Host-side helpers (abi.hip).
 bool make_layout(const nm_grid* g, Layout* out);
 DevWs dev_ws(const nm_grid* g, const Layout& lay, void* ws);
 
@@ -248,10 +373,11 @@ DevWs dev_ws(const nm_grid* g, const Layout& lay, void* ws);
 hipError_t launch_ws_init(const DevWs& w, hipStream_t s);
 hipError_t launch_build(const DevWs& w, const int32_t* x, const int32_t* y, const float* theta,
                         const nm_params* p, uint64_t step, hipStream_t s);
-hipError_t launch_knn(const DevWs& w, int k, int32_t* nbr, long long* d2, hipStream_t s);
-hipError_t launch_knn_align(const DevWs& w, int k, const nm_params* p, const float* theta,
-                            int32_t* nbr, int32_t* x_out, int32_t* y_out, float* theta_out,
-                            hipStream_t s);
+FastCfg fast_cfg(const DevWs& w, int k, int block);
+hipError_t launch_knn(const DevWs& w, int k, int block, int32_t* nbr, long long* d2, hipStream_t s);
+hipError_t launch_knn_align(const DevWs& w, int k, int block, const nm_params* p,
+                            const float* theta, int32_t* nbr, int32_t* x_out, int32_t* y_out,
+                            float* theta_out, hipStream_t s);
 hipError_t launch_metric_count(const DevWs& w, long long rc2, int32_t* offsets, hipStream_t s);
 hipError_t launch_metric_fill(const DevWs& w, long long rc2, const int32_t* offsets, int32_t* idx,
                               long long cap, hipStream_t s);

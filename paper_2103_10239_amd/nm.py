@@ -31,8 +31,9 @@ class NMError(RuntimeError):
 
 
 class Grid(ctypes.Structure):
-    """nm_grid: n particles, box side L, cell width w (powers of two)."""
-    _fields_ = [("n", _c_i32), ("box", _c_i32), ("cell_w", _c_i32), ("flags", _c_i32)]
+    """nm_grid: n particles, box side L, cell width w (powers of two), and the
+    k-NN fast-path block side (0 automatic, -1 exact ring search only)."""
+    _fields_ = [("n", _c_i32), ("box", _c_i32), ("cell_w", _c_i32), ("block", _c_i32)]
 
 
 class Params(ctypes.Structure):
@@ -116,10 +117,10 @@ def make_params(box: int, v0: int = 64, eta: float = 0.2, include_self: int = 1,
 class Workspace:
     """Device workspace of one system's cell grid (owned by torch)."""
 
-    def __init__(self, n: int, box: int, cell_w: int | None = None, device="cuda"):
+    def __init__(self, n: int, box: int, cell_w: int | None = None, device="cuda", block: int = 0):
         if cell_w is None:
             cell_w = suggest_cell_w(n, box)
-        self.grid = Grid(n, box, cell_w, 0)
+        self.grid = Grid(n, box, cell_w, block)
         nbytes = int(lib().nm_workspace_bytes(ctypes.byref(self.grid)))
         if nbytes < 0:
             raise NMError(nbytes, f"workspace_bytes(n={n}, box={box}, cell_w={cell_w})")

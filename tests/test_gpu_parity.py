@@ -321,3 +321,60 @@ def test_grid_mismatch_is_reported():
     other.buf = ws.buf  # same memory, different grid description
     nm.knn(other, 7)
     assert nm.check(ws) == nm.NM_E_INVAL
+
+
+def _gpu_knn_block(x, y, k, w, block):
+    ws = nm.Workspace(len(x), L, w, block=block)
+    nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+    nbr, d2 = nm.knn(ws, k, with_d2=True)
+    assert nm.check(ws) == 0
+    return nbr.cpu().numpy(), d2.cpu().numpy()
+
+
+@pytest.mark.parametrize("block", [-1, 0, 3, 4, 5, 6, 8])
+@pytest.mark.parametrize("kind,n,k,w", [("uniform", 20013, 7, 4096), ("uniform", 20013, 1, 8192),
+                                        ("uniform", 20013, 20, 4096), ("clustered", 20013, 12, 2048),
+                                        ("squeezed", 3000, 7, 1024), ("clustered", 8191, 32, 4096)])
+def test_knn_every_search_path_matches_oracle(kind, n, k, w, block):
+    # block = -1: exact ring search only; 0: automatic fast block; >0: that block side.
+    x, y, _ = _gen(kind, n)
+    nbr, d2 = _gpu_knn_block(x, y, k, w, block)
+    rn, rd = oracle.knn(x, y, L, k)
+    assert np.array_equal(nbr, rn) and np.array_equal(d2, rd)
+
+
+@pytest.mark.parametrize("block", [-1, 0, 4, 6])
+def test_knn_lattice_ties_every_path(block):
+    # every distance is tied: the fast path must always hand over to the exact search
+    x, y, a = workloads.lattice(64)
+    for k in (4, 7, 8):
+        nbr, d2 = _gpu_knn_block(x, y, k, a, block)
+        rn, rd = oracle.knn(x, y, L, k)
+        assert np.array_equal(nbr, rn) and np.array_equal(d2, rd)
+
+
+@pytest.mark.parametrize("block", [-1, 0])
+def test_fused_step_every_path(block):
+    n, k = 20013, 7
+    x, y, th = workloads.uniform(n)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    ws = nm.Workspace(n, L, 4096, block=block)
+    X, Y, T = _dev(x, torch.int32), _dev(y, torch.int32), _dev(th, torch.float32)
+    nbr = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    out = (torch.empty_like(X), torch.empty_like(Y), torch.empty_like(T))
+    nm.step(ws, X, Y, T, k, p, 0, nbr, *out)
+    assert nm.check(ws) == 0
+    rn, rx, ry, rt = oracle.step(x, y, th, L, k, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    assert np.array_equal(nbr.cpu().numpy(), rn)
+    assert np.array_equal(out[0].cpu().numpy(), rx) and np.array_equal(out[1].cpu().numpy(), ry)
+    assert _angle_err(out[2].cpu().numpy(), rt).max() <= TOL
+
+
+@pytest.mark.parametrize("kind,n,mean,w", [("uniform", 20013, 7.0, 4096), ("uniform", 20013, 7.0, 8192),
+                                           ("clustered", 20013, 3.0, 2048), ("squeezed", 3000, 2.0, 1024)])
+def test_metric_fast_block_matches_oracle(kind, n, mean, w):
+    x, y, _ = _gen(kind, n)
+    rc2 = workloads.rc2_for_mean(n, mean)
+    offs, idx = _gpu_metric(x, y, rc2, w)
+    ro, ri, _ = oracle.metric_list(x, y, L, rc2)
+    assert np.array_equal(offs, ro) and np.array_equal(idx, ri)
