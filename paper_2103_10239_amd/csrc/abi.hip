@@ -64,7 +64,11 @@ bool make_layout(const nm_grid* g, Layout* out) {
   L.off_sorted = off;
   off += round_up(16 * static_cast<int64_t>(g->n));
   L.off_cs = off;
-  off += round_up(16 * static_cast<int64_t>(g->n));
+  off += round_up(32 * static_cast<int64_t>(g->n));
+  L.off_queue = off;
+  off += round_up(4 * static_cast<int64_t>(g->n));
+  L.off_qcnt = off;
+  off += round_up(4 * L.C);
   L.total = off;
   *out = L;
   return true;
@@ -81,6 +85,8 @@ DevWs dev_ws(const nm_grid* g, const Layout& lay, void* ws) {
   w.rank = reinterpret_cast<int32_t*>(b + lay.off_rank);
   w.sorted = reinterpret_cast<int4*>(b + lay.off_sorted);
   w.cs = reinterpret_cast<double2*>(b + lay.off_cs);
+  w.queue = reinterpret_cast<int32_t*>(b + lay.off_queue);
+  w.qcnt = reinterpret_cast<int32_t*>(b + lay.off_qcnt);
   w.n = g->n;
   w.box = g->box;
   w.cell_w = g->cell_w;

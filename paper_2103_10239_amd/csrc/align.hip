@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_align(const int32_t* __restrict__ x,
   const double e = static_cast<double>(a.eta);
   const double vx = ax + e * cp;
   const double vy = ay + e * sp;
-  theta_out[i] = (vx == 0.0 && vy == 0.0) ? th0 : static_cast<float>(atan2(vy, vx));
+  theta_out[i] = vec_angle(vx, vy, th0);
 
   const int xi = x[i], yi = y[i];
   if (static_cast<uint32_t>(xi) >= static_cast<uint32_t>(a.box) ||

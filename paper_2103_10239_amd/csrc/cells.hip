@@ -6,9 +6,10 @@
 //   scan        exclusive prefix sum of the histogram -> cell start table,
 //               single pass with decoupled look-back; clears the histogram
 //   bin_scatter per particle: write (x, y, index, noise word) to its slot in
-//               cell order; the fused step also stores (cos, sin) of the
-//               heading in fp64 and draws the Philox noise word here, where
-//               four consecutive particles share one Philox block.
+//               cell order; the fused step also draws the Philox noise word
+//               here (four consecutive particles share one Philox block) and
+//               stores, in fp64, the unit vector of the heading and the
+//               random unit vector of Eq. (2).
 #include "nm_internal.h"
 
 namespace nm {
@@ -39,6 +40,8 @@ __global__ __launch_bounds__(kBlock) void k_ws_init(DevWs w) {
       w.hdr->box = w.box;
       w.hdr->cell_w = w.cell_w;
       w.hdr->built = 0u;
+      w.hdr->qcount = 0u;
+      w.hdr->qdone = 0u;
     }
   }
 }
@@ -202,9 +205,11 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restric
     }
     w.sorted[pos] = make_int4(xi, yi, i, static_cast<int>(uint4_word(noise, q)));
     if (kFused) {
-      double sn, cs;
+      double sn, cs, xs, xc;
       sincos(static_cast<double>(theta[i]), &sn, &cs);
-      w.cs[pos] = make_double2(cs, sn);
+      sincos(noise_angle(uint4_word(noise, q)), &xs, &xc);
+      w.cs[2 * pos] = make_double2(cs, sn);      // unit vector of the heading at time t
+      w.cs[2 * pos + 1] = make_double2(xc, xs);  // the random unit vector xi of Eq. (2)
     }
   }
   if (t == 0) w.hdr->built = kBuilt;

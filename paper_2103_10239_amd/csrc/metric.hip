@@ -78,14 +78,15 @@ __global__ __launch_bounds__(kBlock) void k_metric_count(DevWs w, FastCfg f, lon
   const int4 q = w.sorted[s];
   int cnt = 0;
   bool fast = false;
-  if (f.B > 0) {
-    BlockSegs sg;
-    long long bound;
-    int ncand;
+  if (f.bfix > 0) {
+    const QBlock b = make_qblock(w, q.x, q.y, f.bfix);
     const uint32_t r32 = static_cast<uint32_t>(rc2);
-    fast = scan_block(w, f, s, q.x, q.y, total, sg, bound, ncand,
-                      [&](int x, int y, int qx, int qy, int) { cnt += d2_32(x, y, qx, qy) <= r32; });
-    fast = fast && rc2 < bound;
+    if (rc2 < b.bound) {
+      walk_block(w, b, s, q.x, q.y, total, [&](int x, int y, int qx, int qy, int, bool valid) {
+        cnt += (valid && d2_32(x, y, qx, qy) <= r32) ? 1 : 0;
+      });
+      fast = true;
+    }
   }
   if (!fast) {
     cnt = 0;
@@ -98,34 +99,39 @@ __global__ __launch_bounds__(kBlock) void k_metric_count(DevWs w, FastCfg f, lon
 __device__ __forceinline__ bool fill_fast(const DevWs& w, const FastCfg& f, int s, int qx, int qy,
                                           long long rc2, int total, long long m,
                                           int32_t* __restrict__ out) {
+  const QBlock b = make_qblock(w, qx, qy, f.bfix);
+  if (rc2 >= b.bound) return false;
   const uint32_t r32 = static_cast<uint32_t>(rc2);
-  const int sh = f.sh;
+  int sh = 0;
+  while ((rc2 >> sh) >= (1ll << kDBits) - 1) ++sh;
   uint32_t last = 0u;
   long long written = 0;
-  uint32_t prev_d = 0xFFFFFFFFu;  // d^2 >> sh of the last entry written
+  uint32_t prev_d = 0xFFFFFFFFu;  // distance field of the last entry written
   while (written < m) {
     const int need = static_cast<int>(min<long long>(kChunk, m - written));
     uint32_t key[kChunk];
 #pragma unroll
     for (int t = 0; t < kChunk; ++t) key[t] = (t < kChunk - need) ? 0u : kKey32Inf;
-    BlockSegs sg;
-    long long bound;
-    int ncand;
-    const bool ok = scan_block(w, f, s, qx, qy, total, sg, bound, ncand,
-                               [&](int x, int y, int qxi, int qyi, int ord) {
+    const bool ok = walk_block(w, b, s, qx, qy, total,
+                               [&](int x, int y, int qxi, int qyi, int tag, bool valid) {
                                  const uint32_t d2 = d2_32(x, y, qxi, qyi);
-                                 const uint32_t kk = ((d2 >> sh) << 8) | static_cast<uint32_t>(ord);
-                                 net_insert(key, (d2 <= r32 && kk > last) ? kk : kKey32Inf);
+                                 const uint32_t kk = ((d2 >> sh) << 13) | static_cast<uint32_t>(tag);
+                                 net_insert(key, (valid && d2 <= r32 && kk > last) ? kk : kKey32Inf);
                                });
-    if (!ok || ncand > 255 || rc2 >= bound || key[kChunk - 1] == kKey32Inf) return false;
+    if (!ok || key[kChunk - 1] == kKey32Inf) return false;
     bool good = prev_d == 0xFFFFFFFFu || key32_d(key[kChunk - need]) != prev_d;
 #pragma unroll
     for (int t = 0; t < kChunk - 1; ++t)
       if (t >= kChunk - need) good = good && key32_d(key[t]) != key32_d(key[t + 1]);
     if (!good) return false;
 #pragma unroll
-    for (int t = 0; t < kChunk; ++t)
-      if (t >= kChunk - need) out[written + t - (kChunk - need)] = w.sorted[seg_slot(sg, key32_ord(key[t]))].z;
+    for (int t = 0; t < kChunk; ++t) {
+      if (t >= kChunk - need) {
+        const int slot = tag_slot(w, b, key[t] & 0x1FFFu, qx, qy);
+        if (static_cast<uint32_t>(slot) >= static_cast<uint32_t>(total)) return false;
+        out[written + t - (kChunk - need)] = w.sorted[slot].z;
+      }
+    }
     written += need;
     last = key[kChunk - 1];
     prev_d = key32_d(last);
@@ -153,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_metric_fill(DevWs w, FastCfg f, long
     return;
   }
   int32_t* out = idx + base;
-  if (m == 0 || (f.B > 0 && fill_fast(w, f, s, q.x, q.y, rc2, total, m, out))) return;
+  if (m == 0 || (f.bfix > 0 && fill_fast(w, f, s, q.x, q.y, rc2, total, m, out))) return;
   long long written = 0;
   unsigned long long last = 0ull;  // every real key is >= 1
   while (written < m) {
@@ -177,21 +183,15 @@ __global__ __launch_bounds__(kBlock) void k_metric_fill(DevWs w, FastCfg f, long
 }
 
 // Block of odd side B centred on the home cell that contains the disk of
-// radius r_c for every query: (B - 1) / 2 cells >= r_c + 1.
+// radius r_c for every query: (B - 1) / 2 cells >= r_c + 1, within the limits
+// of the k-NN fast path.
 FastCfg metric_cfg(const DevWs& w, long long rc2) {
-  FastCfg f{0, 0};
+  const FastCfg lim = fast_cfg(w, 1, 0);
   const double rc = sqrt(static_cast<double>(rc2));
   const int cw = 1 << w.log2_w;
-  const int half = static_cast<int>(ceil((rc + 1.0) / cw));
-  const int B = 2 * half + 1;
-  if (B > kMaxB || B + 2 > w.G) return f;
-  const long long ext = static_cast<long long>(half + 1) * cw;
-  if (ext >= 32768) return f;
-  int sh = 0;
-  while ((rc2 >> sh) >= (1ll << 24) - 1) ++sh;
-  f.B = B;
-  f.sh = sh;
-  return f;
+  const int B = 2 * static_cast<int>(ceil((rc + 1.0) / cw)) + 1;
+  if (lim.bmax == 0 || B > lim.bmax) return FastCfg{0, 0, 0.0f};
+  return FastCfg{lim.bmax, B, 0.0f};
 }
 
 }  // namespace

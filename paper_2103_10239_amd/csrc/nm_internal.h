@@ -8,7 +8,11 @@
 //   start       int32[C + 1] first cell-ordered slot of each cell
 //   rank        int32[n]     slot of each particle inside its cell
 //   sorted      int4[n]      cell-ordered (x, y, particle index, noise word)
-//   cs          double2[n]   cell-ordered (cos theta, sin theta), fused step only
+//   cs          double2[2n]  cell-ordered (cos theta, sin theta) and (cos phi, sin phi)
+//                            of the noise, fused step only
+//   queue       int32[n]     slots whose k-NN search is deferred to the exact kernel,
+//                            stored in their tile's own slot range
+//   qcnt        int32[C]     number of deferred queries of each k-NN tile
 // C = G^2 cells, G = L / w.  Cells are numbered row-major: c = cy * G + cx.
 #pragma once
 
@@ -34,7 +38,9 @@ struct WsHeader {
   int32_t err;
   int32_t n, box, cell_w;
   uint32_t built;
-  int32_t pad[58];
+  uint32_t qcount;  // queries deferred to the exact k-NN search
+  uint32_t qdone;   // blocks of the exact-search kernel that have finished
+  int32_t pad[56];
 };
 static_assert(sizeof(WsHeader) == 256, "header is one 256-byte block");
 
@@ -54,6 +60,8 @@ struct DevWs {
   int32_t* rank;
   int4* sorted;
   double2* cs;
+  int32_t* queue;
+  int32_t* qcnt;
   int32_t n;
   int32_t box;
   int32_t cell_w;
@@ -66,7 +74,8 @@ struct DevWs {
 };
 
 struct Layout {
-  int64_t off_scan_c, off_scan_m, off_count, off_start, off_rank, off_sorted, off_cs, total;
+  int64_t off_scan_c, off_scan_m, off_count, off_start, off_rank, off_sorted, off_cs, off_queue, off_qcnt,
+      total;
   int32_t log2_box, log2_w, G, nb_scan_c, nb_scan_m;
   int64_t C;
 };
@@ -136,6 +145,18 @@ __device__ __forceinline__ double noise_angle(uint32_t u) {
   const double unit = static_cast<double>(u) * 0x1p-32;  // exact
   const double turn = unit * 6.283185307179586;           // fp64(2 pi)
   return turn - 3.141592653589793;                        // fp64(pi)
+}
+
+// Direction of the alignment vector (vx, vy) as an fp32 angle: the vector is
+// rescaled exactly by a power of two into [1/2, 1) and then rounded to fp32
+// for atan2f, so the angle moves by under 2^-23 rad plus atan2f's own error.
+// The zero vector keeps `keep` (the normaliser of Eq. (2) is undefined there).
+__device__ __forceinline__ float vec_angle(double vx, double vy, float keep) {
+  const double mx = fmax(fabs(vx), fabs(vy));
+  if (mx == 0.0) return keep;
+  int ex;
+  frexp(mx, &ex);
+  return atan2f(static_cast<float>(ldexp(vy, -ex)), static_cast<float>(ldexp(vx, -ex)));
 }
 
 // ---------------------------------------------------------------------------
@@ -241,34 +262,27 @@ struct QueryGeom {
 };
 
 // ---------------------------------------------------------------------------
-// Fast-path search block.  A B x B block of cells chosen around the query:
-// for odd B centred on its home cell, for even B shifted toward the half of
-// the home cell that holds the query, so the query sits near the block
-// centre.  Each of the B cell rows is one contiguous range of cell-ordered
-// slots (the block may wrap around the box in y, not in x); the home row is
-// split around the query's own slot.  Candidates get 32-bit keys
-//   (d^2 >> sh) << 8 | ordinal,   ordinal = 1 + position in the scan,
-// and every candidate goes through a branch-free insertion network.  The
-// result is exact, and is used, when the block holds fewer than 255
-// candidates, the k+1 smallest keys have distinct d^2 >> sh fields, and the
-// k-th squared distance is strictly below the squared distance from the
-// query to the nearest cell outside the block.  Otherwise the caller runs the
-// exact ring search.
+// Fast-path search block.  A B x B block of cells around the query: for odd
+// B centred on its home cell, for even B shifted toward the half of the home
+// cell that holds the query, so that the query is at least (B - 1) / 2 cell
+// widths from every cell outside.  Each block row is one contiguous range of
+// cell-ordered slots, or two where the row wraps around the box in x; range
+// 2r + part covers part `part` of block row r.  Candidates get 32-bit keys
+//   (min(d^2, bound) >> sh) << 13 | range << 8 | offset in the range,
+// pushed through a branch-free insertion network; a neighbour's slot is
+// start[first cell of its range] + offset.  The result is used only when
+// certified exact: every range shorter than 256, the k+1 smallest keys with
+// distinct distance fields, and the k-th squared distance strictly below the
+// squared distance from the query to the nearest cell outside the block.
 // ---------------------------------------------------------------------------
-constexpr int kMaxB = 8;
-constexpr int kMaxSeg = kMaxB + 1;
+constexpr int kMaxB = 15;  // 2 * kMaxB ranges fit the 5-bit range field
 constexpr uint32_t kKey32Inf = 0xFFFFFFFFu;
+constexpr int kDBits = 19;  // distance field of a 32-bit key
 
 struct FastCfg {
-  int B;   // block side in cells; 0 disables the fast path
-  int sh;  // right shift of d^2 so that every block distance fits 24 bits
-};
-
-// Segment r holds block row r; segment kMaxB holds the part of the home row
-// after the query's own slot.  Unused segments have cum = INT_MAX.
-struct BlockSegs {
-  int beg[kMaxSeg];  // first slot of each scanned range
-  int cum[kMaxSeg];  // ordinal of that range's first candidate
+  int bmax;    // largest block side (0 disables the fast path)
+  int bfix;    // fixed block side, or 0 to pick it per query from density
+  float reach; // distance to the block edge, in mean k-th-neighbour radii
 };
 
 __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
@@ -286,83 +300,126 @@ __device__ __forceinline__ void net_insert(uint32_t (&key)[KT], uint32_t kk) {
   key[0] = min(key[0], kk);
 }
 
-__device__ __forceinline__ uint32_t key32_d(uint32_t kk) { return kk >> 8; }
-__device__ __forceinline__ int key32_ord(uint32_t kk) { return static_cast<int>(kk & 0xFFu); }
+__device__ __forceinline__ uint32_t key32_d(uint32_t kk) { return kk >> 13; }
 
-// Slot of the candidate with scan ordinal `ord` (1-based): it lies in the
-// segment with the largest first ordinal not above `ord`.
-__device__ __forceinline__ int seg_slot(const BlockSegs& b, int ord) {
-  int slot = -1, best = 0;
-#pragma unroll
-  for (int i = 0; i < kMaxSeg; ++i) {
-    if (ord >= b.cum[i] && b.cum[i] >= best) {
-      best = b.cum[i];
-      slot = b.beg[i] + (ord - b.cum[i]);
-    }
-  }
-  return slot;
+// Geometry of one query's block.
+struct QBlock {
+  int hx, hy, lo_x, lo_y, B, sh;
+  long long bound;  // squared distance to the nearest cell outside the block
+};
+
+__device__ __forceinline__ QBlock make_qblock(const DevWs& w, int qx, int qy, int B) {
+  QBlock b;
+  const int cw = 1 << w.log2_w;
+  b.hx = qx >> w.log2_w;
+  b.hy = qy >> w.log2_w;
+  const int ox = qx & (cw - 1), oy = qy & (cw - 1);
+  const int half = B >> 1;
+  b.lo_x = (B & 1) ? -half : -half + (ox >= (cw >> 1) ? 1 : 0);
+  b.lo_y = (B & 1) ? -half : -half + (oy >= (cw >> 1) ? 1 : 0);
+  b.B = B;
+  const int hi_x = b.lo_x + B - 1, hi_y = b.lo_y + B - 1;
+  const int gl = ox - b.lo_x * cw + 1, gr = (hi_x + 1) * cw - ox;
+  const int gd = oy - b.lo_y * cw + 1, gu = (hi_y + 1) * cw - oy;
+  const long long m = min(min(gl, gr), min(gd, gu));
+  b.bound = m * m;
+  const int bits = 64 - __clzll(b.bound);
+  b.sh = bits > kDBits ? bits - kDBits : 0;
+  return b;
 }
 
-// Scan the fast-path block of query (slot s, position qx, qy).  Runs `visit`
-// on every candidate as visit(x, y, qx_image, qy_image, ordinal).  Returns
-// false if the block wraps in x (the caller then uses the exact search);
-// `bound` receives the squared distance to the nearest cell outside.
+// Cell range of part `part` (0 or 1) of block row r: first cell index, cell
+// count (0 if the part is empty), and the query's x / y in that range's image.
+struct RangeGeom {
+  int64_t cell0;
+  int ncell;
+  int qx, qy;
+};
+
+__device__ __forceinline__ RangeGeom range_geom(const DevWs& w, const QBlock& b, int r, int part,
+                                                int qx, int qy) {
+  const int G = w.G, L = w.box;
+  RangeGeom g;
+  int cy = b.hy + b.lo_y + r;
+  g.qy = qy;
+  if (cy < 0) {
+    cy += G;
+    g.qy = qy + L;
+  } else if (cy >= G) {
+    cy -= G;
+    g.qy = qy - L;
+  }
+  const int c0 = b.hx + b.lo_x, c1 = b.hx + b.lo_x + b.B - 1;
+  int a, e;
+  g.qx = qx;
+  if (c0 < 0) {  // part 0: the wrapped cells on the right edge, part 1: from column 0
+    if (part == 0) {
+      a = c0 + G;
+      e = G - 1;
+      g.qx = qx + L;
+    } else {
+      a = 0;
+      e = c1;
+    }
+  } else if (c1 >= G) {  // part 0: up to the right edge, part 1: wrapped from column 0
+    if (part == 0) {
+      a = c0;
+      e = G - 1;
+    } else {
+      a = 0;
+      e = c1 - G;
+      g.qx = qx - L;
+    }
+  } else {
+    a = c0;
+    e = part == 0 ? c1 : c0 - 1;
+  }
+  g.cell0 = static_cast<int64_t>(cy) * G + a;
+  g.ncell = e - a + 1;
+  return g;
+}
+
+// Walk the block's candidates.  visit(x, y, qx_image, qy_image, tag, valid)
+// gets tag = range << 8 | offset; pairs of candidates are loaded together
+// (the second clamped into the range, arriving with valid = false when it is
+// padding).  Returns false if a range is too long for the 8-bit offset.
 template <class Visit>
-__device__ __forceinline__ bool scan_block(const DevWs& w, const FastCfg& f, int s, int qx, int qy,
-                                           int total, BlockSegs& sg, long long& bound, int& ncand,
-                                           Visit&& visit) {
-  const int G = w.G, L = w.box, cw = 1 << w.log2_w;
-  const int hx = qx >> w.log2_w, hy = qy >> w.log2_w;
-  const int ox = qx & (cw - 1), oy = qy & (cw - 1);
-  const int half = f.B >> 1;
-  const int lo_x = (f.B & 1) ? -half : -half + (ox >= (cw >> 1) ? 1 : 0);
-  const int lo_y = (f.B & 1) ? -half : -half + (oy >= (cw >> 1) ? 1 : 0);
-  const int hi_x = lo_x + f.B - 1, hi_y = lo_y + f.B - 1;
-  if (hx + lo_x < 0 || hx + hi_x >= G) return false;
-  const int gl = ox - lo_x * cw + 1, gr = (hi_x + 1) * cw - ox;
-  const int gd = oy - lo_y * cw + 1, gu = (hi_y + 1) * cw - oy;
-  const long long m = min(min(gl, gr), min(gd, gu));
-  bound = m * m;
+__device__ __forceinline__ bool walk_block(const DevWs& w, const QBlock& b, int s, int qx, int qy,
+                                           int total, Visit&& visit) {
   const int2* pos = reinterpret_cast<const int2*>(w.sorted);
-  int ord = 1;
-  sg.beg[kMaxB] = 0;
-  sg.cum[kMaxB] = 0x7FFFFFFF;
-#pragma unroll
-  for (int r = 0; r < kMaxB; ++r) {
-    sg.beg[r] = 0;
-    sg.cum[r] = 0x7FFFFFFF;
-    if (r < f.B) {
-      int cy = hy + lo_y + r, sy = qy;
-      if (cy < 0) {
-        cy += G;
-        sy = qy + L;
-      } else if (cy >= G) {
-        cy -= G;
-        sy = qy - L;
-      }
-      const int64_t row = static_cast<int64_t>(cy) * G + hx;
-      const int a = w.start[row + lo_x];
-      const int e = min(w.start[row + hi_x + 1], total);
-      const bool home = (lo_y + r) == 0;
-      const int e1 = home ? s : e;  // the home row is scanned as [a, s) and (s, e)
-      sg.beg[r] = a;
-      sg.cum[r] = ord;
-      for (int t = a; t < e1; ++t, ++ord) {
-        const int2 p = pos[2 * t];
-        visit(p.x, p.y, qx, sy, ord);
-      }
-      if (home) {
-        sg.beg[kMaxB] = s + 1;
-        sg.cum[kMaxB] = ord;
-        for (int t = s + 1; t < e; ++t, ++ord) {
-          const int2 p = pos[2 * t];
-          visit(p.x, p.y, qx, sy, ord);
+  bool ok = true;
+  for (int r = 0; r < b.B; ++r) {
+    for (int part = 0; part < 2; ++part) {
+      const RangeGeom g = range_geom(w, b, r, part, qx, qy);
+      if (g.ncell <= 0) continue;
+      const int a = w.start[g.cell0];
+      const int e = min(w.start[g.cell0 + g.ncell], total);
+      if (e - a > 256) ok = false;
+      const int tag0 = ((2 * r + part) << 8) - a;  // tag of slot t is tag0 + t
+      auto run = [&](int t0, int t1) {
+        for (int t = t0; t < t1; t += 2) {
+          const int u = min(t + 1, t1 - 1);
+          const int2 p0 = pos[2 * t], p1 = pos[2 * u];
+          visit(p0.x, p0.y, g.qx, g.qy, tag0 + t, true);
+          visit(p1.x, p1.y, g.qx, g.qy, tag0 + u, t + 1 < t1);
         }
+      };
+      if (s >= a && s < e) {  // the query's own range: skip its slot
+        run(a, s);
+        run(s + 1, e);
+      } else {
+        run(a, e);
       }
     }
   }
-  ncand = ord - 1;
-  return true;
+  return ok;
+}
+
+// Slot of the candidate with tag `tag` in block b.
+__device__ __forceinline__ int tag_slot(const DevWs& w, const QBlock& b, uint32_t tag, int qx, int qy) {
+  const int rid = static_cast<int>((tag >> 8) & 31u);
+  const RangeGeom g = range_geom(w, b, rid >> 1, rid & 1, qx, qy);
+  return w.start[g.cell0] + static_cast<int>(tag & 255u);
 }
 
 // Host-side helpers (abi.hip).// Host-side helpers (abi.hip).

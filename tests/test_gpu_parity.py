@@ -378,3 +378,18 @@ def test_metric_fast_block_matches_oracle(kind, n, mean, w):
     offs, idx = _gpu_metric(x, y, rc2, w)
     ro, ri, _ = oracle.metric_list(x, y, L, rc2)
     assert np.array_equal(offs, ro) and np.array_equal(idx, ri)
+
+
+def test_knn_fast_path_query_last_in_home_row():
+    # Particle 0 is the only particle in its block row, so both parts of its home
+    # row around its own slot are empty; its nearest neighbour (1) lies in the next
+    # block row, and particle 2 (same cell row, far outside the block) sits between
+    # them in cell order.  The ordinal -> slot map must skip the empty ranges.
+    w = 4096
+    x = [100 * w + 2048, 100 * w + 2048, 200 * w + 5, 30 * w]
+    y = [100 * w + 4000, 101 * w + 104, 100 * w + 7, 30 * w]
+    for block in (3, 4, 0):
+        nbr, d2 = _gpu_knn_block(x, y, 1, w, block)
+        rn, rd = oracle.knn(x, y, L, 1)
+        assert np.array_equal(nbr, rn) and np.array_equal(d2, rd)
+        assert nbr[0, 0] == 1
