@@ -69,6 +69,8 @@ bool make_layout(const nm_grid* g, Layout* out) {
   off += round_up(4 * static_cast<int64_t>(g->n));
   L.off_qcnt = off;
   off += round_up(4 * L.C);
+  L.off_dflag = off;
+  off += round_up(static_cast<int64_t>(g->n));
   L.total = off;
   *out = L;
   return true;
@@ -87,6 +89,7 @@ DevWs dev_ws(const nm_grid* g, const Layout& lay, void* ws) {
   w.cs = reinterpret_cast<double2*>(b + lay.off_cs);
   w.queue = reinterpret_cast<int32_t*>(b + lay.off_queue);
   w.qcnt = reinterpret_cast<int32_t*>(b + lay.off_qcnt);
+  w.dflag = reinterpret_cast<uint8_t*>(b + lay.off_dflag);
   w.n = g->n;
   w.box = g->box;
   w.cell_w = g->cell_w;

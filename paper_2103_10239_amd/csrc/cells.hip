@@ -30,6 +30,8 @@ __global__ __launch_bounds__(kBlock) void k_ws_init(DevWs w) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < w.C; c += stride)
     w.count[c] = 0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < w.n; i += stride)
+    w.dflag[i] = 0;
   if (blockIdx.x == 0) {
     reset_scan(w.scan_c, w.nb_scan_c);
     reset_scan(w.scan_m, w.nb_scan_m);

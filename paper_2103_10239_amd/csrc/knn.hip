@@ -244,43 +244,53 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
 }
 
 // ---------------------------------------------------------------------------
-// Tiles.  A workgroup owns `tc` consecutive cells of one cell row; its queries
-// (the particles of those cells) are one contiguous range of cell-ordered
-// slots.  It stages the halo of (2h + 1) x (tc + 2h) cells around the tile
-// into LDS -- the cell start table and every particle's position, shifted
-// into the tile's periodic image -- and each lane then runs the block search
-// on LDS only.  A tile whose halo holds more than kTilePts particles (a dense
-// cluster) searches global memory instead.  Queries that are not certified go
-// to the tile's segment of the queue for the exact kernel.
+// Tiles.  A workgroup owns a T x T square of cells (about 256 queries).  It
+// stages the halo of (T + 2h)^2 cells around the tile into LDS: the cell start
+// table, and every particle's position in the tile's periodic image, stored
+// as a pair of 16-bit offsets from the halo's corner (the halo spans fewer
+// than 2^15 grid units), so that a squared distance is one packed subtract
+// and one 16-bit dot product.  Each lane then runs the certified block search
+// of one query on LDS only.  A tile whose halo holds more than kTilePts
+// particles searches global memory instead.  Uncertified queries are flagged
+// for the exact kernel.
 // ---------------------------------------------------------------------------
-constexpr int kTileCells = 2048;
-constexpr int kTilePts = 2048;
+constexpr int kTileCells = 1024;  // (T + 2h)^2 <= kTileCells
+constexpr int kTilePts = 3072;    // staged particles
+constexpr int kTileRows = 32;     // T + 2h <= kTileRows
+
+typedef short short2v __attribute__((ext_vector_type(2)));
 
 struct TileCfg {
-  int tc;    // tile width in cells
+  int t;     // tile side in cells
   int h;     // halo in cells (0: no staging)
-  int ntx;   // tiles per cell row
+  int ntx;   // tiles per side
   int bmax;  // largest block side the halo supports
 };
 
-__device__ __forceinline__ int tile_index(int b, int nb) { return xcd_tile(b, nb); }
+__device__ __forceinline__ int rel_d2(int packed_c, int packed_q) {
+  const short2v d = __builtin_bit_cast(short2v, packed_c) - __builtin_bit_cast(short2v, packed_q);
+  return __builtin_amdgcn_sdot2(d, d, 0, false);
+}
 
-// Block search on the staged tile.  jh: home column in staged coordinates,
-// self: the query's LDS index.
+__device__ __forceinline__ int pack_rel(int rx, int ry) {
+  return (rx & 0xFFFF) | (ry << 16);
+}
+
+// Block search on the staged tile.  (cx, cy): home cell in halo coordinates,
+// self: the query's LDS index, pq: its packed relative position.
 template <int KMAX>
 __device__ __forceinline__ bool knn_lds(const DevWs& w, const FastCfg& f, const TileCfg& tc,
-                                        const int* lcell, const int2* lpos, const int* lslot, int W,
-                                        int jh, int self, int qx, int qy, int k, int (&slot)[KMAX]) {
+                                        const int* lcell, const int* lpos, const int* lslot, int W,
+                                        int cx, int cy, int self, int pq, int qx, int qy, int k,
+                                        int (&slot)[KMAX]) {
   constexpr int KT = KMAX + 1;
-  const int h = tc.h;
   int B = f.bfix;
   if (B == 0) {
     int n9 = 0;
 #pragma unroll
-    for (int dr = -1; dr <= 1; ++dr) n9 += lcell[(h + dr) * W + jh + 2] - lcell[(h + dr) * W + jh - 1];
+    for (int dr = -1; dr <= 1; ++dr) n9 += lcell[(cy + dr) * W + cx + 2] - lcell[(cy + dr) * W + cx - 1];
     const float rk = sqrtf(static_cast<float>(k) * 9.0f / (3.14159265f * fmaxf(static_cast<float>(n9), 0.5f)));
-    B = static_cast<int>(ceilf(2.0f * f.reach * rk)) + 1;
-    B = max(B, 3);
+    B = max(static_cast<int>(ceilf(2.0f * f.reach * rk)) + 1, 3);
   }
   if (B > tc.bmax) return false;
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -294,8 +304,7 @@ __device__ __forceinline__ bool knn_lds(const DevWs& w, const FastCfg& f, const 
     // every candidate of every row (the row switch is a predicated update), so
     // a wavefront runs as many iterations as its longest query, not as the sum
     // of its longest rows.  The query itself gets the key INF.
-    const int j0 = jh + b.lo_x;
-    const int row0 = (h + b.lo_y) * W + j0;
+    const int row0 = (cy + b.lo_y) * W + cx + b.lo_x;
     int ncand = 0;
     for (int r = 0; r < B; ++r) ncand += lcell[row0 + r * W + B] - lcell[row0 + r * W];
     int r = 0, i = lcell[row0], e = lcell[row0 + B];
@@ -304,20 +313,17 @@ __device__ __forceinline__ bool knn_lds(const DevWs& w, const FastCfg& f, const 
       i = lcell[row0 + r * W];
       e = lcell[row0 + r * W + B];
     }
-    int2 p = lpos[min(i, kTilePts - 1)];  // (no candidate at all: a harmless in-bounds read)
+    int pc = lpos[min(i, kTilePts - 1)];  // (no candidate at all: a harmless in-bounds read)
     for (int c = 0; c < ncand; ++c) {
-      const int icur = i;
-      const int2 pc = p;
-      // advance to the next candidate (next row when this one is exhausted)
+      const int icur = i, pcur = pc;
       ++i;
       while (i == e && r + 1 < B) {
         ++r;
         i = lcell[row0 + r * W];
         e = lcell[row0 + r * W + B];
       }
-      p = lpos[min(i, kTilePts - 1)];
-      const int dx = pc.x - qx, dy = pc.y - qy;
-      const uint32_t d2 = static_cast<uint32_t>(__mul24(dx, dx)) + static_cast<uint32_t>(__mul24(dy, dy));
+      pc = lpos[min(i, kTilePts - 1)];
+      const uint32_t d2 = static_cast<uint32_t>(rel_d2(pcur, pq));
       const uint32_t kk = ((min(d2, clampd) >> sh) << 13) | static_cast<uint32_t>(icur);
       net_insert(key, icur == self ? kKey32Inf : kk);
     }
@@ -344,116 +350,160 @@ __device__ __forceinline__ bool knn_lds(const DevWs& w, const FastCfg& f, const 
   return false;
 }
 
+// Cells of tile `tile`: columns [x0, x0 + tx), rows [y0, y0 + ty).
+struct TileBox {
+  int x0, y0, tx, ty;
+};
+
+__device__ __forceinline__ TileBox tile_box(const DevWs& w, const TileCfg& tc, int tile) {
+  TileBox b;
+  const int tyi = tile / tc.ntx, txi = tile - tyi * tc.ntx;
+  b.x0 = txi * tc.t;
+  b.y0 = tyi * tc.t;
+  b.tx = min(tc.t, w.G - b.x0);
+  b.ty = min(tc.t, w.G - b.y0);
+  return b;
+}
+
 template <int KMAX, bool kAlign>
 __global__ __launch_bounds__(kBlock) void k_knn(DevWs w, FastCfg f, TileCfg tc, int k,
                                                 int32_t* __restrict__ nbr,
                                                 long long* __restrict__ d2out, AlignArgs a) {
   __shared__ int lcell[kTileCells + 1];
-  __shared__ int2 lpos[kTilePts];
+  __shared__ int lpos[kTilePts];
   __shared__ int lslot[kTilePts];
-  __shared__ int s_part[kBlock / 64];
+  __shared__ int s_qoff[kTileRows + 1];   // query prefix over the tile's rows
+  __shared__ int s_qbeg[kTileRows];       // first slot of each tile row
+  __shared__ int s_rbase[kTileRows + 1];  // LDS offset of each halo row
+  // Each halo row is up to three physically contiguous pieces (it may wrap
+  // around the box in x): first unwrapped column, first slot, LDS offset
+  // within the row, and image shift of x.
+  __shared__ int s_pu[kTileRows][3];
+  __shared__ int s_pga[kTileRows][3];
+  __shared__ int s_plo[kTileRows][4];
+  __shared__ int s_psx[kTileRows][3];
   __shared__ int s_defer;
   if (!ws_ready(w)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) set_err(w.hdr, NM_E_INVAL);
     return;
   }
-  const int tile = tile_index(blockIdx.x, gridDim.x);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const TileBox tb = tile_box(w, tc, tile);
   const int G = w.G, L = w.box, gm = G - 1;
-  const int ty = tile / tc.ntx, tx0 = (tile - ty * tc.ntx) * tc.tc;
-  const int tce = min(tc.tc, G - tx0);
   const int total = min(w.start[w.C], w.n);
-  const int64_t rowbase = static_cast<int64_t>(ty) * G;
-  const int q_beg = w.start[rowbase + tx0];
-  const int q_end = min(w.start[rowbase + tx0 + tce], total);
-  if (q_beg >= q_end) {
+  const int h = tc.h, W = tb.tx + 2 * h, R = tb.ty + 2 * h;
+  const int uL = tb.x0 - h, uR = tb.x0 + tb.tx + h - 1;
+  const int lane = threadIdx.x & 63;
+  const int ox0 = uL << w.log2_w, oy0 = (tb.y0 - h) << w.log2_w;  // halo corner (tile image)
+
+  // Wave 0: query rows of the tile, and the pieces and length of each halo row.
+  if (threadIdx.x < 64) {
+    int qlen = 0, rlen = 0;
+    if (lane < tb.ty) {
+      const int64_t row = static_cast<int64_t>(tb.y0 + lane) * G;
+      const int a0 = w.start[row + tb.x0];
+      s_qbeg[lane] = a0;
+      qlen = max(min(w.start[row + tb.x0 + tb.tx], total) - a0, 0);
+    }
+    if (h > 0 && lane < R) {
+      const int64_t prow = static_cast<int64_t>((tb.y0 - h + lane) & gm) * G;
+      int np = 0;
+      for (int p0 = uL; p0 <= uR && np < 3; ++np) {
+        const int p1 = p0 < 0 ? min(uR, -1) : (p0 < G ? min(uR, G - 1) : uR);
+        const int ga = w.start[prow + (p0 & gm)];
+        s_pu[lane][np] = p0;
+        s_pga[lane][np] = ga;
+        s_plo[lane][np] = rlen;
+        s_psx[lane][np] = (p0 < 0 ? -L : (p0 >= G ? L : 0)) - ox0;
+        rlen += w.start[prow + (p1 & gm) + 1] - ga;
+        p0 = p1 + 1;
+      }
+      for (int q = np; q < 3; ++q) {
+        s_pu[lane][q] = 0x7FFFFFFF;
+        s_pga[lane][q] = 0;
+        s_plo[lane][q] = rlen;
+        s_psx[lane][q] = 0;
+      }
+      s_plo[lane][3] = rlen;
+    }
+    int qi = qlen, ri = rlen;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t1 = __shfl_up(qi, off, 64), t2 = __shfl_up(ri, off, 64);
+      if (lane >= off) {
+        qi += t1;
+        ri += t2;
+      }
+    }
+    if (lane <= kTileRows) {
+      if (lane <= tb.ty) s_qoff[lane] = qi - qlen;
+      if (lane <= R) s_rbase[lane] = ri - rlen;
+    }
+    if (lane == 0) s_defer = 0;
+  }
+  __syncthreads();
+  const int nq = s_qoff[tb.ty];
+  if (nq == 0) {
     if (threadIdx.x == 0) w.qcnt[tile] = 0;
     return;
   }
-  const int h = tc.h, W = tce + 2 * h, R = 2 * h + 1, ncells = R * W;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_defer = 0;
-  __syncthreads();  // s_defer is live before any lane can defer a query
-  bool staged = h > 0 && ncells <= kTileCells;
+  const bool staged = h > 0 && s_rbase[R] <= kTilePts;
   if (staged) {
-    // Cell counts of the halo, row-major over (rho, j), prefix-summed into lcell.
-    constexpr int kPer = (kTileCells + kBlock - 1) / kBlock;
-    const int c0 = threadIdx.x * kPer;
-    int cnt[kPer];
-    int sum = 0;
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      cnt[i] = 0;
-      const int c = c0 + i;
-      if (c < ncells) {
-        const int rho = c / W, j = c - rho * W;
-        const int64_t cell = static_cast<int64_t>((ty - h + rho) & gm) * G + ((tx0 - h + j) & gm);
-        cnt[i] = w.start[cell + 1] - w.start[cell];
+    // Cell table: LDS offset of every halo cell, from the start table.
+    for (int c = threadIdx.x; c <= R * W; c += kBlock) {
+      if (c == R * W) {
+        lcell[c] = s_rbase[R];
+        continue;
       }
-      sum += cnt[i];
+      const int rho = c / W, u = uL + (c - rho * W);
+      const int pi = (u >= s_pu[rho][2]) ? 2 : ((u >= s_pu[rho][1]) ? 1 : 0);
+      const int64_t cell = static_cast<int64_t>((tb.y0 - h + rho) & gm) * G + (u & gm);
+      lcell[c] = s_rbase[rho] + s_plo[rho][pi] + (w.start[cell] - s_pga[rho][pi]);
     }
-    int incl = sum;
+    // Particles as packed 16-bit offsets from the halo corner, one per thread
+    // per round: find the halo row (binary search over the row offsets) and
+    // the piece, then the source slot.
+    const int npts = s_rbase[R];
+    for (int pidx = threadIdx.x; pidx < npts; pidx += kBlock) {
+      int rho = 0;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int t = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += t;
-    }
-    if (lane == 63) s_part[wave] = incl;
-    __syncthreads();
-    int run = incl - sum, grand = 0;
-#pragma unroll
-    for (int q = 0; q < kBlock / 64; ++q) {
-      if (q < wave) run += s_part[q];
-      grand += s_part[q];
-    }
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      if (c0 + i < ncells) lcell[c0 + i] = run;
-      run += cnt[i];
-    }
-    if (threadIdx.x == 0) lcell[ncells] = grand;
-    staged = grand <= kTilePts;
-    __syncthreads();
-    if (staged) {
-      // Copy each halo row as its (up to three) physically contiguous pieces.
-      for (int rho = 0; rho < R; ++rho) {
-        const int v = ty - h + rho;
-        const int sy = v < 0 ? -L : (v >= G ? L : 0);
-        const int64_t prow = static_cast<int64_t>(v & gm) * G;
-        const int uL = tx0 - h, uR = tx0 + tce + h - 1;
-        int p0 = uL;
-        while (p0 <= uR) {
-          const int p1 = p0 < 0 ? min(uR, -1) : (p0 < G ? min(uR, G - 1) : uR);
-          const int sx = p0 < 0 ? -L : (p0 >= G ? L : 0);
-          const int ga = w.start[prow + (p0 & gm)];
-          const int ge = w.start[prow + (p1 & gm) + 1];
-          const int lo = lcell[rho * W + (p0 - uL)];
-          for (int i = threadIdx.x; i < ge - ga; i += kBlock) {
-            const int4 e = w.sorted[ga + i];
-            lpos[lo + i] = make_int2(e.x + sx, e.y + sy);
-            lslot[lo + i] = ga + i;
-          }
-          p0 = p1 + 1;
-        }
-      }
+      for (int step = kTileRows / 2; step > 0; step >>= 1)
+        if (rho + step < R && s_rbase[rho + step] <= pidx) rho += step;
+      const int inrow = pidx - s_rbase[rho];
+      const int pi = (inrow >= s_plo[rho][2]) ? 2 : ((inrow >= s_plo[rho][1]) ? 1 : 0);
+      const int src = s_pga[rho][pi] + (inrow - s_plo[rho][pi]);
+      const int v = tb.y0 - h + rho;
+      const int sy = (v < 0 ? -L : (v >= G ? L : 0)) - oy0;
+      const int2 e = reinterpret_cast<const int2*>(w.sorted)[2 * src];
+      lpos[pidx] = pack_rel(e.x + s_psx[rho][pi], e.y + sy);
+      lslot[pidx] = src;
     }
     __syncthreads();
   }
 
-  const int lhome = staged ? lcell[h * W + h] : 0;
-  for (int s = q_beg + static_cast<int>(threadIdx.x); s < q_end; s += kBlock) {
+  for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
+    int rq = 0;  // tile row of query qi
+#pragma unroll
+    for (int step = kTileRows / 2; step > 0; step >>= 1)
+      if (rq + step < tb.ty && s_qoff[rq + step] <= qi) rq += step;
+    const int s = s_qbeg[rq] + (qi - s_qoff[rq]);
     const int4 q = w.sorted[s];
     int slot[KMAX];
     bool ok;
     if (staged) {
-      const int jh = (q.x >> w.log2_w) - tx0 + h;
-      ok = knn_lds<KMAX>(w, f, tc, lcell, lpos, lslot, W, jh, lhome + (s - q_beg), q.x, q.y, k, slot);
+      const int cx = (q.x >> w.log2_w) - uL, cy = rq + h;
+      const int64_t hc = static_cast<int64_t>(tb.y0 + rq) * G + (q.x >> w.log2_w);
+      const int self = lcell[cy * W + cx] + (s - w.start[hc]);
+      ok = knn_lds<KMAX>(w, f, tc, lcell, lpos, lslot, W, cx, cy, self,
+                         pack_rel(q.x - ox0, q.y - oy0), q.x, q.y, k, slot);
     } else {
       ok = knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot);
     }
     if (ok) {
       finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
     } else {
-      w.queue[q_beg + atomicAdd(&s_defer, 1)] = s;
+      w.dflag[s] = 1;
+      atomicAdd(&s_defer, 1);
     }
   }
   __syncthreads();
@@ -549,9 +599,11 @@ __device__ __forceinline__ bool knn_wave(const DevWs& w, int s, const int4& q, i
   return top.worst() != ~0ull;
 }
 
-// The deferred queries, tile by tile: a tile with many of them gives each
-// lane one (exact lane search); a tile with a few searches each with the whole
-// wavefront, so that a single long search is not one lane's serial chain.
+// The deferred queries, tile by tile (one wavefront per tile that has any):
+// the lanes walk the tile's slots for the flagged ones and clear the flags.
+// With many flagged, each lane searches its own (exact lane search); with a
+// few, the wavefront searches them one at a time, so that a single long
+// search is not one lane's serial chain.
 template <int KMAX, bool kAlign>
 __global__ __launch_bounds__(kBlock) void k_knn_rest(DevWs w, TileCfg tc, int ntiles, int k,
                                                      int32_t* __restrict__ nbr,
@@ -560,70 +612,83 @@ __global__ __launch_bounds__(kBlock) void k_knn_rest(DevWs w, TileCfg tc, int nt
   const int lane = threadIdx.x & 63;
   const int waves = gridDim.x * (kBlock / 64);
   const int total = min(w.start[w.C], w.n);
+  const int G = w.G;
   for (int tile = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); tile < ntiles; tile += waves) {
     const int cnt = w.qcnt[tile];
     if (cnt <= 0) continue;
-    const int ty = tile / tc.ntx, tx0 = (tile - ty * tc.ntx) * tc.tc;
-    const int base = w.start[static_cast<int64_t>(ty) * w.G + tx0];
-    if (cnt >= 16) {
-      for (int i = lane; i < cnt; i += 64) {
-        const int s = w.queue[base + i];
-        if (static_cast<uint32_t>(s) >= static_cast<uint32_t>(total)) continue;
-        const int4 q = w.sorted[s];
-        int slot[KMAX];
-        if (!knn_exact<KMAX>(w, s, q.x, q.y, k, total, slot)) {
-          set_err(w.hdr, NM_E_RANGE);  // fewer than k other particles were binned
-          continue;
-        }
-        finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
-      }
-    } else {
-      for (int i = 0; i < cnt; ++i) {
-        const int s = w.queue[base + i];
-        if (static_cast<uint32_t>(s) >= static_cast<uint32_t>(total)) continue;
-        const int4 q = w.sorted[s];
-        int slot[KMAX];
-        const bool ok = knn_wave<KMAX>(w, s, q, k, total, slot);
-        if (lane == 0) {
-          if (ok)
-            finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
-          else
-            set_err(w.hdr, NM_E_RANGE);
+    const TileBox tb = tile_box(w, tc, tile);
+    for (int r = 0; r < tb.ty; ++r) {
+      const int64_t row = static_cast<int64_t>(tb.y0 + r) * G;
+      const int a0 = w.start[row + tb.x0];
+      const int a1 = min(w.start[row + tb.x0 + tb.tx], total);
+      for (int base = a0; base < a1; base += 64) {
+        const int s = base + lane;
+        const bool mine = s < a1 && w.dflag[s];
+        if (mine) w.dflag[s] = 0;
+        if (cnt >= 16) {
+          if (mine) {
+            const int4 q = w.sorted[s];
+            int slot[KMAX];
+            if (knn_exact<KMAX>(w, s, q.x, q.y, k, total, slot))
+              finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
+            else
+              set_err(w.hdr, NM_E_RANGE);  // fewer than k other particles were binned
+          }
+        } else {
+          unsigned long long todo = __ballot(mine);
+          while (todo) {
+            const int l = __ffsll(static_cast<long long>(todo)) - 1;
+            todo &= todo - 1;
+            const int sq = __shfl(s, l, 64);
+            const int4 q = w.sorted[sq];
+            int slot[KMAX];
+            const bool ok = knn_wave<KMAX>(w, sq, q, k, total, slot);
+            if (lane == 0) {
+              if (ok)
+                finish_query<KMAX, kAlign>(w, sq, q, slot, k, nbr, d2out, a);
+              else
+                set_err(w.hdr, NM_E_RANGE);
+            }
+          }
         }
       }
     }
   }
 }
 
-// Tile geometry: a halo of h cells supports blocks up to 2h + 1 cells (the
-// staged frame is the minimum image while G >= 2h + 2); the tile width aims at
-// about 224 queries per tile and a halo of at most ~1800 particles at the mean
-// density.
-TileCfg tile_cfg(const DevWs& w, const FastCfg& f) {
+// Tile geometry.  The halo h holds the blocks a query is expected to use
+// (side ~ 2 * reach * r_k / w + 1, plus one widening step); the tile side aims
+// at about 256 queries; the halo must span under 2^15 grid units for the
+// 16-bit offsets, and must not meet itself around the box.
+TileCfg tile_cfg(const DevWs& w, const FastCfg& f, int k) {
   TileCfg t{1, 0, w.G, 0};
   const double rho = static_cast<double>(w.n) / static_cast<double>(w.C);  // particles per cell
-  int h = f.bmax > 0 ? min(4, (f.bmax + 1) / 2) : 0;
-  while (h > 0 && w.G < 2 * h + 2) --h;
-  int tc = static_cast<int>(224.0 / (rho > 1e-9 ? rho : 1e-9));
+  const double rk = sqrt(static_cast<double>(k) / (3.141592653589793 * (rho > 1e-12 ? rho : 1e-12)));
+  const int bexp = (f.bfix > 0 ? f.bfix : static_cast<int>(ceil(2.0 * f.reach * rk)) + 1) + 2;
+  int h = f.bmax > 0 ? min((bexp + 1) / 2, (f.bmax + 1) / 2) : 0;
+  while (h > 0 && (w.G < 2 * h + 2 || ((static_cast<long long>(2 * h + 1) << w.log2_w) > 32768))) --h;
+  int side = static_cast<int>(lround(sqrt(256.0 / (rho > 1e-12 ? rho : 1e-12))));
+  side = max(1, min(side, w.G));
   if (h > 0) {
-    const int R = 2 * h + 1;
-    const int by_cells = kTileCells / R - 2 * h;
-    const int by_pts = static_cast<int>(1800.0 / (R * (rho > 1e-9 ? rho : 1e-9))) - 2 * h;
-    tc = min(tc, min(by_cells, by_pts));
+    while (side > 1 && ((static_cast<long long>(side + 2 * h) << w.log2_w) > 32768 || side + 2 * h > kTileRows ||
+                        (side + 2 * h) * (side + 2 * h) > kTileCells ||
+                        (side + 2 * h) * (side + 2 * h) * rho > 0.75 * kTilePts))
+      --side;
+    if ((static_cast<long long>(side + 2 * h) << w.log2_w) > 32768 || side + 2 * h > kTileRows) h = 0;
   }
-  tc = max(1, min(tc, w.G));
-  t.tc = tc;
-  t.h = (h > 0 && (2 * h + 1) * (tc + 2 * h) <= kTileCells) ? h : 0;
-  t.ntx = (w.G + tc - 1) / tc;
-  t.bmax = t.h > 0 ? min(2 * t.h + 1, f.bmax) : 0;
+  if (h == 0) side = max(1, min(side, kTileRows));
+  t.t = side;
+  t.h = h;
+  t.ntx = (w.G + side - 1) / side;
+  t.bmax = h > 0 ? min(2 * h + 1, f.bmax) : 0;
   return t;
 }
 
 template <int KMAX, bool kAlign>
 hipError_t launch_t(const DevWs& w, const FastCfg& f, int k, int32_t* nbr, long long* d2,
                     const AlignArgs& a, hipStream_t s) {
-  const TileCfg tc = tile_cfg(w, f);
-  const int ntiles = w.G * tc.ntx;
+  const TileCfg tc = tile_cfg(w, f, k);
+  const int ntiles = tc.ntx * tc.ntx;
   hipLaunchKernelGGL((k_knn<KMAX, kAlign>), dim3(ntiles), dim3(kBlock), 0, s, w, f, tc, k, nbr, d2, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

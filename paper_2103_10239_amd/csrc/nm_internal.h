@@ -13,6 +13,8 @@
 //   queue       int32[n]     slots whose k-NN search is deferred to the exact kernel,
 //                            stored in their tile's own slot range
 //   qcnt        int32[C]     number of deferred queries of each k-NN tile
+//   dflag       uint8[n]     1 for a slot whose k-NN search is deferred (kept 0
+//                            between launches)
 // C = G^2 cells, G = L / w.  Cells are numbered row-major: c = cy * G + cx.
 #pragma once
 
@@ -62,6 +64,7 @@ struct DevWs {
   double2* cs;
   int32_t* queue;
   int32_t* qcnt;
+  uint8_t* dflag;
   int32_t n;
   int32_t box;
   int32_t cell_w;
@@ -75,7 +78,7 @@ struct DevWs {
 
 struct Layout {
   int64_t off_scan_c, off_scan_m, off_count, off_start, off_rank, off_sorted, off_cs, off_queue, off_qcnt,
-      total;
+      off_dflag, total;
   int32_t log2_box, log2_w, G, nb_scan_c, nb_scan_m;
   int64_t C;
 };
