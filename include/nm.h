@@ -182,6 +182,76 @@ int nm_knn_align(const nm_grid* g, const void* ws, int32_t k, const nm_params* p
  * last check (NM_OK if none) and clear it. */
 int nm_check(void* ws, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent systems of uneven size, all advanced by
+ * the step of nm_step (Alg. 1 with the k-NN rule, Eq. (2), Eq. (1)), one
+ * persistent launch per stage for the whole batch, the step replayable from
+ * a HIP graph.  Every system's lists, positions and headings are identical
+ * to those of nm_step on that system alone with the same parameters, the
+ * system's own sys_id and its own step count (the Philox stream is keyed by
+ * system, never by its place in the batch).
+ *
+ * State lives in caller-owned concatenated arrays: system s owns particles
+ * [offset_s, offset_s + n_s) (offsets are the prefix sums of n in system
+ * order) and list rows [offset_s * k, (offset_s + n_s) * k) of nbr.  The
+ * state is double-buffered: after a total of t steps since nm_batch_bind the
+ * current positions and headings are in buffer t mod 2.
+ * ------------------------------------------------------------------------ */
+#define NM_BATCH_MAX_SYS 65536
+
+typedef struct nm_batch nm_batch; /* host-side plan (opaque) */
+
+typedef struct nm_batch_io {
+  int32_t* x[2];     /* device, int32[total]: positions, buffers 0 and 1       */
+  int32_t* y[2];
+  float* theta[2];   /* device, fp32[total]: headings, buffers 0 and 1         */
+  int32_t* nbr;      /* device, int32[total * k]: the lists of the last step   */
+} nm_batch_io;
+
+/* Plan a batch: nsys systems with n[s] particles each (host array,
+ * k + 1 <= n[s] <= 2^24, total < 2^31) in boxes of side `box`, k nearest
+ * neighbours, step parameters p (p->box == box; p->sys_id is ignored) and
+ * per-system Philox identities sys_ids (host array, or NULL for 0..nsys-1).
+ * Returns the host plan in *out and the device workspace size in *ws_bytes.
+ * Allocates host memory only; free the plan with nm_batch_destroy. */
+int nm_batch_plan(int32_t nsys, const int32_t* n, int32_t box, int32_t k, const nm_params* p,
+                  const uint32_t* sys_ids, nm_batch** out, int64_t* ws_bytes);
+
+/* Attach device memory and state buffers to a plan: `ws` (256-byte aligned,
+ * at least *ws_bytes bytes) holds the per-system descriptors, the work-item
+ * tables and every system's workspace; io names the state arrays (buffer 0
+ * holds the initial state).  The next step of every system is `step0`.
+ * Uploads the tables and initialises the workspaces on `stream`, then
+ * synchronises it.  Rebinding resets the step count. */
+int nm_batch_bind(nm_batch* b, void* ws, size_t ws_bytes, const nm_batch_io* io, uint64_t step0,
+                  void* stream);
+
+/* Advance every system by nsteps steps.  use_graph = 1: the first call
+ * captures one step into a HIP graph (on a private stream) and every step is
+ * a launch of that graph on `stream`; 0: the stage kernels are launched
+ * directly.  Enqueues only; does not synchronise or allocate device memory. */
+int nm_batch_step(nm_batch* b, int32_t nsteps, int32_t use_graph, void* stream);
+
+/* Autotuner: for each size class (systems with equal floor(log2 n)), time
+ * `reps` steps of the class alone under each candidate cell width (about
+ * 0.5, 1, 2 and 4 particles per cell) and keep the fastest.  The tuning
+ * steps read the current state and write only the other buffer and nbr, and
+ * do not advance the step count.  Synchronises; drops the captured graph. */
+int nm_batch_tune(nm_batch* b, int32_t reps, void* stream);
+
+/* The grid chosen for system s (cell width, block) and its particle offset. */
+int nm_batch_system(const nm_batch* b, int32_t s, nm_grid* g, int32_t* offset);
+
+/* Steps taken since nm_batch_bind (the current state is in buffer
+ * nm_batch_steps_done(b) mod 2). */
+int64_t nm_batch_steps_done(const nm_batch* b);
+
+/* Synchronise `stream` and return the first error recorded by any system
+ * since the last check (then cleared), NM_OK if none. */
+int nm_batch_check(nm_batch* b, void* stream);
+
+void nm_batch_destroy(nm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

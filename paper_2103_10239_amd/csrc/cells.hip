@@ -26,13 +26,15 @@ __device__ void reset_scan(ScanState* st, int nb) {
   if (threadIdx.x == 0) st->ticket = 0u;
 }
 
-__global__ __launch_bounds__(kBlock) void k_ws_init(DevWs w) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < w.C; c += stride)
+// Zero the histogram and the deferral flags, reset the scan states and stamp
+// the header; workgroup `b` of `nb` takes a strided share.
+__device__ __forceinline__ void ws_init_body(const DevWs& w, int b, int nb) {
+  const int64_t stride = static_cast<int64_t>(nb) * blockDim.x;
+  for (int64_t c = static_cast<int64_t>(b) * blockDim.x + threadIdx.x; c < w.C; c += stride)
     w.count[c] = 0;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < w.n; i += stride)
+  for (int64_t i = static_cast<int64_t>(b) * blockDim.x + threadIdx.x; i < w.n; i += stride)
     w.dflag[i] = 0;
-  if (blockIdx.x == 0) {
+  if (b == 0) {
     reset_scan(w.scan_c, w.nb_scan_c);
     reset_scan(w.scan_m, w.nb_scan_m);
     if (threadIdx.x == 0) {
@@ -48,9 +50,14 @@ __global__ __launch_bounds__(kBlock) void k_ws_init(DevWs w) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* __restrict__ x,
-                                                      const int32_t* __restrict__ y, DevWs w) {
-  if (blockIdx.x == 0) {
+__global__ __launch_bounds__(kBlock) void k_ws_init(DevWs w) { ws_init_body(w, blockIdx.x, gridDim.x); }
+
+// Cell and in-cell rank of the particles of workgroup `b`; workgroup 0 also
+// resets the scan state for the following prefix sum.
+__device__ __forceinline__ void bin_count_body(const int32_t* __restrict__ x,
+                                               const int32_t* __restrict__ y, const DevWs& w,
+                                               int b) {
+  if (b == 0) {
     reset_scan(w.scan_c, w.nb_scan_c);
     if (threadIdx.x == 0) {
       if (w.hdr->magic != kMagic || w.hdr->n != w.n || w.hdr->box != w.box ||
@@ -59,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* __restrict_
       w.hdr->built = 0u;
     }
   }
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = b * kBlock + threadIdx.x;
   if (i >= w.n) return;
   const int xi = x[i], yi = y[i];
   if (static_cast<uint32_t>(xi) >= static_cast<uint32_t>(w.box) ||
@@ -72,6 +79,11 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* __restrict_
   w.rank[i] = atomicAdd(&w.count[c], 1);
 }
 
+__global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* __restrict__ x,
+                                                      const int32_t* __restrict__ y, DevWs w) {
+  bin_count_body(x, y, w, blockIdx.x);
+}
+
 // Exclusive prefix sum of in[0, m) into out[0, m], out[m] = total.  `in` may
 // alias `out`.  With clear_in (and in != out) the input is zeroed after it
 // is read.  Single pass with decoupled look-back: each tile publishes its
@@ -80,8 +92,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* __restrict_
 // Tiles take increasing tickets, so every predecessor of a tile is already
 // running when the tile waits on it: the look-back always ends (a bounded
 // spin records NM_E_DEVICE instead of waiting forever).
-__global__ __launch_bounds__(kBlock) void k_scan(int32_t* in, int32_t* out, int64_t m,
-                                                 ScanState* st, WsHeader* hdr, int clear_in) {
+__device__ __forceinline__ void scan_body(int32_t* in, int32_t* out, int64_t m, ScanState* st,
+                                          WsHeader* hdr, int clear_in) {
   __shared__ uint32_t s_tile;
   __shared__ long long s_wave[kBlock / 64];
   __shared__ long long s_prefix;
@@ -177,16 +189,20 @@ __global__ __launch_bounds__(kBlock) void k_scan(int32_t* in, int32_t* out, int6
     out[m] = static_cast<int32_t>(s_prefix + agg);
 }
 
+__global__ __launch_bounds__(kBlock) void k_scan(int32_t* in, int32_t* out, int64_t m,
+                                                 ScanState* st, WsHeader* hdr, int clear_in) {
+  scan_body(in, out, m, st, hdr, clear_in);
+}
+
 template <bool kFused>
-__global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restrict__ x,
-                                                        const int32_t* __restrict__ y,
-                                                        const float* __restrict__ theta, DevWs w,
-                                                        uint32_t step_lo, uint32_t step_hi,
-                                                        uint32_t sys_id, uint32_t seed_lo,
-                                                        uint32_t seed_hi) {
+__device__ __forceinline__ void scatter_body(const int32_t* __restrict__ x,
+                                             const int32_t* __restrict__ y,
+                                             const float* __restrict__ theta, const DevWs& w,
+                                             int b, uint32_t step_lo, uint32_t step_hi,
+                                             uint32_t sys_id, uint32_t seed_lo, uint32_t seed_hi) {
   const WsHeader* h = w.hdr;
   if (h->magic != kMagic || h->n != w.n || h->box != w.box || h->cell_w != w.cell_w) return;
-  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int t = b * kBlock + threadIdx.x;
   const int i0 = 4 * t;
   if (i0 >= w.n) return;
   uint4 noise = make_uint4(0u, 0u, 0u, 0u);
@@ -217,6 +233,67 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restric
   if (t == 0) w.hdr->built = kBuilt;
 }
 
+template <bool kFused>
+__global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restrict__ x,
+                                                        const int32_t* __restrict__ y,
+                                                        const float* __restrict__ theta, DevWs w,
+                                                        uint32_t step_lo, uint32_t step_hi,
+                                                        uint32_t sys_id, uint32_t seed_lo,
+                                                        uint32_t seed_hi) {
+  scatter_body<kFused>(x, y, theta, w, blockIdx.x, step_lo, step_hi, sys_id, seed_lo, seed_hi);
+}
+
+// ---------------------------------------------------------------------------
+// Batched stages.  Workgroup g of a persistent launch takes the stage's items
+// g, g + gridDim.x, ...; an item is one workgroup's share of one system.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ const BatchSys& batch_item(const BatchRef& b, int stage, int it, int& li) {
+  const BatchSys& d = b.sys[b.items[b.begin[stage] + it]];
+  li = it - d.base[stage];
+  return d;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bb_init(BatchRef b) {
+  const int ni = b.begin[kStInit + 1] - b.begin[kStInit];
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    int li;
+    const BatchSys& d = batch_item(b, kStInit, it, li);
+    ws_init_body(d.w, li, d.nitems[kStInit]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bb_count(BatchRef b) {
+  const int ni = b.begin[kStCount + 1] - b.begin[kStCount];
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    int li;
+    const BatchSys& d = batch_item(b, kStCount, it, li);
+    bin_count_body(d.x[d.parity], d.y[d.parity], d.w, li);
+  }
+}
+
+// Tiles of one system's scan are claimed by ticket inside scan_body, so a
+// tile only ever waits on tiles already claimed by running workgroups.
+__global__ __launch_bounds__(kBlock) void k_bb_scan(BatchRef b) {
+  const int ni = b.begin[kStScan + 1] - b.begin[kStScan];
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    int li;
+    const BatchSys& d = batch_item(b, kStScan, it, li);
+    scan_body(d.w.count, d.w.start, d.w.C, d.w.scan_c, d.w.hdr, 1);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bb_scatter(BatchRef b) {
+  const int ni = b.begin[kStScatter + 1] - b.begin[kStScatter];
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    int li;
+    const BatchSys& d = batch_item(b, kStScatter, it, li);
+    const int p = d.parity;
+    scatter_body<true>(d.x[p], d.y[p], d.th[p], d.w, li, d.step_lo, d.step_hi, d.sys_id,
+                       d.seed_lo, d.seed_hi);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_ws_init(const DevWs& w, hipStream_t s) {
@@ -244,6 +321,44 @@ hipError_t launch_build(const DevWs& w, const int32_t* x, const int32_t* y, cons
   } else {
     hipLaunchKernelGGL(k_bin_scatter<false>, dim3(nq), dim3(kBlock), 0, s, x, y, theta, w, 0u, 0u,
                        0u, 0u, 0u);
+  }
+  return hipGetLastError();
+}
+
+int batch_grid(const void* kernel, int items) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+      return items < 1 ? 1 : (items < 256 ? items : 256);
+    cus = prop.multiProcessorCount;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const long long cap = static_cast<long long>(per_cu) * cus;
+  return static_cast<int>(items < 1 ? 1 : (items < cap ? items : cap));
+}
+
+hipError_t launch_batch_bin(const BatchRef& b, int stage, hipStream_t s) {
+  const int items = b.begin[stage + 1] - b.begin[stage];
+  if (items <= 0) return hipSuccess;
+  const void* k = nullptr;
+  switch (stage) {
+    case kStInit: k = reinterpret_cast<const void*>(k_bb_init); break;
+    case kStCount: k = reinterpret_cast<const void*>(k_bb_count); break;
+    case kStScan: k = reinterpret_cast<const void*>(k_bb_scan); break;
+    case kStScatter: k = reinterpret_cast<const void*>(k_bb_scatter); break;
+    default: return hipErrorInvalidValue;
+  }
+  const int grid = batch_grid(k, items);
+  switch (stage) {
+    case kStInit: hipLaunchKernelGGL(k_bb_init, dim3(grid), dim3(kBlock), 0, s, b); break;
+    case kStCount: hipLaunchKernelGGL(k_bb_count, dim3(grid), dim3(kBlock), 0, s, b); break;
+    case kStScan: hipLaunchKernelGGL(k_bb_scan, dim3(grid), dim3(kBlock), 0, s, b); break;
+    default: hipLaunchKernelGGL(k_bb_scatter, dim3(grid), dim3(kBlock), 0, s, b); break;
   }
   return hipGetLastError();
 }

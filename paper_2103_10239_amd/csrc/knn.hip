@@ -181,16 +181,6 @@ __device__ __forceinline__ bool ws_ready(const DevWs& w) {
   return h->built == kBuilt && h->n == w.n && h->box == w.box && h->cell_w == w.cell_w;
 }
 
-struct AlignArgs {
-  int32_t v0;
-  float eta;
-  int32_t include_self;
-  const float* theta;
-  int32_t* x_out;
-  int32_t* y_out;
-  float* theta_out;
-};
-
 // Outputs of one query from the slots of its k neighbours: the list row (and
 // squared distances), and for the fused step Eq. (2) and Eq. (1).
 template <int KMAX, bool kAlign>
@@ -259,13 +249,6 @@ constexpr int kTilePts = 3072;    // staged particles
 constexpr int kTileRows = 32;     // T + 2h <= kTileRows
 
 typedef short short2v __attribute__((ext_vector_type(2)));
-
-struct TileCfg {
-  int t;     // tile side in cells
-  int h;     // halo in cells (0: no staging)
-  int ntx;   // tiles per side
-  int bmax;  // largest block side the halo supports
-};
 
 __device__ __forceinline__ int rel_d2(int packed_c, int packed_q) {
   const short2v d = __builtin_bit_cast(short2v, packed_c) - __builtin_bit_cast(short2v, packed_q);
@@ -366,9 +349,10 @@ __device__ __forceinline__ TileBox tile_box(const DevWs& w, const TileCfg& tc, i
 }
 
 template <int KMAX, bool kAlign>
-__global__ __launch_bounds__(kBlock) void k_knn(DevWs w, FastCfg f, TileCfg tc, int k,
-                                                int32_t* __restrict__ nbr,
-                                                long long* __restrict__ d2out, AlignArgs a) {
+__device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, const TileCfg& tc,
+                                              int k, int32_t* __restrict__ nbr,
+                                              long long* __restrict__ d2out, const AlignArgs& a,
+                                              int tile) {
   __shared__ int lcell[kTileCells + 1];
   __shared__ int lpos[kTilePts];
   __shared__ int lslot[kTilePts];
@@ -384,10 +368,9 @@ __global__ __launch_bounds__(kBlock) void k_knn(DevWs w, FastCfg f, TileCfg tc, 
   __shared__ int s_psx[kTileRows][3];
   __shared__ int s_defer;
   if (!ws_ready(w)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) set_err(w.hdr, NM_E_INVAL);
+    if (tile == 0 && threadIdx.x == 0) set_err(w.hdr, NM_E_INVAL);
     return;
   }
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const TileBox tb = tile_box(w, tc, tile);
   const int G = w.G, L = w.box, gm = G - 1;
   const int total = min(w.start[w.C], w.n);
@@ -510,6 +493,13 @@ __global__ __launch_bounds__(kBlock) void k_knn(DevWs w, FastCfg f, TileCfg tc, 
   if (threadIdx.x == 0) w.qcnt[tile] = s_defer;
 }
 
+template <int KMAX, bool kAlign>
+__global__ __launch_bounds__(kBlock) void k_knn(DevWs w, FastCfg f, TileCfg tc, int k,
+                                                int32_t* __restrict__ nbr,
+                                                long long* __restrict__ d2out, AlignArgs a) {
+  knn_tile_body<KMAX, kAlign>(w, f, tc, k, nbr, d2out, a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 // Cell (dx, dy) number q of ring r (q < 8r; the single cell of ring 0),
 // walking the perimeter from (-r, -r) as the exact lane search does.
 __device__ __forceinline__ void ring_cell(int r, int q, int& dx, int& dy) {
@@ -605,15 +595,15 @@ __device__ __forceinline__ bool knn_wave(const DevWs& w, int s, const int4& q, i
 // few, the wavefront searches them one at a time, so that a single long
 // search is not one lane's serial chain.
 template <int KMAX, bool kAlign>
-__global__ __launch_bounds__(kBlock) void k_knn_rest(DevWs w, TileCfg tc, int ntiles, int k,
-                                                     int32_t* __restrict__ nbr,
-                                                     long long* __restrict__ d2out, AlignArgs a) {
+__device__ __forceinline__ void knn_rest_body(const DevWs& w, const TileCfg& tc, int ntiles, int k,
+                                              int32_t* __restrict__ nbr,
+                                              long long* __restrict__ d2out, const AlignArgs& a,
+                                              int tile0, int stride) {
   if (!ws_ready(w)) return;
   const int lane = threadIdx.x & 63;
-  const int waves = gridDim.x * (kBlock / 64);
   const int total = min(w.start[w.C], w.n);
   const int G = w.G;
-  for (int tile = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); tile < ntiles; tile += waves) {
+  for (int tile = tile0; tile < ntiles; tile += stride) {
     const int cnt = w.qcnt[tile];
     if (cnt <= 0) continue;
     const TileBox tb = tile_box(w, tc, tile);
@@ -656,11 +646,80 @@ __global__ __launch_bounds__(kBlock) void k_knn_rest(DevWs w, TileCfg tc, int nt
   }
 }
 
+template <int KMAX, bool kAlign>
+__global__ __launch_bounds__(kBlock) void k_knn_rest(DevWs w, TileCfg tc, int ntiles, int k,
+                                                     int32_t* __restrict__ nbr,
+                                                     long long* __restrict__ d2out, AlignArgs a) {
+  knn_rest_body<KMAX, kAlign>(w, tc, ntiles, k, nbr, d2out, a,
+                              blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6),
+                              gridDim.x * (kBlock / 64));
+}
+
+// Batched k-NN + alignment.  Items of the tile stage are (system, tile); the
+// hardware item order is remapped so that each XCD walks one contiguous run of
+// items (consecutive tiles of a system share halo cells in that XCD's L2).
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return reinterpret_cast<T*>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ AlignArgs uniform_load_align(const BatchSys* d) {
+  const int p = __builtin_amdgcn_readfirstlane(d->parity);
+  AlignArgs a;
+  a.v0 = __builtin_amdgcn_readfirstlane(d->v0);
+  a.eta = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, d->eta)));
+  a.include_self = __builtin_amdgcn_readfirstlane(d->include_self);
+  a.theta = uniform_ptr(d->th[p]);
+  a.x_out = uniform_ptr(d->x[1 - p]);
+  a.y_out = uniform_ptr(d->y[1 - p]);
+  a.theta_out = uniform_ptr(d->th[1 - p]);
+  return a;
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void k_bb_knn(BatchRef b, int k) {
+  const int ni = b.begin[kStKnn + 1] - b.begin[kStKnn];
+  const int per = gridDim.x & ~7;  // whole rounds of the 8 XCDs
+  for (int hw = blockIdx.x; hw < ni; hw += gridDim.x) {
+    // Remap within the rounds that every workgroup of a multiple-of-8 grid takes.
+    int it = hw;
+    const int round_base = (hw / gridDim.x) * gridDim.x;
+    if (per == static_cast<int>(gridDim.x) && round_base + per <= ni)
+      it = round_base + xcd_tile(hw - round_base, per);
+    const BatchSys* g = b.sys + b.items[b.begin[kStKnn] + it];
+    const DevWs w = uniform_load(&g->w);
+    const FastCfg f = uniform_load(&g->f);
+    const TileCfg tc = uniform_load(&g->tc);
+    const AlignArgs a = uniform_load_align(g);
+    const int li = it - __builtin_amdgcn_readfirstlane(g->base[kStKnn]);
+    knn_tile_body<KMAX, true>(w, f, tc, k, uniform_ptr(g->nbr), nullptr, a, li);
+    __syncthreads();
+  }
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void k_bb_rest(BatchRef b, int k) {
+  const int ni = b.begin[kStRest + 1] - b.begin[kStRest];
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    const BatchSys* g = b.sys + b.items[b.begin[kStRest] + it];
+    const DevWs w = uniform_load(&g->w);
+    const TileCfg tc = uniform_load(&g->tc);
+    const AlignArgs a = uniform_load_align(g);
+    const int li = it - __builtin_amdgcn_readfirstlane(g->base[kStRest]);
+    knn_rest_body<KMAX, true>(w, tc, __builtin_amdgcn_readfirstlane(g->ntiles), k,
+                              uniform_ptr(g->nbr), nullptr, a,
+                              li * (kBlock / 64) + (threadIdx.x >> 6), 1 << 30);
+  }
+}
+
 // Tile geometry.  The halo h holds the blocks a query is expected to use
 // (side ~ 2 * reach * r_k / w + 1, plus one widening step); the tile side aims
 // at about 256 queries; the halo must span under 2^15 grid units for the
 // 16-bit offsets, and must not meet itself around the box.
-TileCfg tile_cfg(const DevWs& w, const FastCfg& f, int k) {
+TileCfg tile_cfg_impl(const DevWs& w, const FastCfg& f, int k) {
   TileCfg t{1, 0, w.G, 0};
   const double rho = static_cast<double>(w.n) / static_cast<double>(w.C);  // particles per cell
   const double rk = sqrt(static_cast<double>(k) / (3.141592653589793 * (rho > 1e-12 ? rho : 1e-12)));
@@ -687,7 +746,7 @@ TileCfg tile_cfg(const DevWs& w, const FastCfg& f, int k) {
 template <int KMAX, bool kAlign>
 hipError_t launch_t(const DevWs& w, const FastCfg& f, int k, int32_t* nbr, long long* d2,
                     const AlignArgs& a, hipStream_t s) {
-  const TileCfg tc = tile_cfg(w, f, k);
+  const TileCfg tc = tile_cfg_impl(w, f, k);
   const int ntiles = tc.ntx * tc.ntx;
   hipLaunchKernelGGL((k_knn<KMAX, kAlign>), dim3(ntiles), dim3(kBlock), 0, s, w, f, tc, k, nbr, d2, a);
   hipError_t e = hipGetLastError();
@@ -715,6 +774,27 @@ hipError_t dispatch_k(int k, F&& f) {
 }
 
 }  // namespace
+
+TileCfg tile_cfg(const DevWs& w, const FastCfg& f, int k) { return tile_cfg_impl(w, f, k); }
+
+hipError_t launch_batch_knn(const BatchRef& b, int k, hipStream_t s) {
+  const int nt = b.begin[kStKnn + 1] - b.begin[kStKnn];
+  const int nr = b.begin[kStRest + 1] - b.begin[kStRest];
+  return dispatch_k(k, [&](auto km) {
+    constexpr int KM = decltype(km)::value;
+    if (nt > 0) {
+      const int g = batch_grid(reinterpret_cast<const void*>(k_bb_knn<KM>), nt);
+      hipLaunchKernelGGL((k_bb_knn<KM>), dim3(g), dim3(kBlock), 0, s, b, k);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (nr > 0) {
+      const int g = batch_grid(reinterpret_cast<const void*>(k_bb_rest<KM>), nr);
+      hipLaunchKernelGGL((k_bb_rest<KM>), dim3(g), dim3(kBlock), 0, s, b, k);
+    }
+    return hipGetLastError();
+  });
+}
 
 // Fast-path limits for a grid: block sides up to the largest B whose
 // offsets keep 32-bit squared distances exact ((B / 2 + 1) w < 2^15) and whose

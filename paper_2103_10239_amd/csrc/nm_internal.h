@@ -10,8 +10,6 @@
 //   sorted      int4[n]      cell-ordered (x, y, particle index, noise word)
 //   cs          double2[2n]  cell-ordered (cos theta, sin theta) and (cos phi, sin phi)
 //                            of the noise, fused step only
-//   queue       int32[n]     slots whose k-NN search is deferred to the exact kernel,
-//                            stored in their tile's own slot range
 //   qcnt        int32[C]     number of deferred queries of each k-NN tile
 //   dflag       uint8[n]     1 for a slot whose k-NN search is deferred (kept 0
 //                            between launches)
@@ -62,7 +60,6 @@ struct DevWs {
   int32_t* rank;
   int4* sorted;
   double2* cs;
-  int32_t* queue;
   int32_t* qcnt;
   uint8_t* dflag;
   int32_t n;
@@ -77,7 +74,7 @@ struct DevWs {
 };
 
 struct Layout {
-  int64_t off_scan_c, off_scan_m, off_count, off_start, off_rank, off_sorted, off_cs, off_queue, off_qcnt,
+  int64_t off_scan_c, off_scan_m, off_count, off_start, off_rank, off_sorted, off_cs, off_qcnt,
       off_dflag, total;
   int32_t log2_box, log2_w, G, nb_scan_c, nb_scan_m;
   int64_t C;
@@ -425,6 +422,76 @@ __device__ __forceinline__ int tag_slot(const DevWs& w, const QBlock& b, uint32_
   return w.start[g.cell0] + static_cast<int>(tag & 255u);
 }
 
+// k-NN tile geometry (knn.hip): a workgroup owns a t x t square of cells and
+// stages a halo of h cells around it.
+struct TileCfg {
+  int t;     // tile side in cells
+  int h;     // halo in cells (0: no staging)
+  int ntx;   // tiles per side
+  int bmax;  // largest block side the halo supports
+};
+
+// Parameters and outputs of the fused Eq. (2) / Eq. (1) epilogue.
+struct AlignArgs {
+  int32_t v0;
+  float eta;
+  int32_t include_self;
+  const float* theta;
+  int32_t* x_out;
+  int32_t* y_out;
+  float* theta_out;
+};
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent systems advanced by one launch per stage.
+// Each stage is a persistent launch whose workgroups walk the stage's work
+// items (items of one system are contiguous; `items` maps an item to its
+// system).  The state of system s is double-buffered: step t reads buffer
+// `parity` and writes buffer 1 - parity; the advance stage flips the parity
+// and increments the step, so one captured step replays for any step.
+// ---------------------------------------------------------------------------
+enum BatchStage { kStInit = 0, kStCount, kStScan, kStScatter, kStKnn, kStRest, kStages };
+
+struct BatchSys {
+  DevWs w;
+  FastCfg f;
+  TileCfg tc;
+  int32_t* x[2];
+  int32_t* y[2];
+  float* th[2];
+  int32_t* nbr;       // int32[n * k], this system's rows
+  int32_t v0;
+  float eta;
+  int32_t include_self;
+  uint32_t sys_id, seed_lo, seed_hi;
+  uint32_t step_lo, step_hi;  // Philox step of the next step (device-updated)
+  int32_t parity;             // buffer holding the current state (device-updated)
+  int32_t ntiles;             // k-NN tiles
+  int32_t base[kStages];      // first item of this system in each stage
+  int32_t nitems[kStages];    // items of this system in each stage
+};
+
+// A workgroup-uniform copy of a descriptor read from global memory, held in
+// scalar registers (the loads are vector loads because earlier stores of the
+// kernel may alias them; each dword is then taken from the first lane).
+template <class T>
+__device__ __forceinline__ T uniform_load(const T* src) {
+  static_assert(sizeof(T) % 4 == 0, "dword-sized descriptor");
+  T out;
+  const int* s = reinterpret_cast<const int*>(src);
+  int* o = reinterpret_cast<int*>(&out);
+#pragma unroll
+  for (int i = 0; i < static_cast<int>(sizeof(T) / 4); ++i) o[i] = __builtin_amdgcn_readfirstlane(s[i]);
+  return out;
+}
+
+struct BatchRef {
+  BatchSys* sys;        // device array [nsys]
+  const int32_t* items; // device: stage item -> system, stages concatenated
+  int32_t nsys;
+  int32_t begin[kStages + 1];  // stage s owns items [begin[s], begin[s + 1])
+};
+
 // Host-side helpers (abi.hip).// Host-side helpers (abi.hip).
 bool make_layout(const nm_grid* g, Layout* out);
 DevWs dev_ws(const nm_grid* g, const Layout& lay, void* ws);
@@ -443,6 +510,13 @@ hipError_t launch_metric_fill(const DevWs& w, long long rc2, const int32_t* offs
                               long long cap, hipStream_t s);
 hipError_t launch_scan_rows(int32_t* data, int64_t m, ScanState* st, int nb, WsHeader* hdr,
                             hipStream_t s);
+TileCfg tile_cfg(const DevWs& w, const FastCfg& f, int k);
+// Persistent grid for a batched stage: at most `items` workgroups, at most
+// what stays resident on the device.
+int batch_grid(const void* kernel, int items);
+hipError_t launch_batch_bin(const BatchRef& b, int stage, hipStream_t s);
+hipError_t launch_batch_knn(const BatchRef& b, int k, hipStream_t s);
+hipError_t launch_batch_advance(const BatchRef& b, hipStream_t s);
 hipError_t launch_align(const int32_t* x, const int32_t* y, const float* theta, int32_t n,
                         const int32_t* nbr, const int32_t* offsets, int32_t k, long long nnz_cap,
                         const nm_params* p, uint64_t step, int32_t* x_out, int32_t* y_out,

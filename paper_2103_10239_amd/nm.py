@@ -42,6 +42,11 @@ class Params(ctypes.Structure):
                 ("seed", _c_u64), ("sys_id", _c_u32), ("reserved", _c_u32)]
 
 
+class BatchIO(ctypes.Structure):
+    """nm_batch_io: concatenated double-buffered state and the list output."""
+    _fields_ = [("x", _vp * 2), ("y", _vp * 2), ("theta", _vp * 2), ("nbr", _vp)]
+
+
 _lib = None
 
 
@@ -70,8 +75,18 @@ def lib():
     L.nm_bin_step.argtypes = [gp, _vp, _vp, _vp, pp, _c_u64, _vp, ctypes.c_size_t, _vp]
     L.nm_knn_align.argtypes = [gp, _vp, _c_i32, pp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.nm_check.argtypes = [_vp, _vp]
+    L.nm_batch_plan.argtypes = [_c_i32, ctypes.POINTER(_c_i32), _c_i32, _c_i32, pp,
+                                ctypes.POINTER(_c_u32), ctypes.POINTER(_vp), ctypes.POINTER(_c_i64)]
+    L.nm_batch_bind.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(BatchIO), _c_u64, _vp]
+    L.nm_batch_step.argtypes = [_vp, _c_i32, _c_i32, _vp]
+    L.nm_batch_tune.argtypes = [_vp, _c_i32, _vp]
+    L.nm_batch_system.argtypes = [_vp, _c_i32, gp, ctypes.POINTER(_c_i32)]
+    L.nm_batch_steps_done.argtypes, L.nm_batch_steps_done.restype = [_vp], _c_i64
+    L.nm_batch_check.argtypes = [_vp, _vp]
+    L.nm_batch_destroy.argtypes, L.nm_batch_destroy.restype = [_vp], None
     for f in ("nm_workspace_init", "nm_build_cells", "nm_knn", "nm_metric_list", "nm_align_step",
-              "nm_step", "nm_bin_step", "nm_knn_align", "nm_check"):
+              "nm_step", "nm_bin_step", "nm_knn_align", "nm_check", "nm_batch_plan", "nm_batch_bind",
+              "nm_batch_step", "nm_batch_tune", "nm_batch_system", "nm_batch_check"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -275,3 +290,89 @@ class System:
         self._back = (self.x, self.y, self.theta)
         self.x, self.y, self.theta = xo, yo, to
         self.step_index += 1
+
+
+class Batch:
+    """Batched form (nm_batch_*): independent systems of uneven size in
+    concatenated double-buffered arrays, advanced together on the device.
+
+    x, y, theta: host or device arrays of the concatenated initial state
+    (system s owns [offsets[s], offsets[s] + n[s])).  After t steps the state
+    is in buffer t % 2 (see `current`)."""
+
+    def __init__(self, n, x, y, theta, k: int, params: Params, sys_ids=None, device="cuda",
+                 step0: int = 0):
+        L = lib()
+        self.device = torch.device(device)
+        self.n = [int(v) for v in n]
+        self.k = int(k)
+        nsys = len(self.n)
+        narr = (_c_i32 * nsys)(*self.n)
+        ids = None if sys_ids is None else (_c_u32 * nsys)(*[int(v) for v in sys_ids])
+        h, nbytes = _vp(), _c_i64()
+        _ok(L.nm_batch_plan(nsys, narr, params.box, self.k, ctypes.byref(params), ids,
+                            ctypes.byref(h), ctypes.byref(nbytes)), "batch_plan")
+        self._h = h
+        total = sum(self.n)
+        self.offsets = [0]
+        for v in self.n:
+            self.offsets.append(self.offsets[-1] + v)
+        t = lambda a, dt: torch.as_tensor(a, dtype=dt).to(self.device).contiguous()
+        x0, y0, t0 = t(x, torch.int32), t(y, torch.int32), t(theta, torch.float32)
+        if x0.numel() != total or y0.numel() != total or t0.numel() != total:
+            raise ValueError(f"state arrays need {total} elements")
+        self.x = [x0, torch.empty_like(x0)]
+        self.y = [y0, torch.empty_like(y0)]
+        self.theta = [t0, torch.empty_like(t0)]
+        self.nbr = torch.empty(total * self.k, dtype=torch.int32, device=self.device)
+        self.buf = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        io = BatchIO()
+        for b in range(2):
+            io.x[b], io.y[b], io.theta[b] = (self.x[b].data_ptr(), self.y[b].data_ptr(),
+                                             self.theta[b].data_ptr())
+        io.nbr = self.nbr.data_ptr()
+        self._io = io
+        _ok(L.nm_batch_bind(self._h, self.buf.data_ptr(), self.buf.numel(), ctypes.byref(io),
+                            int(step0), _stream(self.device)), "batch_bind")
+
+    def step(self, nsteps: int = 1, use_graph: bool = True) -> None:
+        _ok(lib().nm_batch_step(self._h, int(nsteps), 1 if use_graph else 0, _stream(self.device)),
+            "batch_step")
+
+    def tune(self, reps: int = 3) -> None:
+        _ok(lib().nm_batch_tune(self._h, int(reps), _stream(self.device)), "batch_tune")
+
+    def grid(self, s: int) -> Grid:
+        g, off = Grid(), _c_i32()
+        _ok(lib().nm_batch_system(self._h, int(s), ctypes.byref(g), ctypes.byref(off)), "batch_system")
+        return g
+
+    @property
+    def steps_done(self) -> int:
+        return int(lib().nm_batch_steps_done(self._h))
+
+    def current(self):
+        """(x, y, theta) tensors holding the current state."""
+        b = self.steps_done % 2
+        return self.x[b], self.y[b], self.theta[b]
+
+    def system(self, s: int):
+        """Views (x, y, theta, nbr[n_s, k]) of system s's current state and last lists."""
+        a, e = self.offsets[s], self.offsets[s + 1]
+        x, y, th = self.current()
+        return x[a:e], y[a:e], th[a:e], self.nbr[a * self.k:e * self.k].view(e - a, self.k)
+
+    def check(self) -> int:
+        return int(lib().nm_batch_check(self._h, _stream(self.device)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            lib().nm_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,154 @@
+"""Batched form: many independent systems advanced together (nm_batch_*).
+
+Every system's lists, positions and headings must equal those of the plain
+one-system step (same parameters, the system's own sys_id and step count),
+bit for bit, and the first step must match the brute-force oracle to the
+usual bar (lists and positions exact, headings within 1e-5 rad).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2103_10239_amd as nm
+from paper_2103_10239_amd import workloads
+
+pytestmark = pytest.mark.gpu
+L = workloads.BOX
+TOL = 1e-5
+
+
+def _angle_err(a, b):
+    d = np.asarray(a, np.float64) - np.asarray(b, np.float64)
+    return np.abs(np.remainder(d + np.pi, 2 * np.pi) - np.pi)
+
+
+def _systems(sizes, clustered_every=0, seed=7):
+    """Concatenated state of independent systems (each its own seeded draw)."""
+    xs, ys, ts = [], [], []
+    for s, n in enumerate(sizes):
+        if clustered_every and s % clustered_every == 0:
+            x, y, _ = workloads.clustered(int(n), n_clusters=8, seed=seed + s)
+        else:
+            x, y, _ = workloads.uniform(int(n), seed_pos=seed + s)
+        xs.append(x)
+        ys.append(y)
+        ts.append(workloads.headings(int(n), seed=1000 + seed + s))
+    return xs, ys, ts
+
+
+def _plain_run(x, y, th, k, params, nsteps):
+    sysm = nm.System.create(x, y, th, k, params)
+    for _ in range(nsteps):
+        sysm.step()
+    torch.cuda.synchronize()
+    assert nm.check(sysm.ws) == 0
+    return (sysm.x.cpu().numpy(), sysm.y.cpu().numpy(), sysm.theta.cpu().numpy(),
+            sysm.nbr.cpu().numpy())
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_matches_plain_steps(use_graph):
+    sizes = [int(v) for v in workloads.batched_sizes(12, lo=64, hi=40000, seed=11)]
+    k = 7
+    xs, ys, ts = _systems(sizes, clustered_every=3)
+    ids = [100 + 3 * s for s in range(len(sizes))]
+    p = nm.make_params(L, v0=64, eta=0.2, seed=12345)
+    b = nm.Batch(sizes, np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), k, p, sys_ids=ids)
+    nsteps = 3
+    b.step(nsteps, use_graph=use_graph)
+    torch.cuda.synchronize()
+    assert b.check() == 0
+    for s, n in enumerate(sizes):
+        ps = nm.make_params(L, v0=64, eta=0.2, seed=12345, sys_id=ids[s])
+        rx, ry, rt, rn = _plain_run(xs[s], ys[s], ts[s], k, ps, nsteps)
+        bx, by, bt, bn = (t.cpu().numpy() for t in b.system(s))
+        assert np.array_equal(bx, rx) and np.array_equal(by, ry), f"system {s} (n={n}) positions"
+        assert np.array_equal(bn, rn), f"system {s} (n={n}) lists"
+        assert np.array_equal(bt.view(np.uint32), rt.view(np.uint32)), f"system {s} (n={n}) headings"
+    b.close()
+
+
+@pytest.mark.parametrize("k", [7, 12])
+def test_batch_first_step_matches_oracle(k):
+    sizes = [k + 1, 300, 1025, 5000, 17]
+    xs, ys, ts = _systems(sizes, clustered_every=2, seed=21)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=99)
+    b = nm.Batch(sizes, np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), k, p, step0=5)
+    b.step(1)
+    torch.cuda.synchronize()
+    assert b.check() == 0
+    for s in range(len(sizes)):
+        rn, rx, ry, rt = oracle.step(xs[s], ys[s], ts[s], L, k, v0=64, eta=0.2, seed=99, sys_id=s,
+                                     step_index=5)
+        bx, by, bt, bn = (t.cpu().numpy() for t in b.system(s))
+        assert np.array_equal(bn, rn), f"system {s}"
+        assert np.array_equal(bx, rx) and np.array_equal(by, ry), f"system {s}"
+        assert _angle_err(bt, rt).max() <= TOL, f"system {s}"
+    b.close()
+
+
+def test_batch_graph_replays_match_eager():
+    """Replays of the captured step, with eager work and synchronisation in
+    between, against a batch stepped without the graph."""
+    sizes = [int(v) for v in workloads.batched_sizes(9, lo=256, hi=20000, seed=3)]
+    xs, ys, ts = _systems(sizes)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=5)
+    args = (sizes, np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), 7, p)
+    bg, be = nm.Batch(*args), nm.Batch(*args)
+    for rep in range(4):
+        bg.step(1 + rep % 2, use_graph=True)
+        be.step(1 + rep % 2, use_graph=False)
+        junk = torch.randn(1 << 16, device="cuda").sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for a, e in zip(bg.current(), be.current()):
+            assert torch.equal(a, e), f"replay {rep}"
+        assert torch.equal(bg.nbr, be.nbr), f"replay {rep}"
+    assert bg.check() == 0 and be.check() == 0
+    bg.close()
+    be.close()
+
+
+def test_batch_tune_keeps_results():
+    sizes = [int(v) for v in workloads.batched_sizes(10, lo=256, hi=65536, seed=4)]
+    xs, ys, ts = _systems(sizes, clustered_every=4)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=8)
+    args = (sizes, np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), 7, p)
+    bt, bu = nm.Batch(*args), nm.Batch(*args)
+    bu.step(1)
+    bt.step(1)
+    bt.tune(reps=2)  # tuning steps must not disturb the state
+    assert bt.steps_done == 1
+    widths = {bt.grid(s).cell_w for s in range(len(sizes))}
+    assert all(w & (w - 1) == 0 for w in widths)
+    bu.step(2)
+    bt.step(2)
+    torch.cuda.synchronize()
+    for a, e in zip(bt.current(), bu.current()):
+        assert torch.equal(a, e)
+    assert torch.equal(bt.nbr, bu.nbr)
+    assert bt.check() == 0 and bu.check() == 0
+    bt.close()
+    bu.close()
+
+
+def test_batch_reports_out_of_range_coordinate():
+    sizes = [500, 700, 300]
+    xs, ys, ts = _systems(sizes)
+    x = np.concatenate(xs)
+    x[600] = L + 5  # a coordinate of system 1 outside the box
+    p = nm.make_params(L, v0=64, eta=0.2, seed=1)
+    b = nm.Batch(sizes, x, np.concatenate(ys), np.concatenate(ts), 7, p)
+    b.step(1)
+    assert b.check() == nm.NM_E_RANGE
+    assert b.check() == 0  # cleared
+    b.close()
+
+
+def test_batch_plan_rejects_bad_arguments():
+    p = nm.make_params(L)
+    with pytest.raises(nm.NMError):
+        nm.Batch([5, 100], np.zeros(105, np.int32), np.zeros(105, np.int32), np.zeros(105, np.float32), 7, p)
+    with pytest.raises(nm.NMError):
+        nm.Batch([100], np.zeros(100, np.int32), np.zeros(100, np.int32), np.zeros(100, np.float32), 33, p)
