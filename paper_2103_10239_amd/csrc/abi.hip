@@ -65,8 +65,6 @@ bool make_layout(const nm_grid* g, Layout* out) {
   off += round_up(16 * static_cast<int64_t>(g->n));
   L.off_cs = off;
   off += round_up(32 * static_cast<int64_t>(g->n));
-  L.off_qcnt = off;
-  off += round_up(4 * L.C);
   L.off_dflag = off;
   off += round_up(static_cast<int64_t>(g->n));
   L.total = off;
@@ -85,7 +83,6 @@ DevWs dev_ws(const nm_grid* g, const Layout& lay, void* ws) {
   w.rank = reinterpret_cast<int32_t*>(b + lay.off_rank);
   w.sorted = reinterpret_cast<int4*>(b + lay.off_sorted);
   w.cs = reinterpret_cast<double2*>(b + lay.off_cs);
-  w.qcnt = reinterpret_cast<int32_t*>(b + lay.off_qcnt);
   w.dflag = reinterpret_cast<uint8_t*>(b + lay.off_dflag);
   w.n = g->n;
   w.box = g->box;

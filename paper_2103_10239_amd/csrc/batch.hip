@@ -150,7 +150,6 @@ void build_tables(nm_batch* b, const std::vector<int>& which, std::vector<BatchS
     d.nitems[kStScan] = lay.nb_scan_c;
     d.nitems[kStScatter] = (g.n + 4 * kBlock - 1) / (4 * kBlock);
     d.nitems[kStKnn] = d.ntiles;
-    d.nitems[kStRest] = (d.ntiles + 3) / 4;
     for (int st = 0; st < kStages; ++st) {
       d.base[st] = static_cast<int32_t>(per[st].size());
       per[st].insert(per[st].end(), d.nitems[st], static_cast<int32_t>(q));
@@ -175,7 +174,7 @@ int64_t max_items(const nm_batch* b, int s) {
     const TileCfg tc = tile_cfg(w, fast_cfg(w, b->k, 0), b->k);
     const int64_t tiles = static_cast<int64_t>(tc.ntx) * tc.ntx;
     best = std::max<int64_t>(best, 64 + (g.n + kBlock - 1) / kBlock + lay.nb_scan_c +
-                                       (g.n + 4 * kBlock - 1) / (4 * kBlock) + tiles + (tiles + 3) / 4);
+                                       (g.n + 4 * kBlock - 1) / (4 * kBlock) + tiles);
   }
   return best;
 }

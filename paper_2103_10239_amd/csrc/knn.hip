@@ -247,6 +247,7 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
 constexpr int kTileCells = 1024;  // (T + 2h)^2 <= kTileCells
 constexpr int kTilePts = 3072;    // staged particles
 constexpr int kTileRows = 32;     // T + 2h <= kTileRows
+constexpr int kDeferCap = 256;    // uncertified queries listed in LDS per tile
 
 typedef short short2v __attribute__((ext_vector_type(2)));
 
@@ -331,173 +332,6 @@ __device__ __forceinline__ bool knn_lds(const DevWs& w, const FastCfg& f, const 
     return true;
   }
   return false;
-}
-
-// Cells of tile `tile`: columns [x0, x0 + tx), rows [y0, y0 + ty).
-struct TileBox {
-  int x0, y0, tx, ty;
-};
-
-__device__ __forceinline__ TileBox tile_box(const DevWs& w, const TileCfg& tc, int tile) {
-  TileBox b;
-  const int tyi = tile / tc.ntx, txi = tile - tyi * tc.ntx;
-  b.x0 = txi * tc.t;
-  b.y0 = tyi * tc.t;
-  b.tx = min(tc.t, w.G - b.x0);
-  b.ty = min(tc.t, w.G - b.y0);
-  return b;
-}
-
-template <int KMAX, bool kAlign>
-__device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, const TileCfg& tc,
-                                              int k, int32_t* __restrict__ nbr,
-                                              long long* __restrict__ d2out, const AlignArgs& a,
-                                              int tile) {
-  __shared__ int lcell[kTileCells + 1];
-  __shared__ int lpos[kTilePts];
-  __shared__ int lslot[kTilePts];
-  __shared__ int s_qoff[kTileRows + 1];   // query prefix over the tile's rows
-  __shared__ int s_qbeg[kTileRows];       // first slot of each tile row
-  __shared__ int s_rbase[kTileRows + 1];  // LDS offset of each halo row
-  // Each halo row is up to three physically contiguous pieces (it may wrap
-  // around the box in x): first unwrapped column, first slot, LDS offset
-  // within the row, and image shift of x.
-  __shared__ int s_pu[kTileRows][3];
-  __shared__ int s_pga[kTileRows][3];
-  __shared__ int s_plo[kTileRows][4];
-  __shared__ int s_psx[kTileRows][3];
-  __shared__ int s_defer;
-  if (!ws_ready(w)) {
-    if (tile == 0 && threadIdx.x == 0) set_err(w.hdr, NM_E_INVAL);
-    return;
-  }
-  const TileBox tb = tile_box(w, tc, tile);
-  const int G = w.G, L = w.box, gm = G - 1;
-  const int total = min(w.start[w.C], w.n);
-  const int h = tc.h, W = tb.tx + 2 * h, R = tb.ty + 2 * h;
-  const int uL = tb.x0 - h, uR = tb.x0 + tb.tx + h - 1;
-  const int lane = threadIdx.x & 63;
-  const int ox0 = uL << w.log2_w, oy0 = (tb.y0 - h) << w.log2_w;  // halo corner (tile image)
-
-  // Wave 0: query rows of the tile, and the pieces and length of each halo row.
-  if (threadIdx.x < 64) {
-    int qlen = 0, rlen = 0;
-    if (lane < tb.ty) {
-      const int64_t row = static_cast<int64_t>(tb.y0 + lane) * G;
-      const int a0 = w.start[row + tb.x0];
-      s_qbeg[lane] = a0;
-      qlen = max(min(w.start[row + tb.x0 + tb.tx], total) - a0, 0);
-    }
-    if (h > 0 && lane < R) {
-      const int64_t prow = static_cast<int64_t>((tb.y0 - h + lane) & gm) * G;
-      int np = 0;
-      for (int p0 = uL; p0 <= uR && np < 3; ++np) {
-        const int p1 = p0 < 0 ? min(uR, -1) : (p0 < G ? min(uR, G - 1) : uR);
-        const int ga = w.start[prow + (p0 & gm)];
-        s_pu[lane][np] = p0;
-        s_pga[lane][np] = ga;
-        s_plo[lane][np] = rlen;
-        s_psx[lane][np] = (p0 < 0 ? -L : (p0 >= G ? L : 0)) - ox0;
-        rlen += w.start[prow + (p1 & gm) + 1] - ga;
-        p0 = p1 + 1;
-      }
-      for (int q = np; q < 3; ++q) {
-        s_pu[lane][q] = 0x7FFFFFFF;
-        s_pga[lane][q] = 0;
-        s_plo[lane][q] = rlen;
-        s_psx[lane][q] = 0;
-      }
-      s_plo[lane][3] = rlen;
-    }
-    int qi = qlen, ri = rlen;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int t1 = __shfl_up(qi, off, 64), t2 = __shfl_up(ri, off, 64);
-      if (lane >= off) {
-        qi += t1;
-        ri += t2;
-      }
-    }
-    if (lane <= kTileRows) {
-      if (lane <= tb.ty) s_qoff[lane] = qi - qlen;
-      if (lane <= R) s_rbase[lane] = ri - rlen;
-    }
-    if (lane == 0) s_defer = 0;
-  }
-  __syncthreads();
-  const int nq = s_qoff[tb.ty];
-  if (nq == 0) {
-    if (threadIdx.x == 0) w.qcnt[tile] = 0;
-    return;
-  }
-  const bool staged = h > 0 && s_rbase[R] <= kTilePts;
-  if (staged) {
-    // Cell table: LDS offset of every halo cell, from the start table.
-    for (int c = threadIdx.x; c <= R * W; c += kBlock) {
-      if (c == R * W) {
-        lcell[c] = s_rbase[R];
-        continue;
-      }
-      const int rho = c / W, u = uL + (c - rho * W);
-      const int pi = (u >= s_pu[rho][2]) ? 2 : ((u >= s_pu[rho][1]) ? 1 : 0);
-      const int64_t cell = static_cast<int64_t>((tb.y0 - h + rho) & gm) * G + (u & gm);
-      lcell[c] = s_rbase[rho] + s_plo[rho][pi] + (w.start[cell] - s_pga[rho][pi]);
-    }
-    // Particles as packed 16-bit offsets from the halo corner, one per thread
-    // per round: find the halo row (binary search over the row offsets) and
-    // the piece, then the source slot.
-    const int npts = s_rbase[R];
-    for (int pidx = threadIdx.x; pidx < npts; pidx += kBlock) {
-      int rho = 0;
-#pragma unroll
-      for (int step = kTileRows / 2; step > 0; step >>= 1)
-        if (rho + step < R && s_rbase[rho + step] <= pidx) rho += step;
-      const int inrow = pidx - s_rbase[rho];
-      const int pi = (inrow >= s_plo[rho][2]) ? 2 : ((inrow >= s_plo[rho][1]) ? 1 : 0);
-      const int src = s_pga[rho][pi] + (inrow - s_plo[rho][pi]);
-      const int v = tb.y0 - h + rho;
-      const int sy = (v < 0 ? -L : (v >= G ? L : 0)) - oy0;
-      const int2 e = reinterpret_cast<const int2*>(w.sorted)[2 * src];
-      lpos[pidx] = pack_rel(e.x + s_psx[rho][pi], e.y + sy);
-      lslot[pidx] = src;
-    }
-    __syncthreads();
-  }
-
-  for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
-    int rq = 0;  // tile row of query qi
-#pragma unroll
-    for (int step = kTileRows / 2; step > 0; step >>= 1)
-      if (rq + step < tb.ty && s_qoff[rq + step] <= qi) rq += step;
-    const int s = s_qbeg[rq] + (qi - s_qoff[rq]);
-    const int4 q = w.sorted[s];
-    int slot[KMAX];
-    bool ok;
-    if (staged) {
-      const int cx = (q.x >> w.log2_w) - uL, cy = rq + h;
-      const int64_t hc = static_cast<int64_t>(tb.y0 + rq) * G + (q.x >> w.log2_w);
-      const int self = lcell[cy * W + cx] + (s - w.start[hc]);
-      ok = knn_lds<KMAX>(w, f, tc, lcell, lpos, lslot, W, cx, cy, self,
-                         pack_rel(q.x - ox0, q.y - oy0), q.x, q.y, k, slot);
-    } else {
-      ok = knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot);
-    }
-    if (ok) {
-      finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
-    } else {
-      w.dflag[s] = 1;
-      atomicAdd(&s_defer, 1);
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) w.qcnt[tile] = s_defer;
-}
-
-template <int KMAX, bool kAlign>
-__global__ __launch_bounds__(kBlock) void k_knn(DevWs w, FastCfg f, TileCfg tc, int k,
-                                                int32_t* __restrict__ nbr,
-                                                long long* __restrict__ d2out, AlignArgs a) {
-  knn_tile_body<KMAX, kAlign>(w, f, tc, k, nbr, d2out, a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Cell (dx, dy) number q of ring r (q < 8r; the single cell of ring 0),
@@ -589,57 +423,207 @@ __device__ __forceinline__ bool knn_wave(const DevWs& w, int s, const int4& q, i
   return top.worst() != ~0ull;
 }
 
-// The deferred queries, tile by tile (one wavefront per tile that has any):
-// the lanes walk the tile's slots for the flagged ones and clear the flags.
-// With many flagged, each lane searches its own (exact lane search); with a
-// few, the wavefront searches them one at a time, so that a single long
-// search is not one lane's serial chain.
+// One uncertified query searched by its own lane (exact ring search).
 template <int KMAX, bool kAlign>
-__device__ __forceinline__ void knn_rest_body(const DevWs& w, const TileCfg& tc, int ntiles, int k,
-                                              int32_t* __restrict__ nbr,
+__device__ __forceinline__ void exact_lane(const DevWs& w, int s, int k, int total,
+                                           int32_t* __restrict__ nbr, long long* __restrict__ d2out,
+                                           const AlignArgs& a) {
+  const int4 q = w.sorted[s];
+  int slot[KMAX];
+  if (knn_exact<KMAX>(w, s, q.x, q.y, k, total, slot))
+    finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
+  else
+    set_err(w.hdr, NM_E_RANGE);  // fewer than k other particles were binned
+}
+
+// Cells of tile `tile`: columns [x0, x0 + tx), rows [y0, y0 + ty).
+struct TileBox {
+  int x0, y0, tx, ty;
+};
+
+__device__ __forceinline__ TileBox tile_box(const DevWs& w, const TileCfg& tc, int tile) {
+  TileBox b;
+  const int tyi = tile / tc.ntx, txi = tile - tyi * tc.ntx;
+  b.x0 = txi * tc.t;
+  b.y0 = tyi * tc.t;
+  b.tx = min(tc.t, w.G - b.x0);
+  b.ty = min(tc.t, w.G - b.y0);
+  return b;
+}
+
+template <int KMAX, bool kAlign>
+__device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, const TileCfg& tc,
+                                              int k, int32_t* __restrict__ nbr,
                                               long long* __restrict__ d2out, const AlignArgs& a,
-                                              int tile0, int stride) {
-  if (!ws_ready(w)) return;
-  const int lane = threadIdx.x & 63;
+                                              int tile) {
+  __shared__ int lcell[kTileCells + 1];
+  __shared__ int lpos[kTilePts];
+  __shared__ int lslot[kTilePts];
+  __shared__ int s_qoff[kTileRows + 1];   // query prefix over the tile's rows
+  __shared__ int s_qbeg[kTileRows];       // first slot of each tile row
+  __shared__ int s_rbase[kTileRows + 1];  // LDS offset of each halo row
+  // Each halo row is up to three physically contiguous pieces (it may wrap
+  // around the box in x): first unwrapped column, first slot, LDS offset
+  // within the row, and image shift of x.
+  __shared__ int s_pu[kTileRows][3];
+  __shared__ int s_pga[kTileRows][3];
+  __shared__ int s_plo[kTileRows][4];
+  __shared__ int s_psx[kTileRows][3];
+  __shared__ int s_defer;
+  __shared__ int s_dq[kDeferCap];  // slots of the tile's uncertified queries
+  if (!ws_ready(w)) {
+    if (tile == 0 && threadIdx.x == 0) set_err(w.hdr, NM_E_INVAL);
+    return;
+  }
+  const TileBox tb = tile_box(w, tc, tile);
+  const int G = w.G, L = w.box, gm = G - 1;
   const int total = min(w.start[w.C], w.n);
-  const int G = w.G;
-  for (int tile = tile0; tile < ntiles; tile += stride) {
-    const int cnt = w.qcnt[tile];
-    if (cnt <= 0) continue;
-    const TileBox tb = tile_box(w, tc, tile);
-    for (int r = 0; r < tb.ty; ++r) {
-      const int64_t row = static_cast<int64_t>(tb.y0 + r) * G;
+  const int h = tc.h, W = tb.tx + 2 * h, R = tb.ty + 2 * h;
+  const int uL = tb.x0 - h, uR = tb.x0 + tb.tx + h - 1;
+  const int lane = threadIdx.x & 63;
+  const int ox0 = uL << w.log2_w, oy0 = (tb.y0 - h) << w.log2_w;  // halo corner (tile image)
+
+  // Wave 0: query rows of the tile, and the pieces and length of each halo row.
+  if (threadIdx.x < 64) {
+    int qlen = 0, rlen = 0;
+    if (lane < tb.ty) {
+      const int64_t row = static_cast<int64_t>(tb.y0 + lane) * G;
       const int a0 = w.start[row + tb.x0];
-      const int a1 = min(w.start[row + tb.x0 + tb.tx], total);
-      for (int base = a0; base < a1; base += 64) {
-        const int s = base + lane;
-        const bool mine = s < a1 && w.dflag[s];
-        if (mine) w.dflag[s] = 0;
-        if (cnt >= 16) {
-          if (mine) {
-            const int4 q = w.sorted[s];
-            int slot[KMAX];
-            if (knn_exact<KMAX>(w, s, q.x, q.y, k, total, slot))
-              finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
-            else
-              set_err(w.hdr, NM_E_RANGE);  // fewer than k other particles were binned
-          }
-        } else {
-          unsigned long long todo = __ballot(mine);
-          while (todo) {
-            const int l = __ffsll(static_cast<long long>(todo)) - 1;
-            todo &= todo - 1;
-            const int sq = __shfl(s, l, 64);
-            const int4 q = w.sorted[sq];
-            int slot[KMAX];
-            const bool ok = knn_wave<KMAX>(w, sq, q, k, total, slot);
-            if (lane == 0) {
-              if (ok)
-                finish_query<KMAX, kAlign>(w, sq, q, slot, k, nbr, d2out, a);
-              else
-                set_err(w.hdr, NM_E_RANGE);
-            }
-          }
+      s_qbeg[lane] = a0;
+      qlen = max(min(w.start[row + tb.x0 + tb.tx], total) - a0, 0);
+    }
+    if (h > 0 && lane < R) {
+      const int64_t prow = static_cast<int64_t>((tb.y0 - h + lane) & gm) * G;
+      int np = 0;
+      for (int p0 = uL; p0 <= uR && np < 3; ++np) {
+        const int p1 = p0 < 0 ? min(uR, -1) : (p0 < G ? min(uR, G - 1) : uR);
+        const int ga = w.start[prow + (p0 & gm)];
+        s_pu[lane][np] = p0;
+        s_pga[lane][np] = ga;
+        s_plo[lane][np] = rlen;
+        s_psx[lane][np] = (p0 < 0 ? -L : (p0 >= G ? L : 0)) - ox0;
+        rlen += w.start[prow + (p1 & gm) + 1] - ga;
+        p0 = p1 + 1;
+      }
+      for (int q = np; q < 3; ++q) {
+        s_pu[lane][q] = 0x7FFFFFFF;
+        s_pga[lane][q] = 0;
+        s_plo[lane][q] = rlen;
+        s_psx[lane][q] = 0;
+      }
+      s_plo[lane][3] = rlen;
+    }
+    int qi = qlen, ri = rlen;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t1 = __shfl_up(qi, off, 64), t2 = __shfl_up(ri, off, 64);
+      if (lane >= off) {
+        qi += t1;
+        ri += t2;
+      }
+    }
+    if (lane <= kTileRows) {
+      if (lane <= tb.ty) s_qoff[lane] = qi - qlen;
+      if (lane <= R) s_rbase[lane] = ri - rlen;
+    }
+    if (lane == 0) s_defer = 0;
+  }
+  __syncthreads();
+  const int nq = s_qoff[tb.ty];
+  if (nq == 0) return;
+  const bool staged = h > 0 && s_rbase[R] <= kTilePts;
+  if (staged) {
+    // Cell table: LDS offset of every halo cell, from the start table.
+    for (int c = threadIdx.x; c <= R * W; c += kBlock) {
+      if (c == R * W) {
+        lcell[c] = s_rbase[R];
+        continue;
+      }
+      const int rho = c / W, u = uL + (c - rho * W);
+      const int pi = (u >= s_pu[rho][2]) ? 2 : ((u >= s_pu[rho][1]) ? 1 : 0);
+      const int64_t cell = static_cast<int64_t>((tb.y0 - h + rho) & gm) * G + (u & gm);
+      lcell[c] = s_rbase[rho] + s_plo[rho][pi] + (w.start[cell] - s_pga[rho][pi]);
+    }
+    // Particles as packed 16-bit offsets from the halo corner, one per thread
+    // per round: find the halo row (binary search over the row offsets) and
+    // the piece, then the source slot.
+    const int npts = s_rbase[R];
+    for (int pidx = threadIdx.x; pidx < npts; pidx += kBlock) {
+      int rho = 0;
+#pragma unroll
+      for (int step = kTileRows / 2; step > 0; step >>= 1)
+        if (rho + step < R && s_rbase[rho + step] <= pidx) rho += step;
+      const int inrow = pidx - s_rbase[rho];
+      const int pi = (inrow >= s_plo[rho][2]) ? 2 : ((inrow >= s_plo[rho][1]) ? 1 : 0);
+      const int src = s_pga[rho][pi] + (inrow - s_plo[rho][pi]);
+      const int v = tb.y0 - h + rho;
+      const int sy = (v < 0 ? -L : (v >= G ? L : 0)) - oy0;
+      const int2 e = reinterpret_cast<const int2*>(w.sorted)[2 * src];
+      lpos[pidx] = pack_rel(e.x + s_psx[rho][pi], e.y + sy);
+      lslot[pidx] = src;
+    }
+    __syncthreads();
+  }
+
+  for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
+    int rq = 0;  // tile row of query qi
+#pragma unroll
+    for (int step = kTileRows / 2; step > 0; step >>= 1)
+      if (rq + step < tb.ty && s_qoff[rq + step] <= qi) rq += step;
+    const int s = s_qbeg[rq] + (qi - s_qoff[rq]);
+    const int4 q = w.sorted[s];
+    int slot[KMAX];
+    bool ok;
+    if (staged) {
+      const int cx = (q.x >> w.log2_w) - uL, cy = rq + h;
+      const int64_t hc = static_cast<int64_t>(tb.y0 + rq) * G + (q.x >> w.log2_w);
+      const int self = lcell[cy * W + cx] + (s - w.start[hc]);
+      ok = knn_lds<KMAX>(w, f, tc, lcell, lpos, lslot, W, cx, cy, self,
+                         pack_rel(q.x - ox0, q.y - oy0), q.x, q.y, k, slot);
+    } else {
+      ok = knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot);
+    }
+    if (ok) {
+      finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
+    } else {
+      const int pos = atomicAdd(&s_defer, 1);
+      if (pos < kDeferCap)
+        s_dq[pos] = s;
+      else
+        w.dflag[s] = 1;  // overflow of the list: found again below by its flag
+    }
+  }
+  __syncthreads();
+  const int nd = s_defer;
+  if (nd == 0) return;
+
+  // The tile's uncertified queries, by the exact ring search.  With many,
+  // each lane searches its own; with a few, a wavefront searches one at a
+  // time, so that a single long search is not one lane's serial chain.
+  const int nl = min(nd, kDeferCap);
+  if (nl >= 64) {
+    for (int j = threadIdx.x; j < nl; j += kBlock) exact_lane<KMAX, kAlign>(w, s_dq[j], k, total, nbr, d2out, a);
+  } else {
+    for (int j = threadIdx.x >> 6; j < nl; j += kBlock / 64) {
+      const int sq = s_dq[j];
+      const int4 q = w.sorted[sq];
+      int slot[KMAX];
+      const bool ok = knn_wave<KMAX>(w, sq, q, k, total, slot);
+      if (lane == 0) {
+        if (ok)
+          finish_query<KMAX, kAlign>(w, sq, q, slot, k, nbr, d2out, a);
+        else
+          set_err(w.hdr, NM_E_RANGE);  // fewer than k other particles were binned
+      }
+    }
+  }
+  if (nd > kDeferCap) {
+    for (int r = 0; r < tb.ty; ++r) {
+      const int a0 = s_qbeg[r], a1 = a0 + (s_qoff[r + 1] - s_qoff[r]);
+      for (int sq = a0 + threadIdx.x; sq < a1; sq += kBlock) {
+        if (w.dflag[sq]) {
+          w.dflag[sq] = 0;
+          exact_lane<KMAX, kAlign>(w, sq, k, total, nbr, d2out, a);
         }
       }
     }
@@ -647,12 +631,10 @@ __device__ __forceinline__ void knn_rest_body(const DevWs& w, const TileCfg& tc,
 }
 
 template <int KMAX, bool kAlign>
-__global__ __launch_bounds__(kBlock) void k_knn_rest(DevWs w, TileCfg tc, int ntiles, int k,
-                                                     int32_t* __restrict__ nbr,
-                                                     long long* __restrict__ d2out, AlignArgs a) {
-  knn_rest_body<KMAX, kAlign>(w, tc, ntiles, k, nbr, d2out, a,
-                              blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6),
-                              gridDim.x * (kBlock / 64));
+__global__ __launch_bounds__(kBlock) void k_knn(DevWs w, FastCfg f, TileCfg tc, int k,
+                                                int32_t* __restrict__ nbr,
+                                                long long* __restrict__ d2out, AlignArgs a) {
+  knn_tile_body<KMAX, kAlign>(w, f, tc, k, nbr, d2out, a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Batched k-NN + alignment.  Items of the tile stage are (system, tile); the
@@ -700,21 +682,6 @@ __global__ __launch_bounds__(kBlock) void k_bb_knn(BatchRef b, int k) {
   }
 }
 
-template <int KMAX>
-__global__ __launch_bounds__(kBlock) void k_bb_rest(BatchRef b, int k) {
-  const int ni = b.begin[kStRest + 1] - b.begin[kStRest];
-  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
-    const BatchSys* g = b.sys + b.items[b.begin[kStRest] + it];
-    const DevWs w = uniform_load(&g->w);
-    const TileCfg tc = uniform_load(&g->tc);
-    const AlignArgs a = uniform_load_align(g);
-    const int li = it - __builtin_amdgcn_readfirstlane(g->base[kStRest]);
-    knn_rest_body<KMAX, true>(w, tc, __builtin_amdgcn_readfirstlane(g->ntiles), k,
-                              uniform_ptr(g->nbr), nullptr, a,
-                              li * (kBlock / 64) + (threadIdx.x >> 6), 1 << 30);
-  }
-}
-
 // Tile geometry.  The halo h holds the blocks a query is expected to use
 // (side ~ 2 * reach * r_k / w + 1, plus one widening step); the tile side aims
 // at about 256 queries; the halo must span under 2^15 grid units for the
@@ -749,11 +716,6 @@ hipError_t launch_t(const DevWs& w, const FastCfg& f, int k, int32_t* nbr, long 
   const TileCfg tc = tile_cfg_impl(w, f, k);
   const int ntiles = tc.ntx * tc.ntx;
   hipLaunchKernelGGL((k_knn<KMAX, kAlign>), dim3(ntiles), dim3(kBlock), 0, s, w, f, tc, k, nbr, d2, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int nr = min((ntiles + 3) / 4, 1024);
-  hipLaunchKernelGGL((k_knn_rest<KMAX, kAlign>), dim3(nr), dim3(kBlock), 0, s, w, tc, ntiles, k, nbr,
-                     d2, a);
   return hipGetLastError();
 }
 
@@ -779,19 +741,11 @@ TileCfg tile_cfg(const DevWs& w, const FastCfg& f, int k) { return tile_cfg_impl
 
 hipError_t launch_batch_knn(const BatchRef& b, int k, hipStream_t s) {
   const int nt = b.begin[kStKnn + 1] - b.begin[kStKnn];
-  const int nr = b.begin[kStRest + 1] - b.begin[kStRest];
+  if (nt <= 0) return hipSuccess;
   return dispatch_k(k, [&](auto km) {
     constexpr int KM = decltype(km)::value;
-    if (nt > 0) {
-      const int g = batch_grid(reinterpret_cast<const void*>(k_bb_knn<KM>), nt);
-      hipLaunchKernelGGL((k_bb_knn<KM>), dim3(g), dim3(kBlock), 0, s, b, k);
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
-    if (nr > 0) {
-      const int g = batch_grid(reinterpret_cast<const void*>(k_bb_rest<KM>), nr);
-      hipLaunchKernelGGL((k_bb_rest<KM>), dim3(g), dim3(kBlock), 0, s, b, k);
-    }
+    const int g = batch_grid(reinterpret_cast<const void*>(k_bb_knn<KM>), nt);
+    hipLaunchKernelGGL((k_bb_knn<KM>), dim3(g), dim3(kBlock), 0, s, b, k);
     return hipGetLastError();
   });
 }

@@ -10,7 +10,6 @@
 //   sorted      int4[n]      cell-ordered (x, y, particle index, noise word)
 //   cs          double2[2n]  cell-ordered (cos theta, sin theta) and (cos phi, sin phi)
 //                            of the noise, fused step only
-//   qcnt        int32[C]     number of deferred queries of each k-NN tile
 //   dflag       uint8[n]     1 for a slot whose k-NN search is deferred (kept 0
 //                            between launches)
 // C = G^2 cells, G = L / w.  Cells are numbered row-major: c = cy * G + cx.
@@ -60,7 +59,6 @@ struct DevWs {
   int32_t* rank;
   int4* sorted;
   double2* cs;
-  int32_t* qcnt;
   uint8_t* dflag;
   int32_t n;
   int32_t box;
@@ -74,7 +72,7 @@ struct DevWs {
 };
 
 struct Layout {
-  int64_t off_scan_c, off_scan_m, off_count, off_start, off_rank, off_sorted, off_cs, off_qcnt,
+  int64_t off_scan_c, off_scan_m, off_count, off_start, off_rank, off_sorted, off_cs,
       off_dflag, total;
   int32_t log2_box, log2_w, G, nb_scan_c, nb_scan_m;
   int64_t C;
@@ -450,7 +448,7 @@ struct AlignArgs {
 // `parity` and writes buffer 1 - parity; the advance stage flips the parity
 // and increments the step, so one captured step replays for any step.
 // ---------------------------------------------------------------------------
-enum BatchStage { kStInit = 0, kStCount, kStScan, kStScatter, kStKnn, kStRest, kStages };
+enum BatchStage { kStInit = 0, kStCount, kStScan, kStScatter, kStKnn, kStages };
 
 struct BatchSys {
   DevWs w;
