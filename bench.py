@@ -1,28 +1,41 @@
 #!/usr/bin/env python3
-"""Throughput of one full step of the non-metric Vicsek model on one MI355X.
+"""Throughput of the non-metric Vicsek step on one MI355X.
 
-Workload (synthetic, seeded): N = 2^20 particles uniform in a periodic box of
-side L = 2^20, headings uniform, k = 7 topological neighbours, v0 = 64,
-eta = 0.2, Philox seed 0; beside the k-NN list the metric cutoff list is
-rebuilt every step with r_c^2 = 2,336,407 (a mean of 7 neighbours).
+Headline workload (synthetic, seeded): N = 2^20 particles uniform in a
+periodic box of side L = 2^20, headings uniform in [-pi, pi), k = 7
+topological neighbours, v0 = 64, eta = 0.2, Philox seed 0, 1000 steps; every
+step rebuilds the lists (Alg. 1).  One timed step is the whole hot path on
+the GPU, inputs resident in HBM:
 
-One timed step = every stage of the hot path on the GPU:
-  nm_bin_step      cell binning (histogram, scan, scatter + noise + unit vectors)
-  nm_knn_align     k-NN lists fused with Eq. (2) alignment and Eq. (1) move
-  nm_metric_list   metric cutoff list (count, scan, fill; capacity preset)
-Inputs are resident in HBM before timing starts.  The value is particle-steps
-per second (N * steps / wall time of the timed steps).
+  nm_bin_step    cell binning (histogram, scan, scatter + noise + unit vectors)
+  nm_knn_align   k-NN lists fused with Eq. (2) alignment and Eq. (1) move
 
-The dominant kernel (the fused k-NN + alignment kernel) is bracketed by HIP
-events on the stream it runs on; its roofline entry prices the step's
-compulsory traffic, 24 + 4k bytes per particle-step (read x, y, theta; write
-the k indices and x', y', theta'), against the 8 TB/s HBM peak.
+value = N * steps / wall time of the timed steps (particle-steps/s).  The
+cell width and block side are picked by the library's tuner (nm_tune_grid)
+on the initial state before warm-up.
 
-cpu_baseline: the brute-force oracle timed on the host on a sample of the same
-workload (a few thousand query particles of the N = 2^20 system, all stages).
+Beside it, on the same GPU:
+  metric   the metric cutoff list (r_c^2 = 2,336,407, mean 7 neighbours),
+           timed on its own and inside a metric-mode step
+  batched  512 systems, N log-uniform in [256, 65536], k = 7, one persistent
+           launch per stage under a captured HIP graph, tuned cell widths;
+           compared with the plain per-system calls (eager and graph-captured)
+  served   a Poisson stream of jobs through the served form (when built)
+
+roofline: the fused k-NN + alignment kernel (k_knn<7, align>) bracketed by
+HIP events on the stream it runs on; its algorithmic traffic is 24 + 4k bytes
+per particle-step (read x, y, theta; write the k indices and x', y',
+theta'), priced against the 8 TB/s HBM peak.  `traffic` is the DRAM traffic
+per launch that rocprofv3 counters measured for the same kernel source (null
+if the kernel changed since).
+
+cpu_baseline: the brute-force oracle on the host, on a sample of query
+particles of the same N = 2^20 system (k-NN rows and the Eq. 1-2 step).
 """
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -33,6 +46,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "particle-steps/s (k=7 kNN rebuild + align) at N=1M; batched p50/p99 latency"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_knn_align_uniform_1m_k7.json")
+KERNEL_SOURCES = ("knn.hip", "nm_internal.h")
 
 
 def log(*a):
@@ -46,14 +61,50 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--k", type=int, default=7)
-    ap.add_argument("--cell-w", type=int, default=0, help="cell width (0: built-in choice)")
-    ap.add_argument("--no-metric", action="store_true", help="time the k-NN step only")
+    ap.add_argument("--cell-w", type=int, default=0, help="cell width (0: tuned)")
+    ap.add_argument("--block", type=int, default=0, help="fast-path block side with --cell-w")
+    ap.add_argument("--metric-steps", type=int, default=100)
+    ap.add_argument("--batched-steps", type=int, default=50)
+    ap.add_argument("--served-seconds", type=float, default=20.0)
+    ap.add_argument("--no-metric", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
 
-def cpu_baseline(x, y, th, k, rc2, box, target_s):
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2103_10239_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n, k, cell_w, block):
+    """DRAM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on this kernel source and configuration."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if (t.get("source_sha") != kernel_source_sha() or t.get("n") != n or t.get("k") != k
+            or t.get("cell_w") != cell_w or t.get("block") != block):
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def pct(v, q):
+    v = sorted(v)
+    if not v:
+        return None
+    i = min(len(v) - 1, max(0, int(math.ceil(q / 100.0 * len(v))) - 1))
+    return v[i]
+
+
+def cpu_baseline(x, y, th, k, box, target_s):
     """Oracle (brute force, all host threads) on sampled query rows of the same system."""
     import numpy as np
 
@@ -67,8 +118,6 @@ def cpu_baseline(x, y, th, k, rc2, box, target_s):
         t0 = time.perf_counter()
         nbr, _ = oracle.knn(x, y, box, k, rows=rows, with_d2=False)
         oracle.align_step(x, y, th, box, nbr=nbr, v0=64, eta=0.2, seed=workloads.NOISE_SEED, rows=rows)
-        if rc2 is not None:
-            oracle.metric_list(x, y, box, rc2, rows=rows, with_d2=False)
         return time.perf_counter() - t0
 
     probe = rng.choice(n, size=min(256, n), replace=False).astype(np.int32)
@@ -77,73 +126,50 @@ def cpu_baseline(x, y, th, k, rc2, box, target_s):
     rows = rng.choice(n, size=m, replace=False).astype(np.int32)
     t = run(rows)
     return {"value": m / t, "unit": "particle-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{m} sampled particles of the N={n} system: brute-force k-NN rows, "
-                      f"Eq. 1-2 step{' and metric rows' if rc2 is not None else ''}; {t:.1f} s",
+            "sample": f"{m} sampled particles of the N={n} uniform system: brute-force k-NN rows "
+                      f"(O(N) per row) and the Eq. 1-2 step for them, {t:.1f} s",
             "seconds": t}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
-              "multi-GPU mode in this build.", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    import paper_2103_10239_amd as nm
-    from paper_2103_10239_amd import workloads
-
-    assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+def bench_single(args, torch, nm, workloads):
     n, k, box = args.n, args.k, workloads.BOX
-    rc2 = None if args.no_metric else workloads.rc2_for_mean(n, 7.0)
-    cell_w = args.cell_w or nm.suggest_cell_w(n, box, 4.0)
-
+    dev = torch.device("cuda:0")
     x, y, th = workloads.uniform(n)
     p = nm.make_params(box, v0=64, eta=0.2, include_self=1, seed=workloads.NOISE_SEED)
-    ws = nm.Workspace(n, box, cell_w, dev)
-    X = torch.as_tensor(x).to(dev)
-    Y = torch.as_tensor(y).to(dev)
-    T = torch.as_tensor(th).to(dev)
+    X, Y, T = (torch.as_tensor(a).to(dev) for a in (x, y, th))
+    tuned = None
+    if args.cell_w:
+        ws = nm.Workspace(n, box, args.cell_w, dev, block=args.block)
+    else:
+        cws = sorted({nm.suggest_cell_w(n, box, pc) for pc in (1.0, 2.0, 4.0)})
+        ws, tuned = nm.tune_grid(n, box, X, Y, T, k, p, cell_ws=cws, blocks=(0, 4, 6), reps=5,
+                                 device=dev)
+    cell_w, block = ws.grid.cell_w, ws.grid.block
+    log(f"[bench] N={n} k={k} cell_w={cell_w} block={block} "
+        f"tuned={ {f'{w}/{b}': round(v, 4) for (w, b), v in tuned.items()} if tuned else None}")
     Xb, Yb, Tb = torch.empty_like(X), torch.empty_like(Y), torch.empty_like(T)
     nbr = torch.empty((n, k), dtype=torch.int32, device=dev)
-    offsets = torch.empty(n + 1, dtype=torch.int32, device=dev)
-    idx = None
-    if rc2 is not None:
-        # From the disordered start the aligned groups cluster, and the mean metric
-        # degree climbs steadily (7 at step 0, about 31 by step 375), so the index
-        # array gets a fixed capacity of 160 per particle; an overflow would be
-        # reported by nm_check and fail the run.
-        idx = torch.empty(160 * n, dtype=torch.int32, device=dev)
-
-    state = {"x": X, "y": Y, "t": T, "xb": Xb, "yb": Yb, "tb": Tb, "step": 0}
+    st = {"x": X, "y": Y, "t": T, "xb": Xb, "yb": Yb, "tb": Tb, "step": 0}
 
     def one_step(ev=None):
-        s = state
+        s = st
         nm.bin_step(ws, s["x"], s["y"], s["t"], p, s["step"])
         if ev is not None:
             ev[0].record()
         nm.knn_align(ws, k, p, s["t"], nbr, s["xb"], s["yb"], s["tb"])
         if ev is not None:
             ev[1].record()
-        if rc2 is not None:
-            nm.metric_list(ws, rc2, offsets, idx)
         s["x"], s["xb"] = s["xb"], s["x"]
         s["y"], s["yb"] = s["yb"], s["y"]
         s["t"], s["tb"] = s["tb"], s["t"]
         s["step"] += 1
 
-    log(f"[bench] N={n} k={k} cell_w={cell_w} metric={'on' if rc2 else 'off'} "
-        f"warmup={args.warmup} steps={args.steps}")
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
     if nm.check(ws) != 0:
         raise RuntimeError("device error during warmup")
     log("[bench] warmup done")
-
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -156,12 +182,168 @@ def main():
     if status != 0:
         raise RuntimeError(f"device error in timed steps: {nm.nm.status_str(status)}")
     ms_step = (t1 - t0) * 1e3 / args.steps
-    k_ms = sum(a.elapsed_time(b) for a, b in events) / args.steps
-    log(f"[bench] timed {args.steps} steps: {ms_step:.4f} ms/step, fused kernel {k_ms:.4f} ms")
+    kms = [a.elapsed_time(b) for a, b in events]
+    k_ms = sum(kms) / len(kms)
+    log(f"[bench] timed {args.steps} steps: {ms_step:.4f} ms/step, k-NN+align kernel {k_ms:.4f} ms")
+    return {"x": x, "y": y, "th": th, "ms_step": ms_step, "k_ms": k_ms, "k_p50": pct(kms, 50),
+            "k_p99": pct(kms, 99), "cell_w": cell_w, "block": block, "tuned": tuned}
 
-    value = n / (ms_step * 1e-3)
+
+def bench_metric(args, torch, nm, workloads):
+    """Metric-mode steps from the initial state: binning, k-NN + align, and the
+    metric list (count, scan, fill) every step."""
+    n, k, box = args.n, args.k, workloads.BOX
+    dev = torch.device("cuda:0")
+    rc2 = workloads.rc2_for_mean(n, 7.0)
+    x, y, th = workloads.uniform(n)
+    p = nm.make_params(box, v0=64, eta=0.2, include_self=1, seed=workloads.NOISE_SEED)
+    X, Y, T = (torch.as_tensor(a).to(dev) for a in (x, y, th))
+    Xb, Yb, Tb = torch.empty_like(X), torch.empty_like(Y), torch.empty_like(T)
+    ws = nm.Workspace(n, box, nm.suggest_cell_w(n, box, 4.0), dev)
+    nbr = torch.empty((n, k), dtype=torch.int32, device=dev)
+    offsets = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    # Aligned groups cluster from the disordered start and the mean metric
+    # degree grows (about 7 at step 0); a fixed capacity of 64 per particle
+    # covers the timed steps, and an overflow would fail the run.
+    idx = torch.empty(64 * n, dtype=torch.int32, device=dev)
+    steps = args.metric_steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    s = {"x": X, "y": Y, "t": T, "xb": Xb, "yb": Yb, "tb": Tb}
+    for warm in (True, False):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(3 if warm else steps):
+            nm.bin_step(ws, s["x"], s["y"], s["t"], p, i)
+            nm.knn_align(ws, k, p, s["t"], nbr, s["xb"], s["yb"], s["tb"])
+            if not warm:
+                ev[i][0].record()
+            nm.metric_list(ws, rc2, offsets, idx)
+            if not warm:
+                ev[i][1].record()
+            s["x"], s["xb"] = s["xb"], s["x"]
+            s["y"], s["yb"] = s["yb"], s["y"]
+            s["t"], s["tb"] = s["tb"], s["t"]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    if nm.check(ws) != 0:
+        raise RuntimeError("device error in metric-mode steps")
+    nnz = int(offsets[n].item())
+    m_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    ms_step = (t1 - t0) * 1e3 / steps
+    log(f"[bench] metric mode: {ms_step:.4f} ms/step, metric list {m_ms:.4f} ms, final nnz {nnz}")
+    return {"rc2": rc2, "steps": steps, "ms_per_step": ms_step, "metric_list_ms": m_ms,
+            "particle_steps_per_s": n / (ms_step * 1e-3), "final_mean_degree": nnz / n,
+            "metric_list_roofline_frac": (8 + 4 + 4 * nnz / n) * n / (m_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def bench_batched(args, torch, nm, workloads):
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    box, k = workloads.BOX, 7
+    sizes = [int(v) for v in workloads.batched_sizes(512)]
+    total = sum(sizes)
+    xs, ys, ts = [], [], []
+    for s, n in enumerate(sizes):
+        x, y, _ = workloads.uniform(n, seed_pos=10_000 + s)
+        xs.append(x)
+        ys.append(y)
+        ts.append(workloads.headings(n, seed=20_000 + s))
+    p = nm.make_params(box, v0=64, eta=0.2, include_self=1, seed=workloads.NOISE_SEED)
+    b = nm.Batch(sizes, np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), k, p, device=dev)
+    t0 = time.perf_counter()
+    b.tune(reps=3)
+    tune_s = time.perf_counter() - t0
+    b.step(3, use_graph=True)
+    torch.cuda.synchronize()
+    if b.check() != 0:
+        raise RuntimeError("device error in batched warm-up")
+    steps = args.batched_steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record()
+        b.step(1, use_graph=True)
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if b.check() != 0:
+        raise RuntimeError("device error in batched steps")
+    lat = [a.elapsed_time(e) for a, e in ev]
+    ms_step = (t1 - t0) * 1e3 / steps
+    widths = sorted({b.grid(s).cell_w for s in range(len(sizes))})
+    b.close()
+    log(f"[bench] batched: {len(sizes)} systems, {total} particles, {ms_step:.4f} ms/step "
+        f"(p50 {pct(lat, 50):.4f}, p99 {pct(lat, 99):.4f}), tune {tune_s:.2f} s")
+
+    # Baseline: the plain one-system calls for every system, eager and captured.
+    systems = [nm.System.create(xs[s], ys[s], ts[s], k, nm.make_params(box, 64, 0.2, 1, workloads.NOISE_SEED, s),
+                                device=dev) for s in range(len(sizes))]
+    plain_steps = max(3, steps // 5)
+    for sysm in systems:
+        sysm.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(plain_steps):
+        for sysm in systems:
+            sysm.step()
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3 / plain_steps
+    outs = [(torch.empty_like(s.x), torch.empty_like(s.y), torch.empty_like(s.theta)) for s in systems]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for sysm, (xo, yo, to) in zip(systems, outs):
+            nm.step(sysm.ws, sysm.x, sysm.y, sysm.theta, k, sysm.params, 0, sysm.nbr, xo, yo, to)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(plain_steps):
+        g.replay()
+    torch.cuda.synchronize()
+    plain_graph_ms = (time.perf_counter() - t0) * 1e3 / plain_steps
+    for sysm in systems:
+        if nm.check(sysm.ws) != 0:
+            raise RuntimeError("device error in plain per-system steps")
+    log(f"[bench] plain per-system: eager {plain_ms:.4f} ms/step, graph {plain_graph_ms:.4f} ms/step")
+    del g, systems, outs
+    torch.cuda.empty_cache()
+    return {"systems": len(sizes), "particles": total, "k": k, "steps": steps,
+            "ms_per_step": ms_step, "particle_steps_per_s": total / (ms_step * 1e-3),
+            "step_latency_ms_p50": pct(lat, 50), "step_latency_ms_p99": pct(lat, 99),
+            "roofline_frac": (24 + 4 * k) * total / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "cell_widths": widths, "tune_seconds": tune_s,
+            "plain_eager_ms_per_step": plain_ms, "plain_graph_ms_per_step": plain_graph_ms,
+            "speedup_vs_plain_eager": plain_ms / ms_step, "speedup_vs_plain_graph": plain_graph_ms / ms_step}
+
+
+def bench_served(args, torch, nm, workloads):
+    srv = getattr(nm, "serve_stream", None)
+    if srv is None:
+        return None
+    return srv(rate_hz=200.0, duration_s=args.served_seconds, log=log)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the path is a "
+              "single-GPU build with no multi-GPU mode.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2103_10239_amd as nm
+    from paper_2103_10239_amd import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    n, k = args.n, args.k
+    r = bench_single(args, torch, nm, workloads)
+    value = n / (r["ms_step"] * 1e-3)
     bytes_per_ps = 24 + 4 * k
-    achieved = bytes_per_ps * n / (k_ms * 1e-3) / 1e9
+    achieved = bytes_per_ps * n / (r["k_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(n, k, r["cell_w"], r["block"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -169,34 +351,44 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int64/f64",
         "data": "synthetic",
         "config": {
-            "workload": f"uniform N={n}, L=2^20, k={k} kNN rebuild + Eq.2 align + Eq.1 move"
-                        + (f" + metric list r_c^2={rc2}" if rc2 is not None else "")
-                        + ", v0=64, eta=0.2, Philox seed 0, every list rebuilt every step",
-            "n": n, "k": k, "cell_w": cell_w, "box": box, "rc2": rc2,
+            "workload": f"uniform N={n} in a periodic box L=2^20, k={k}: per step cell binning, "
+                        "k-NN rebuild fused with Eq.2 alignment (vectorial noise eta=0.2) and Eq.1 move "
+                        "(v0=64), Philox seed 0, lists rebuilt every step",
+            "n": n, "k": k, "box": workloads.BOX, "cell_w": r["cell_w"], "block": r["block"],
         },
+        "neighbor_queries_per_s": value,
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_knn_align<{k}>",
+            "kernel": f"k_knn<{k},align>",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel_ms": k_ms,
-            "bytes_per_particle_step": bytes_per_ps,
+            "traffic": traffic,
+            "bytes_per_unit": bytes_per_ps,
+            "units_per_launch": n,
+            "kernel_ms_avg": r["k_ms"],
+            "kernel_ms_p50": r["k_p50"],
+            "kernel_ms_p99": r["k_p99"],
         },
-        "step_roofline_frac": bytes_per_ps * n / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "step_roofline_frac": bytes_per_ps * n / (r["ms_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
+    if not args.no_metric:
+        out["metric_list"] = bench_metric(args, torch, nm, workloads)
+    if not args.no_batched:
+        out["batched"] = bench_batched(args, torch, nm, workloads)
+    if not args.no_served:
+        out["served"] = bench_served(args, torch, nm, workloads)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(x, y, th, k, rc2, box, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(r["x"], r["y"], r["th"], k, workloads.BOX, args.cpu_seconds)
         log(f"[bench] cpu baseline {out['cpu_baseline']['value']:.3g} particle-steps/s")
     print(json.dumps(out), flush=True)
 

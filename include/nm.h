@@ -182,6 +182,19 @@ int nm_knn_align(const nm_grid* g, const void* ws, int32_t k, const nm_params* p
  * last check (NM_OK if none) and clear it. */
 int nm_check(void* ws, void* stream);
 
+/* Autotuner of the one-system step: for each of the ncand candidate grids
+ * (same n and box; cell width and block may differ) time `reps` steps of
+ * nm_bin_step + nm_knn_align on the given state (after one untimed step) and
+ * store the index of the fastest in *best and, if ms_out != NULL, the mean
+ * milliseconds per step of each candidate in ms_out[ncand].  `ws` must hold
+ * nm_workspace_bytes of every candidate; it is left initialised for the
+ * chosen grid.  The outputs are scratch (they receive tuning steps).
+ * Synchronises `stream`. */
+int nm_tune_grid(const nm_grid* cand, int32_t ncand, const int32_t* x, const int32_t* y,
+                 const float* theta, int32_t k, const nm_params* p, uint64_t step, void* ws,
+                 size_t ws_bytes, int32_t* nbr, int32_t* x_out, int32_t* y_out, float* theta_out,
+                 int32_t reps, int32_t* best, float* ms_out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched form: many independent systems of uneven size, all advanced by
  * the step of nm_step (Alg. 1 with the k-NN rule, Eq. (2), Eq. (1)), one

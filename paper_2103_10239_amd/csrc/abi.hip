@@ -248,6 +248,51 @@ int nm_step(const nm_grid* g, const int32_t* x, const int32_t* y, const float* t
   return nm_knn_align(g, ws, k, p, theta, nbr, x_out, y_out, theta_out, stream);
 }
 
+int nm_tune_grid(const nm_grid* cand, int32_t ncand, const int32_t* x, const int32_t* y,
+                 const float* theta, int32_t k, const nm_params* p, uint64_t step, void* ws,
+                 size_t ws_bytes, int32_t* nbr, int32_t* x_out, int32_t* y_out, float* theta_out,
+                 int32_t reps, int32_t* best, float* ms_out, void* stream) {
+  if (cand == nullptr || ncand < 1 || reps < 1 || best == nullptr) return NM_E_INVAL;
+  for (int c = 0; c < ncand; ++c) {
+    Layout lay;
+    if (!ws_ok(&cand[c], ws, ws_bytes, &lay) || cand[c].n != cand[0].n || cand[c].box != cand[0].box)
+      return NM_E_INVAL;
+  }
+  hipStream_t s = as_stream(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return NM_E_DEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return NM_E_DEVICE;
+  }
+  int rc = NM_OK, arg = -1;
+  float best_ms = 0.0f;
+  for (int c = 0; c < ncand && rc == NM_OK; ++c) {
+    rc = nm_workspace_init(&cand[c], ws, ws_bytes, stream);
+    if (rc == NM_OK)
+      rc = nm_step(&cand[c], x, y, theta, k, p, step, ws, ws_bytes, nbr, x_out, y_out, theta_out, stream);
+    if (rc == NM_OK && hipEventRecord(e0, s) != hipSuccess) rc = NM_E_DEVICE;
+    for (int t = 0; t < reps && rc == NM_OK; ++t)
+      rc = nm_step(&cand[c], x, y, theta, k, p, step, ws, ws_bytes, nbr, x_out, y_out, theta_out, stream);
+    float ms = 0.0f;
+    if (rc == NM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = NM_E_DEVICE;
+    if (rc == NM_OK) rc = nm_check(ws, stream);
+    ms /= static_cast<float>(reps);
+    if (ms_out) ms_out[c] = ms;
+    if (rc == NM_OK && (arg < 0 || ms < best_ms)) {
+      best_ms = ms;
+      arg = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != NM_OK) return rc;
+  *best = arg;
+  return nm_workspace_init(&cand[arg], ws, ws_bytes, stream);
+}
+
 int nm_check(void* ws, void* stream) {
   if (ws == nullptr) return NM_E_INVAL;
   hipStream_t s = as_stream(stream);

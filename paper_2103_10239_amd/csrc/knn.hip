@@ -261,12 +261,16 @@ __device__ __forceinline__ int pack_rel(int rx, int ry) {
 }
 
 // Block search on the staged tile.  (cx, cy): home cell in halo coordinates,
-// self: the query's LDS index, pq: its packed relative position.
-template <int KMAX>
+// self: the query's LDS index, pq: its relative position (packed 16-bit pair;
+// wide tiles: the x offset, with the y offset in pqy and staged points as
+// int32 pairs).
+template <int KMAX, bool kWide>
 __device__ __forceinline__ bool knn_lds(const DevWs& w, const FastCfg& f, const TileCfg& tc,
                                         const int* lcell, const int* lpos, const int* lslot, int W,
-                                        int cx, int cy, int self, int pq, int qx, int qy, int k,
-                                        int (&slot)[KMAX]) {
+                                        int cx, int cy, int self, int pq, int pqy, int qx, int qy,
+                                        int k, int (&slot)[KMAX]) {
+  constexpr int kPts = kWide ? kTilePts / 2 : kTilePts;
+  const int2* lpos2 = reinterpret_cast<const int2*>(lpos);
   constexpr int KT = KMAX + 1;
   int B = f.bfix;
   if (B == 0) {
@@ -297,18 +301,34 @@ __device__ __forceinline__ bool knn_lds(const DevWs& w, const FastCfg& f, const 
       i = lcell[row0 + r * W];
       e = lcell[row0 + r * W + B];
     }
-    int pc = lpos[min(i, kTilePts - 1)];  // (no candidate at all: a harmless in-bounds read)
+    // (with no candidate at all, the first read is a harmless in-bounds one)
+    int pc = 0;
+    int2 pc2 = make_int2(0, 0);
+    if (kWide)
+      pc2 = lpos2[min(i, kPts - 1)];
+    else
+      pc = lpos[min(i, kPts - 1)];
     for (int c = 0; c < ncand; ++c) {
       const int icur = i, pcur = pc;
+      const int2 pcur2 = pc2;
       ++i;
       while (i == e && r + 1 < B) {
         ++r;
         i = lcell[row0 + r * W];
         e = lcell[row0 + r * W + B];
       }
-      pc = lpos[min(i, kTilePts - 1)];
-      const uint32_t d2 = static_cast<uint32_t>(rel_d2(pcur, pq));
-      const uint32_t kk = ((min(d2, clampd) >> sh) << 13) | static_cast<uint32_t>(icur);
+      uint32_t kk;
+      if (kWide) {
+        pc2 = lpos2[min(i, kPts - 1)];
+        const long long dx = pcur2.x - pq, dy = pcur2.y - pqy;
+        const unsigned long long d2 = static_cast<unsigned long long>(dx * dx + dy * dy);
+        kk = (static_cast<uint32_t>(min(d2, static_cast<unsigned long long>(b.bound)) >> sh) << 13) |
+             static_cast<uint32_t>(icur);
+      } else {
+        pc = lpos[min(i, kPts - 1)];
+        const uint32_t d2 = static_cast<uint32_t>(rel_d2(pcur, pq));
+        kk = ((min(d2, clampd) >> sh) << 13) | static_cast<uint32_t>(icur);
+      }
       net_insert(key, icur == self ? kKey32Inf : kk);
     }
     const uint32_t kth = key[KT - 2];
@@ -457,7 +477,8 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
                                               long long* __restrict__ d2out, const AlignArgs& a,
                                               int tile) {
   __shared__ int lcell[kTileCells + 1];
-  __shared__ int lpos[kTilePts];
+  __shared__ int2 lpos_store[kTilePts / 2];  // packed 16-bit pairs, or int32 pairs (wide)
+  int* lpos = reinterpret_cast<int*>(lpos_store);
   __shared__ int lslot[kTilePts];
   __shared__ int s_qoff[kTileRows + 1];   // query prefix over the tile's rows
   __shared__ int s_qbeg[kTileRows];       // first slot of each tile row
@@ -531,7 +552,8 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   __syncthreads();
   const int nq = s_qoff[tb.ty];
   if (nq == 0) return;
-  const bool staged = h > 0 && s_rbase[R] <= kTilePts;
+  const bool wide = tc.wide != 0;
+  const bool staged = h > 0 && s_rbase[R] <= (wide ? kTilePts / 2 : kTilePts);
   if (staged) {
     // Cell table: LDS offset of every halo cell, from the start table.
     for (int c = threadIdx.x; c <= R * W; c += kBlock) {
@@ -559,7 +581,10 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
       const int v = tb.y0 - h + rho;
       const int sy = (v < 0 ? -L : (v >= G ? L : 0)) - oy0;
       const int2 e = reinterpret_cast<const int2*>(w.sorted)[2 * src];
-      lpos[pidx] = pack_rel(e.x + s_psx[rho][pi], e.y + sy);
+      if (wide)
+        lpos_store[pidx] = make_int2(e.x + s_psx[rho][pi], e.y + sy);
+      else
+        lpos[pidx] = pack_rel(e.x + s_psx[rho][pi], e.y + sy);
       lslot[pidx] = src;
     }
     __syncthreads();
@@ -578,8 +603,10 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
       const int cx = (q.x >> w.log2_w) - uL, cy = rq + h;
       const int64_t hc = static_cast<int64_t>(tb.y0 + rq) * G + (q.x >> w.log2_w);
       const int self = lcell[cy * W + cx] + (s - w.start[hc]);
-      ok = knn_lds<KMAX>(w, f, tc, lcell, lpos, lslot, W, cx, cy, self,
-                         pack_rel(q.x - ox0, q.y - oy0), q.x, q.y, k, slot);
+      ok = wide ? knn_lds<KMAX, true>(w, f, tc, lcell, lpos, lslot, W, cx, cy, self, q.x - ox0,
+                                      q.y - oy0, q.x, q.y, k, slot)
+                : knn_lds<KMAX, false>(w, f, tc, lcell, lpos, lslot, W, cx, cy, self,
+                                       pack_rel(q.x - ox0, q.y - oy0), 0, q.x, q.y, k, slot);
     } else {
       ok = knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot);
     }
@@ -601,7 +628,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   // each lane searches its own; with a few, a wavefront searches one at a
   // time, so that a single long search is not one lane's serial chain.
   const int nl = min(nd, kDeferCap);
-  if (nl >= 64) {
+  if (nl > 16) {
     for (int j = threadIdx.x; j < nl; j += kBlock) exact_lane<KMAX, kAlign>(w, s_dq[j], k, total, nbr, d2out, a);
   } else {
     for (int j = threadIdx.x >> 6; j < nl; j += kBlock / 64) {
@@ -687,20 +714,41 @@ __global__ __launch_bounds__(kBlock) void k_bb_knn(BatchRef b, int k) {
 // at about 256 queries; the halo must span under 2^15 grid units for the
 // 16-bit offsets, and must not meet itself around the box.
 TileCfg tile_cfg_impl(const DevWs& w, const FastCfg& f, int k) {
-  TileCfg t{1, 0, w.G, 0};
+  TileCfg t{1, 0, w.G, 0, 0};
   const double rho = static_cast<double>(w.n) / static_cast<double>(w.C);  // particles per cell
-  const double rk = sqrt(static_cast<double>(k) / (3.141592653589793 * (rho > 1e-12 ? rho : 1e-12)));
+  const double rr = rho > 1e-12 ? rho : 1e-12;
+  const double rk = sqrt(static_cast<double>(k) / (3.141592653589793 * rr));
   const int bexp = (f.bfix > 0 ? f.bfix : static_cast<int>(ceil(2.0 * f.reach * rk)) + 1) + 2;
+  const int side0 = max(1, min(static_cast<int>(lround(sqrt(256.0 / rr))), w.G));
+  // Narrow tiles: packed 16-bit offsets, the halo spans under 2^15 units.
   int h = f.bmax > 0 ? min((bexp + 1) / 2, (f.bmax + 1) / 2) : 0;
   while (h > 0 && (w.G < 2 * h + 2 || ((static_cast<long long>(2 * h + 1) << w.log2_w) > 32768))) --h;
-  int side = static_cast<int>(lround(sqrt(256.0 / (rho > 1e-12 ? rho : 1e-12))));
-  side = max(1, min(side, w.G));
+  int side = side0;
   if (h > 0) {
     while (side > 1 && ((static_cast<long long>(side + 2 * h) << w.log2_w) > 32768 || side + 2 * h > kTileRows ||
                         (side + 2 * h) * (side + 2 * h) > kTileCells ||
                         (side + 2 * h) * (side + 2 * h) * rho > 0.75 * kTilePts))
       --side;
     if ((static_cast<long long>(side + 2 * h) << w.log2_w) > 32768 || side + 2 * h > kTileRows) h = 0;
+  }
+  // A halo of at least the expected block that narrow offsets cannot span:
+  // wide tiles (int32 offset pairs, half as many staged points).
+  const int hw = f.bmax_w > 0 ? min((bexp + 1) / 2, (f.bmax_w + 1) / 2) : 0;
+  if (h < hw && 2 * h + 1 < bexp) {
+    int h2 = hw;
+    while (h2 > 0 && w.G < 2 * h2 + 2) --h2;
+    int s2 = side0;
+    while (s2 > 1 && (s2 + 2 * h2 > kTileRows || (s2 + 2 * h2) * (s2 + 2 * h2) > kTileCells ||
+                      (s2 + 2 * h2) * (s2 + 2 * h2) * rho > 0.375 * kTilePts))
+      --s2;
+    if (h2 > 0 && s2 + 2 * h2 <= kTileRows && (s2 + 2 * h2) * (s2 + 2 * h2) <= kTileCells) {
+      t.t = s2;
+      t.h = h2;
+      t.ntx = (w.G + s2 - 1) / s2;
+      t.bmax = min(2 * h2 + 1, f.bmax_w);
+      t.wide = 1;
+      return t;
+    }
   }
   if (h == 0) side = max(1, min(side, kTileRows));
   t.t = side;
@@ -756,17 +804,21 @@ hipError_t launch_batch_knn(const BatchRef& b, int k, hipStream_t s) {
 // side, 0 picks it per query, < 0 disables the fast path.
 FastCfg fast_cfg(const DevWs& w, int k, int block) {
   (void)k;
-  FastCfg f{0, 0, 1.6f};
+  FastCfg f{0, 0, 1.6f, 0};
   if (block < 0) return f;
-  int bmax = kMaxB;
-  while (bmax >= 3 && ((static_cast<long long>((bmax >> 1) + 1) << w.log2_w) >= 32768 || bmax + 2 > w.G))
-    --bmax;
-  if (bmax < 3) return f;
-  f.bmax = bmax;
+  int bw = kMaxB;  // any span (64-bit distances): the block must not meet itself
+  while (bw >= 3 && bw + 2 > w.G) --bw;
+  if (bw < 3) return f;
+  int bmax = bw;
+  while (bmax >= 3 && (static_cast<long long>((bmax >> 1) + 1) << w.log2_w) >= 32768) --bmax;
+  if (bmax < 3) bmax = 0;
   if (block > 0) {
-    if (block > bmax) return FastCfg{0, 0, 1.6f};
+    if (block > bw) return f;
     f.bfix = block;
+    if (block > bmax) bmax = 0;
   }
+  f.bmax = bmax;
+  f.bmax_w = bw;
   return f;
 }
 

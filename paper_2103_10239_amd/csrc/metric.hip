@@ -190,8 +190,8 @@ FastCfg metric_cfg(const DevWs& w, long long rc2) {
   const double rc = sqrt(static_cast<double>(rc2));
   const int cw = 1 << w.log2_w;
   const int B = 2 * static_cast<int>(ceil((rc + 1.0) / cw)) + 1;
-  if (lim.bmax == 0 || B > lim.bmax) return FastCfg{0, 0, 0.0f};
-  return FastCfg{lim.bmax, B, 0.0f};
+  if (lim.bmax == 0 || B > lim.bmax) return FastCfg{0, 0, 0.0f, 0};
+  return FastCfg{lim.bmax, B, 0.0f, 0};
 }
 
 }  // namespace

@@ -278,9 +278,10 @@ constexpr uint32_t kKey32Inf = 0xFFFFFFFFu;
 constexpr int kDBits = 19;  // distance field of a 32-bit key
 
 struct FastCfg {
-  int bmax;    // largest block side (0 disables the fast path)
+  int bmax;    // largest block side of 32-bit distances (0 disables the fast path)
   int bfix;    // fixed block side, or 0 to pick it per query from density
   float reach; // distance to the block edge, in mean k-th-neighbour radii
+  int bmax_w;  // largest block side of the 64-bit-distance ("wide") tiles
 };
 
 __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
@@ -427,6 +428,8 @@ struct TileCfg {
   int h;     // halo in cells (0: no staging)
   int ntx;   // tiles per side
   int bmax;  // largest block side the halo supports
+  int wide;  // 1: staged offsets are int32 pairs and distances 64-bit (halo
+             // spans 2^15 units or more); 0: packed 16-bit offsets
 };
 
 // Parameters and outputs of the fused Eq. (2) / Eq. (1) epilogue.

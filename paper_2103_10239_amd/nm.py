@@ -75,6 +75,9 @@ def lib():
     L.nm_bin_step.argtypes = [gp, _vp, _vp, _vp, pp, _c_u64, _vp, ctypes.c_size_t, _vp]
     L.nm_knn_align.argtypes = [gp, _vp, _c_i32, pp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.nm_check.argtypes = [_vp, _vp]
+    L.nm_tune_grid.argtypes = [gp, _c_i32, _vp, _vp, _vp, _c_i32, pp, _c_u64, _vp, ctypes.c_size_t,
+                               _vp, _vp, _vp, _vp, _c_i32, ctypes.POINTER(_c_i32),
+                               ctypes.POINTER(ctypes.c_float), _vp]
     L.nm_batch_plan.argtypes = [_c_i32, ctypes.POINTER(_c_i32), _c_i32, _c_i32, pp,
                                 ctypes.POINTER(_c_u32), ctypes.POINTER(_vp), ctypes.POINTER(_c_i64)]
     L.nm_batch_bind.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(BatchIO), _c_u64, _vp]
@@ -85,7 +88,7 @@ def lib():
     L.nm_batch_check.argtypes = [_vp, _vp]
     L.nm_batch_destroy.argtypes, L.nm_batch_destroy.restype = [_vp], None
     for f in ("nm_workspace_init", "nm_build_cells", "nm_knn", "nm_metric_list", "nm_align_step",
-              "nm_step", "nm_bin_step", "nm_knn_align", "nm_check", "nm_batch_plan", "nm_batch_bind",
+              "nm_step", "nm_bin_step", "nm_knn_align", "nm_check", "nm_tune_grid", "nm_batch_plan", "nm_batch_bind",
               "nm_batch_step", "nm_batch_tune", "nm_batch_system", "nm_batch_check"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
@@ -132,13 +135,15 @@ def make_params(box: int, v0: int = 64, eta: float = 0.2, include_self: int = 1,
 class Workspace:
     """Device workspace of one system's cell grid (owned by torch)."""
 
-    def __init__(self, n: int, box: int, cell_w: int | None = None, device="cuda", block: int = 0):
+    def __init__(self, n: int, box: int, cell_w: int | None = None, device="cuda", block: int = 0,
+                 nbytes: int | None = None):
         if cell_w is None:
             cell_w = suggest_cell_w(n, box)
         self.grid = Grid(n, box, cell_w, block)
-        nbytes = int(lib().nm_workspace_bytes(ctypes.byref(self.grid)))
-        if nbytes < 0:
-            raise NMError(nbytes, f"workspace_bytes(n={n}, box={box}, cell_w={cell_w})")
+        need = int(lib().nm_workspace_bytes(ctypes.byref(self.grid)))
+        if need < 0:
+            raise NMError(need, f"workspace_bytes(n={n}, box={box}, cell_w={cell_w})")
+        nbytes = max(need, int(nbytes or 0))
         self.device = torch.device(device)
         self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.nbytes = nbytes
@@ -252,6 +257,30 @@ def knn_align(ws: Workspace, k: int, params: Params, theta, nbr, x_out, y_out, t
                            _dev(x_out, torch.int32, n, "x_out"), _dev(y_out, torch.int32, n, "y_out"),
                            _dev(theta_out, torch.float32, n, "theta_out"), _stream(ws.device)),
         "knn_align")
+
+
+def tune_grid(n: int, box: int, x, y, theta, k: int, params: Params, step_index: int = 0,
+              cell_ws=None, blocks=(0,), reps: int = 5, device="cuda"):
+    """Time the one-system step over candidate grids (cell widths x block sides)
+    on the given state; returns (Workspace for the fastest grid, {(w, block): ms})."""
+    if cell_ws is None:
+        cell_ws = sorted({suggest_cell_w(n, box, pc) for pc in (1.0, 2.0, 4.0)})
+    cands = [(int(w), int(b)) for w in cell_ws for b in blocks]
+    arr = (Grid * len(cands))(*[Grid(n, box, w, b) for w, b in cands])
+    need = max(int(lib().nm_workspace_bytes(ctypes.byref(g))) for g in arr)
+    ws = Workspace(n, box, cands[0][0], device, block=cands[0][1], nbytes=need)
+    dev = ws.device
+    nbr = torch.empty(n * k, dtype=torch.int32, device=dev)
+    xo, yo = torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev)
+    to = torch.empty(n, dtype=torch.float32, device=dev)
+    best, ms = _c_i32(), (ctypes.c_float * len(cands))()
+    _ok(lib().nm_tune_grid(arr, len(cands), _dev(x, torch.int32, n, "x"), _dev(y, torch.int32, n, "y"),
+                           _dev(theta, torch.float32, n, "theta"), k, ctypes.byref(params), step_index,
+                           ws.ptr, ws.nbytes, nbr.data_ptr(), xo.data_ptr(), yo.data_ptr(), to.data_ptr(),
+                           reps, ctypes.byref(best), ms, _stream(dev)), "tune_grid")
+    w, b = cands[best.value]
+    ws.grid = Grid(n, box, w, b)
+    return ws, {c: float(m) for c, m in zip(cands, ms)}
 
 
 def check(ws: Workspace) -> int:

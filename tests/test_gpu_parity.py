@@ -343,6 +343,41 @@ def test_knn_every_search_path_matches_oracle(kind, n, k, w, block):
     assert np.array_equal(nbr, rn) and np.array_equal(d2, rd)
 
 
+# Sparse systems (mean spacing several thousand units): the k-NN halo spans
+# more than 2^15 units, so the staged tiles hold int32 offset pairs and the
+# block search uses 64-bit squared distances.
+WIDE_CASES = [("uniform", 16384, 7, 16384, 0), ("uniform", 16384, 12, 8192, 0),
+              ("uniform", 4096, 7, 32768, 0), ("clustered", 16384, 7, 8192, 0),
+              ("uniform", 16384, 20, 16384, 5), ("uniform", 3001, 1, 65536, 0),
+              ("uniform", 16384, 7, 8192, 9), ("squeezed", 3000, 7, 16384, 0)]
+
+
+@pytest.mark.parametrize("kind,n,k,w,block", WIDE_CASES)
+def test_knn_wide_tiles_match_oracle(kind, n, k, w, block):
+    x, y, _ = _gen(kind, n)
+    if kind == "squeezed":  # duplicates and ties spread over a sparse box
+        x, y = (x * 37) % L, (y * 53) % L
+    nbr, d2 = _gpu_knn_block(x, y, k, w, block)
+    rn, rd = oracle.knn(x, y, L, k)
+    assert np.array_equal(nbr, rn) and np.array_equal(d2, rd)
+
+
+@pytest.mark.parametrize("kind,n,k,w,block", WIDE_CASES[:4])
+def test_fused_step_wide_tiles_match_oracle(kind, n, k, w, block):
+    x, y, th = _gen(kind, n)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    ws = nm.Workspace(n, L, w, block=block)
+    X, Y, T = _dev(x, torch.int32), _dev(y, torch.int32), _dev(th, torch.float32)
+    nbr = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    out = (torch.empty_like(X), torch.empty_like(Y), torch.empty_like(T))
+    nm.step(ws, X, Y, T, k, p, 0, nbr, *out)
+    assert nm.check(ws) == 0
+    rn, rx, ry, rt = oracle.step(x, y, th, L, k, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    assert np.array_equal(nbr.cpu().numpy(), rn)
+    assert np.array_equal(out[0].cpu().numpy(), rx) and np.array_equal(out[1].cpu().numpy(), ry)
+    assert _angle_err(out[2].cpu().numpy(), rt).max() <= TOL
+
+
 @pytest.mark.parametrize("block", [-1, 0, 4, 6])
 def test_knn_lattice_ties_every_path(block):
     # every distance is tied: the fast path must always hand over to the exact search
