@@ -265,6 +265,77 @@ int nm_batch_check(nm_batch* b, void* stream);
 
 void nm_batch_destroy(nm_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Served form: a request loop over jobs of different sizes.  Each job is a
+ * system (n particles, k nearest neighbours, nsteps steps of nm_step from its
+ * initial state, its own Philox seed and sys_id, step counter from 0).  The
+ * server keeps admitted jobs' state on the device and advances all of them
+ * together, one step per engine iteration (continuous batching: jobs that
+ * arrive while others run join at the next iteration, finished jobs leave).
+ * Admission is FIFO under a byte budget of device memory counted per job as
+ * nm_server_job_bytes (workspace, double-buffered state, list).  A job's
+ * results equal those of nm_step on that job alone: lists and positions
+ * bit-exact, headings bit-exact as well (same kernels and arithmetic).
+ * The server runs two host threads of its own and two HIP streams on the
+ * device current at nm_server_create; it allocates device memory in slabs
+ * (1 GiB or one job) that it keeps until destroyed.
+ * ------------------------------------------------------------------------ */
+typedef struct nm_server nm_server; /* opaque */
+
+typedef struct nm_job {
+  int32_t n;          /* particles, k + 1 <= n <= 2^24                          */
+  int32_t k;          /* 1 <= k <= NM_MAX_K                                     */
+  int32_t nsteps;     /* >= 1                                                   */
+  int32_t want_nbr;   /* 1: keep the lists of the last step for nm_server_wait */
+  nm_params p;        /* Eq. (1)-(2) parameters, box, seed, sys_id              */
+  const int32_t* x;   /* HOST int32[n], initial positions in [0, box)           */
+  const int32_t* y;
+  const float* theta; /* HOST fp32[n], initial headings                         */
+} nm_job;
+
+typedef struct nm_job_result {
+  int32_t status;     /* NM_OK or the first error of the job                    */
+  int32_t steps;      /* steps taken                                            */
+  double submit_s;    /* seconds since nm_server_create: submitted,             */
+  double admit_s;     /*   admitted to the device,                              */
+  double done_s;      /*   final state copied back to the host                  */
+} nm_job_result;
+
+typedef struct nm_server_info {
+  int64_t submitted, completed, iterations;
+  int64_t budget_bytes, used_bytes, peak_used_bytes; /* ledger                  */
+  int64_t reserved_bytes;                            /* device slabs held       */
+  int32_t active, peak_active, queued, status;       /* status: engine errors   */
+  double now_s;
+} nm_server_info;
+
+/* Ledger bytes of a job (its admission cost), or < 0 if invalid. */
+int64_t nm_server_job_bytes(int32_t n, int32_t k, int32_t box);
+
+/* Start a server with a device-memory budget and at most max_slots jobs on
+ * the device at once. */
+int nm_server_create(int64_t budget_bytes, int32_t max_slots, nm_server** out);
+
+/* Queue a job (its host inputs are copied before returning).  NM_E_NOMEM if
+ * the job alone exceeds the budget; *id names it for poll/wait. */
+int nm_server_submit(nm_server* s, const nm_job* job, int64_t* id);
+
+/* 1 if job id has finished, 0 if not yet, NM_E_INVAL if unknown. */
+int nm_server_poll(nm_server* s, int64_t id);
+
+/* Block until job id finishes, copy its final state (and lists) into the
+ * HOST arrays given (each may be NULL), fill *r (may be NULL) and forget the
+ * job.  Returns the job's status. */
+int nm_server_wait(nm_server* s, int64_t id, int32_t* x, int32_t* y, float* theta, int32_t* nbr,
+                   nm_job_result* r);
+
+/* Counters and ledger of the server (a snapshot). */
+int nm_server_stats(nm_server* s, nm_server_info* out);
+
+/* Finish every queued and running job, then stop the threads and release
+ * the device memory.  Results not collected are dropped. */
+void nm_server_destroy(nm_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(objdir, exist_ok=True)
     common = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
               "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-Wall", "-Wno-unused-function"]
+              "-pthread", "-Wall", "-Wno-unused-function"]
     procs, objs = [], []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
@@ -42,7 +42,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
     tmp = LIB + ".tmp%d" % os.getpid()
-    link = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    link = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)

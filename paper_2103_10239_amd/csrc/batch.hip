@@ -20,7 +20,7 @@
 #include <map>
 #include <vector>
 
-#include "nm_internal.h"
+#include "batch_host.h"
 
 namespace nm {
 
@@ -54,6 +54,60 @@ hipError_t launch_batch_advance(const BatchRef& b, hipStream_t s) {
   hipLaunchKernelGGL(k_bb_advance, dim3((b.nsys + kBlock - 1) / kBlock), dim3(kBlock), 0, s, b.sys,
                      b.nsys);
   return hipGetLastError();
+}
+
+BatchSys make_batch_sys(const SysSpec& s, int k) {
+  BatchSys d{};
+  Layout lay;
+  make_layout(&s.g, &lay);
+  d.w = dev_ws(&s.g, lay, s.ws);
+  d.f = fast_cfg(d.w, k, s.g.block);
+  d.tc = tile_cfg(d.w, d.f, k);
+  for (int t = 0; t < 2; ++t) {
+    d.x[t] = s.x[t];
+    d.y[t] = s.y[t];
+    d.th[t] = s.th[t];
+  }
+  d.nbr = s.nbr;
+  d.v0 = s.v0;
+  d.eta = s.eta;
+  d.include_self = s.include_self;
+  d.sys_id = s.sys_id;
+  d.seed_lo = static_cast<uint32_t>(s.seed);
+  d.seed_hi = static_cast<uint32_t>(s.seed >> 32);
+  d.step_lo = static_cast<uint32_t>(s.step);
+  d.step_hi = static_cast<uint32_t>(s.step >> 32);
+  d.parity = s.parity;
+  d.ntiles = d.tc.ntx * d.tc.ntx;
+  const int64_t big = std::max<int64_t>(lay.C, s.g.n);
+  d.nitems[kStInit] = static_cast<int32_t>(
+      std::max<int64_t>(1, std::min<int64_t>(64, (big + 4 * kBlock - 1) / (4 * kBlock))));
+  d.nitems[kStCount] = (s.g.n + kBlock - 1) / kBlock;
+  d.nitems[kStScan] = lay.nb_scan_c;
+  d.nitems[kStScatter] = (s.g.n + 4 * kBlock - 1) / (4 * kBlock);
+  d.nitems[kStKnn] = d.ntiles;
+  return d;
+}
+
+void batch_items(std::vector<BatchSys>& sys, std::vector<int32_t>& items, int32_t begin[kStages + 1]) {
+  items.clear();
+  for (int st = 0; st < kStages; ++st) {
+    begin[st] = static_cast<int32_t>(items.size());
+    for (size_t q = 0; q < sys.size(); ++q) {
+      sys[q].base[st] = static_cast<int32_t>(items.size()) - begin[st];
+      items.insert(items.end(), sys[q].nitems[st], static_cast<int32_t>(q));
+    }
+  }
+  begin[kStages] = static_cast<int32_t>(items.size());
+}
+
+hipError_t enqueue_batch_step(const BatchRef& r, int k, bool advance, hipStream_t s) {
+  hipError_t e = launch_batch_bin(r, kStCount, s);
+  if (e == hipSuccess) e = launch_batch_bin(r, kStScan, s);
+  if (e == hipSuccess) e = launch_batch_bin(r, kStScatter, s);
+  if (e == hipSuccess) e = launch_batch_knn(r, k, s);
+  if (e == hipSuccess && advance) e = launch_batch_advance(r, s);
+  return e;
 }
 
 }  // namespace nm
@@ -111,56 +165,31 @@ nm_grid grid_of(const nm_batch* b, int s) {
   return g;
 }
 
-// Work items of every stage for the systems in `which` (in that order);
-// fills the descriptors' item ranges and returns the item table.
+// Descriptors and work items for the systems in `which` (in that order).
 void build_tables(nm_batch* b, const std::vector<int>& which, std::vector<BatchSys>& sys,
                   std::vector<int32_t>& items, int32_t begin[kStages + 1]) {
-  sys.assign(which.size(), BatchSys{});
-  std::vector<std::vector<int32_t>> per(kStages);
-  for (size_t q = 0; q < which.size(); ++q) {
-    const int s = which[q];
-    const nm_grid g = grid_of(b, s);
-    Layout lay;
-    make_layout(&g, &lay);
-    BatchSys& d = sys[q];
-    d.w = dev_ws(&g, lay, b->ws + b->ws_off[s]);
-    d.f = fast_cfg(d.w, b->k, g.block);
-    d.tc = tile_cfg(d.w, d.f, b->k);
+  sys.clear();
+  for (int s : which) {
+    SysSpec sp{};
+    sp.g = grid_of(b, s);
+    sp.ws = b->ws + b->ws_off[s];
     const int64_t o = b->off[s];
     for (int t = 0; t < 2; ++t) {
-      d.x[t] = b->io.x[t] + o;
-      d.y[t] = b->io.y[t] + o;
-      d.th[t] = b->io.theta[t] + o;
+      sp.x[t] = b->io.x[t] + o;
+      sp.y[t] = b->io.y[t] + o;
+      sp.th[t] = b->io.theta[t] + o;
     }
-    d.nbr = b->io.nbr + o * b->k;
-    d.v0 = b->p.v0;
-    d.eta = b->p.eta;
-    d.include_self = b->p.include_self;
-    d.sys_id = b->sys_id[s];
-    d.seed_lo = static_cast<uint32_t>(b->p.seed);
-    d.seed_hi = static_cast<uint32_t>(b->p.seed >> 32);
-    const uint64_t step = b->step0 + static_cast<uint64_t>(b->steps_done);
-    d.step_lo = static_cast<uint32_t>(step);
-    d.step_hi = static_cast<uint32_t>(step >> 32);
-    d.parity = static_cast<int32_t>(b->steps_done & 1);
-    d.ntiles = d.tc.ntx * d.tc.ntx;
-    const int64_t big = std::max<int64_t>(lay.C, g.n);
-    d.nitems[kStInit] = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(64, (big + 4 * kBlock - 1) / (4 * kBlock))));
-    d.nitems[kStCount] = (g.n + kBlock - 1) / kBlock;
-    d.nitems[kStScan] = lay.nb_scan_c;
-    d.nitems[kStScatter] = (g.n + 4 * kBlock - 1) / (4 * kBlock);
-    d.nitems[kStKnn] = d.ntiles;
-    for (int st = 0; st < kStages; ++st) {
-      d.base[st] = static_cast<int32_t>(per[st].size());
-      per[st].insert(per[st].end(), d.nitems[st], static_cast<int32_t>(q));
-    }
+    sp.nbr = b->io.nbr + o * b->k;
+    sp.v0 = b->p.v0;
+    sp.eta = b->p.eta;
+    sp.include_self = b->p.include_self;
+    sp.seed = b->p.seed;
+    sp.sys_id = b->sys_id[s];
+    sp.step = b->step0 + static_cast<uint64_t>(b->steps_done);
+    sp.parity = static_cast<int32_t>(b->steps_done & 1);
+    sys.push_back(make_batch_sys(sp, b->k));
   }
-  items.clear();
-  for (int st = 0; st < kStages; ++st) {
-    begin[st] = static_cast<int32_t>(items.size());
-    items.insert(items.end(), per[st].begin(), per[st].end());
-  }
-  begin[kStages] = static_cast<int32_t>(items.size());
+  batch_items(sys, items, begin);
 }
 
 // Largest item count of one system over every tuner candidate.
@@ -202,15 +231,6 @@ hipError_t upload(nm_batch* b, const std::vector<BatchSys>& sys, const std::vect
 void drop_graph(nm_batch* b) {
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   b->graph = nullptr;
-}
-
-hipError_t enqueue_step(const BatchRef& r, int k, bool advance, hipStream_t s) {
-  hipError_t e = launch_batch_bin(r, kStCount, s);
-  if (e == hipSuccess) e = launch_batch_bin(r, kStScan, s);
-  if (e == hipSuccess) e = launch_batch_bin(r, kStScatter, s);
-  if (e == hipSuccess) e = launch_batch_knn(r, k, s);
-  if (e == hipSuccess && advance) e = launch_batch_advance(r, s);
-  return e;
 }
 
 // Tables for all systems with the current choices, uploaded, workspaces
@@ -318,7 +338,7 @@ int nm_batch_step(nm_batch* b, int32_t nsteps, int32_t use_graph, void* stream) 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (!use_graph) {
     for (int t = 0; t < nsteps; ++t)
-      if (enqueue_step(b->ref, b->k, true, s) != hipSuccess) return NM_E_DEVICE;
+      if (enqueue_batch_step(b->ref, b->k, true, s) != hipSuccess) return NM_E_DEVICE;
     b->steps_done += nsteps;
     return NM_OK;
   }
@@ -331,7 +351,7 @@ int nm_batch_step(nm_batch* b, int32_t nsteps, int32_t use_graph, void* stream) 
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
       return NM_E_DEVICE;
-    const hipError_t e = enqueue_step(b->ref, b->k, true, b->cap_stream);
+    const hipError_t e = enqueue_batch_step(b->ref, b->k, true, b->cap_stream);
     const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess || g == nullptr) {
       if (g) (void)hipGraphDestroy(g);
@@ -378,12 +398,12 @@ int nm_batch_tune(nm_batch* b, int32_t reps, void* stream) {
       build_tables(b, mem, sys, items, begin);
       if (upload(b, sys, items, begin, s) != hipSuccess ||
           launch_batch_bin(b->ref, kStInit, s) != hipSuccess ||
-          enqueue_step(b->ref, b->k, false, s) != hipSuccess || hipEventRecord(e0, s) != hipSuccess) {
+          enqueue_batch_step(b->ref, b->k, false, s) != hipSuccess || hipEventRecord(e0, s) != hipSuccess) {
         rc = NM_E_DEVICE;
         break;
       }
       for (int t = 0; t < reps && rc == NM_OK; ++t)
-        if (enqueue_step(b->ref, b->k, false, s) != hipSuccess) rc = NM_E_DEVICE;
+        if (enqueue_batch_step(b->ref, b->k, false, s) != hipSuccess) rc = NM_E_DEVICE;
       float ms = 0.0f;
       if (rc != NM_OK || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
           hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {

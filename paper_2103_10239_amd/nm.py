@@ -47,6 +47,24 @@ class BatchIO(ctypes.Structure):
     _fields_ = [("x", _vp * 2), ("y", _vp * 2), ("theta", _vp * 2), ("nbr", _vp)]
 
 
+class Job(ctypes.Structure):
+    """nm_job: one served job (host inputs, copied at submission)."""
+    _fields_ = [("n", _c_i32), ("k", _c_i32), ("nsteps", _c_i32), ("want_nbr", _c_i32), ("p", Params),
+                ("x", _vp), ("y", _vp), ("theta", _vp)]
+
+
+class JobResult(ctypes.Structure):
+    _fields_ = [("status", _c_i32), ("steps", _c_i32), ("submit_s", ctypes.c_double),
+                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("submitted", _c_i64), ("completed", _c_i64), ("iterations", _c_i64),
+                ("budget_bytes", _c_i64), ("used_bytes", _c_i64), ("peak_used_bytes", _c_i64),
+                ("reserved_bytes", _c_i64), ("active", _c_i32), ("peak_active", _c_i32),
+                ("queued", _c_i32), ("status", _c_i32), ("now_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -87,6 +105,16 @@ def lib():
     L.nm_batch_steps_done.argtypes, L.nm_batch_steps_done.restype = [_vp], _c_i64
     L.nm_batch_check.argtypes = [_vp, _vp]
     L.nm_batch_destroy.argtypes, L.nm_batch_destroy.restype = [_vp], None
+    L.nm_server_job_bytes.argtypes, L.nm_server_job_bytes.restype = [_c_i32, _c_i32, _c_i32], _c_i64
+    L.nm_server_create.argtypes = [_c_i64, _c_i32, ctypes.POINTER(_vp)]
+    L.nm_server_submit.argtypes = [_vp, ctypes.POINTER(Job), ctypes.POINTER(_c_i64)]
+    L.nm_server_poll.argtypes = [_vp, _c_i64]
+    L.nm_server_wait.argtypes = [_vp, _c_i64, _vp, _vp, _vp, _vp, ctypes.POINTER(JobResult)]
+    L.nm_server_stats.argtypes = [_vp, ctypes.POINTER(ServerInfo)]
+    L.nm_server_destroy.argtypes, L.nm_server_destroy.restype = [_vp], None
+    for f in ("nm_server_create", "nm_server_submit", "nm_server_poll", "nm_server_wait",
+              "nm_server_stats"):
+        getattr(L, f).restype = ctypes.c_int
     for f in ("nm_workspace_init", "nm_build_cells", "nm_knn", "nm_metric_list", "nm_align_step",
               "nm_step", "nm_bin_step", "nm_knn_align", "nm_check", "nm_tune_grid", "nm_batch_plan", "nm_batch_bind",
               "nm_batch_step", "nm_batch_tune", "nm_batch_system", "nm_batch_check"):
@@ -398,6 +426,74 @@ class Batch:
         if getattr(self, "_h", None) is not None and self._h.value:
             torch.cuda.synchronize(self.device)
             lib().nm_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def server_job_bytes(n: int, k: int, box: int) -> int:
+    """Admission (ledger) bytes of a served job."""
+    return int(lib().nm_server_job_bytes(n, k, box))
+
+
+class Server:
+    """Served form (nm_server_*): jobs with host inputs, state resident on the
+    device while they run, continuous batching under a device-memory budget."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 1024):
+        h = _vp()
+        _ok(lib().nm_server_create(int(budget_bytes), int(max_slots), ctypes.byref(h)), "server_create")
+        self._h = h
+        self._shape = {}
+
+    def submit(self, x, y, theta, k: int, nsteps: int, params: Params, want_nbr: bool = False) -> int:
+        import numpy as np
+        x = np.ascontiguousarray(x, dtype=np.int32)
+        y = np.ascontiguousarray(y, dtype=np.int32)
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        n = int(x.size)
+        if y.size != n or theta.size != n:
+            raise ValueError("x, y, theta must have the same length")
+        job = Job(n, int(k), int(nsteps), 1 if want_nbr else 0, params, x.ctypes.data, y.ctypes.data,
+                  theta.ctypes.data)
+        jid = _c_i64()
+        _ok(lib().nm_server_submit(self._h, ctypes.byref(job), ctypes.byref(jid)), "server_submit")
+        self._shape[int(jid.value)] = (n, int(k), bool(want_nbr))
+        return int(jid.value)
+
+    def poll(self, jid: int) -> bool:
+        rc = int(lib().nm_server_poll(self._h, int(jid)))
+        if rc < 0:
+            raise NMError(rc, "server_poll")
+        return rc == 1
+
+    def wait(self, jid: int):
+        """Final (x, y, theta[, nbr]) host arrays and the job's timing record."""
+        import numpy as np
+        n, k, want_nbr = self._shape.pop(int(jid))
+        x = np.empty(n, np.int32)
+        y = np.empty(n, np.int32)
+        th = np.empty(n, np.float32)
+        nbr = np.empty((n, k), np.int32) if want_nbr else None
+        r = JobResult()
+        rc = int(lib().nm_server_wait(self._h, int(jid), x.ctypes.data, y.ctypes.data, th.ctypes.data,
+                                      nbr.ctypes.data if nbr is not None else None, ctypes.byref(r)))
+        res = {"status": rc, "steps": r.steps, "submit_s": r.submit_s, "admit_s": r.admit_s,
+               "done_s": r.done_s, "x": x, "y": y, "theta": th, "nbr": nbr}
+        return res
+
+    def stats(self) -> dict:
+        info = ServerInfo()
+        _ok(lib().nm_server_stats(self._h, ctypes.byref(info)), "server_stats")
+        return {f: getattr(info, f) for f, _ in ServerInfo._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().nm_server_destroy(self._h)
             self._h = _vp()
 
     def __del__(self):

@@ -92,3 +92,29 @@ def test_binding_rejects_host_tensors():
     import torch
     with pytest.raises((TypeError, ImportError)):
         nm._dev(torch.zeros(4, dtype=torch.int32), torch.int32, 4, "x")
+
+
+L = 1 << 20
+
+
+def test_server_job_bytes_ledger():
+    # workspace + double-buffered x, y, theta + the k-NN list, 256-byte aligned pieces
+    b1 = nm.server_job_bytes(1024, 7, L)
+    assert b1 > (24 + 4 * 7) * 1024
+    assert nm.server_job_bytes(4096, 7, L) > b1
+    assert nm.server_job_bytes(1024, 12, L) - b1 >= 4 * 5 * 1024
+    assert nm.server_job_bytes(1 << 20, 12, L) < 160 * (1 << 20)  # about 127 MiB
+    assert nm.server_job_bytes(5, 7, L) < 0 and nm.server_job_bytes(100, 33, L) < 0
+
+
+def test_batch_plan_is_host_only():
+    # planning allocates host memory only and validates its arguments
+    L_ = nm.lib()
+    h, nbytes = ctypes.c_void_p(), ctypes.c_int64()
+    p = nm.make_params(L)
+    sizes = (ctypes.c_int32 * 3)(300, 5000, 65536)
+    assert L_.nm_batch_plan(3, sizes, L, 7, ctypes.byref(p), None, ctypes.byref(h), ctypes.byref(nbytes)) == 0
+    assert nbytes.value > sum((24 + 4 * 7) * n for n in (300, 5000, 65536))
+    L_.nm_batch_destroy(h)
+    bad = (ctypes.c_int32 * 2)(300, 7)  # a system with n < k + 1
+    assert L_.nm_batch_plan(2, bad, L, 7, ctypes.byref(p), None, ctypes.byref(h), ctypes.byref(nbytes)) == nm.NM_E_INVAL
