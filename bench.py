@@ -20,7 +20,10 @@ Beside it, on the same GPU:
   batched  512 systems, N log-uniform in [256, 65536], k = 7, one persistent
            launch per stage under a captured HIP graph, tuned cell widths;
            compared with the plain per-system calls (eager and graph-captured)
-  served   a Poisson stream of jobs through the served form (when built)
+  served   a seeded Poisson stream of jobs (200 req/s, N log-uniform in
+           [1024, 2^20], k in {7, 12}, 1..100 steps, half clustered) through
+           the served form under a 200 GB and a 1 GB budget, and the same
+           stream run one job at a time with the plain calls
 
 roofline: the fused k-NN + alignment kernel (k_knn<7, align>) bracketed by
 HIP events on the stream it runs on; its algorithmic traffic is 24 + 4k bytes
@@ -65,7 +68,7 @@ def parse():
     ap.add_argument("--block", type=int, default=0, help="fast-path block side with --cell-w")
     ap.add_argument("--metric-steps", type=int, default=100)
     ap.add_argument("--batched-steps", type=int, default=50)
-    ap.add_argument("--served-seconds", type=float, default=20.0)
+    ap.add_argument("--served-seconds", type=float, default=15.0)
     ap.add_argument("--no-metric", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
@@ -317,11 +320,133 @@ def bench_batched(args, torch, nm, workloads):
             "speedup_vs_plain_eager": plain_ms / ms_step, "speedup_vs_plain_graph": plain_graph_ms / ms_step}
 
 
+def served_pool(workloads, nmax, count=8):
+    """Seeded input pools: a job of size n uses the first n particles of pool
+    entry (seed mod count), uniform or clustered as the request says (a prefix
+    of an i.i.d. sample keeps its distribution)."""
+    pools = {}
+    for c in (False, True):
+        for i in range(count):
+            if c:
+                x, y, _ = workloads.clustered(nmax, seed=700 + i)
+            else:
+                x, y, _ = workloads.uniform(nmax, seed_pos=500 + i)
+            pools[(c, i)] = (x, y, workloads.headings(nmax, seed=900 + i))
+    return pools
+
+
+def run_stream(reqs, pools, submit, collect, t_limit):
+    """Submit requests at their arrival times (one thread) while another thread
+    collects results; returns per-job (latency s, n * nsteps)."""
+    import threading
+
+    out, ids = [], []
+    lock = threading.Lock()
+    done = threading.Event()
+
+    def collector():
+        i = 0
+        while True:
+            with lock:
+                ready = i < len(ids)
+                item = ids[i] if ready else None
+            if item is None:
+                if done.is_set() and i >= len(ids):
+                    break
+                time.sleep(0.0005)
+                continue
+            out.append(collect(item))
+            i += 1
+
+    th = threading.Thread(target=collector)
+    th.start()
+    t0 = time.perf_counter()
+    for r in reqs:
+        wait = r.arrival_s - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        if time.perf_counter() - t0 > t_limit:
+            break
+        x, y, th_ = pools[(r.clustered, r.seed % 8)]
+        item = submit(r, x[:r.n], y[:r.n], th_[:r.n])
+        with lock:
+            ids.append(item)
+    done.set()
+    th.join()
+    return out, time.perf_counter() - t0
+
+
 def bench_served(args, torch, nm, workloads):
-    srv = getattr(nm, "serve_stream", None)
-    if srv is None:
-        return None
-    return srv(rate_hz=200.0, duration_s=args.served_seconds, log=log)
+    box = workloads.BOX
+    reqs = workloads.request_stream(200.0, args.served_seconds)
+    pools = served_pool(workloads, max(r.n for r in reqs))
+    res = {}
+    for label, budget in (("budget_200GB", 200 * 10**9), ("budget_1GB", 10**9)):
+        if label == "budget_1GB":
+            reqs_run = [r for r in reqs if nm.server_job_bytes(r.n, r.k, box) <= budget]
+            reqs_run = [r for r in reqs_run if r.arrival_s < min(args.served_seconds, 5.0)]
+        else:
+            reqs_run = reqs
+        srv = nm.Server(budget_bytes=budget, max_slots=1024)
+
+        def submit(r, x, y, th):
+            p = nm.make_params(box, v0=64, eta=0.2, include_self=1, seed=r.seed, sys_id=r.seed & 0xFFFF)
+            return (srv.submit(x, y, th, r.k, r.nsteps, p), r)
+
+        def collect(item):
+            jid, r = item
+            o = srv.wait(jid)
+            if o["status"] != 0:
+                raise RuntimeError(f"served job failed: {nm.nm.status_str(o['status'])}")
+            return (o["done_s"] - o["submit_s"], r.n * r.nsteps, o["submit_s"], o["done_s"])
+
+        out, wall = run_stream(reqs_run, pools, submit, collect, args.served_seconds + 1.0)
+        st = srv.stats()
+        srv.close()
+        lat = [o[0] for o in out]
+        span = max(o[3] for o in out) - min(o[2] for o in out)
+        work = sum(o[1] for o in out)
+        res[label] = {"jobs": len(out), "latency_ms_p50": 1e3 * pct(lat, 50),
+                      "latency_ms_p99": 1e3 * pct(lat, 99), "particle_steps_per_s": work / span,
+                      "peak_active": st["peak_active"], "peak_ledger_bytes": st["peak_used_bytes"],
+                      "device_slab_bytes": st["reserved_bytes"], "iterations": st["iterations"]}
+        log(f"[bench] served {label}: {len(out)} jobs, p50 {res[label]['latency_ms_p50']:.1f} ms, "
+            f"p99 {res[label]['latency_ms_p99']:.1f} ms, {work / span:.3g} particle-steps/s, "
+            f"peak active {st['peak_active']}")
+
+    # Baseline: the same stream served one job at a time with the plain calls.
+    dev = torch.device("cuda:0")
+
+    def submit_plain(r, x, y, th):
+        return (r, x, y, th, time.perf_counter())
+
+    t_base = [None]
+
+    def collect_plain(item):
+        r, x, y, th, t_sub = item
+        p = nm.make_params(box, v0=64, eta=0.2, include_self=1, seed=r.seed, sys_id=r.seed & 0xFFFF)
+        sysm = nm.System.create(x, y, th, r.k, p, device=dev)
+        for _ in range(r.nsteps):
+            sysm.step()
+        xo = sysm.x.cpu()
+        t_done = time.perf_counter()
+        del sysm, xo
+        return (t_done - t_sub, r.n * r.nsteps, t_sub, t_done)
+
+    # (a shorter window: one job at a time falls behind the offered load)
+    reqs_plain = [r for r in reqs if r.arrival_s < min(args.served_seconds, 5.0)]
+    out, wall = run_stream(reqs_plain, pools, submit_plain, collect_plain, args.served_seconds + 1.0)
+    lat = [o[0] for o in out]
+    span = max(o[3] for o in out) - min(o[2] for o in out)
+    res["plain_one_job_at_a_time"] = {"jobs": len(out), "window_s": min(args.served_seconds, 5.0),
+                                      "latency_ms_p50": 1e3 * pct(lat, 50),
+                                      "latency_ms_p99": 1e3 * pct(lat, 99),
+                                      "particle_steps_per_s": sum(o[1] for o in out) / span}
+    log(f"[bench] served plain: p50 {1e3 * pct(lat, 50):.1f} ms, p99 {1e3 * pct(lat, 99):.1f} ms")
+    res["stream"] = {"rate_hz": 200.0, "seconds": args.served_seconds, "requests": len(reqs),
+                     "n": "log-uniform [1024, 2^20]", "k": [7, 12], "nsteps": "uniform [1, 100]",
+                     "inputs": "half uniform, half clustered (256 Gaussian clusters, sigma 0.01 L)"}
+    return res
 
 
 def main():
