@@ -12,7 +12,8 @@ the GPU, inputs resident in HBM:
 
 value = N * steps / wall time of the timed steps (particle-steps/s).  The
 cell width and block side are picked by the library's tuner (nm_tune_grid)
-on the initial state before warm-up.
+on the initial state before warm-up, and re-picked among the neighbouring
+grids every 200 steps as the flock clusters (those tuning steps are timed).
 
 Beside it, on the same GPU:
   metric   the metric cutoff list (r_c^2 = 2,336,407, mean 7 neighbours),
@@ -66,6 +67,7 @@ def parse():
     ap.add_argument("--k", type=int, default=7)
     ap.add_argument("--cell-w", type=int, default=0, help="cell width (0: tuned)")
     ap.add_argument("--block", type=int, default=0, help="fast-path block side with --cell-w")
+    ap.add_argument("--retune-every", type=int, default=200, help="re-pick the grid every this many steps")
     ap.add_argument("--metric-steps", type=int, default=100)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--served-seconds", type=float, default=15.0)
@@ -141,13 +143,17 @@ def bench_single(args, torch, nm, workloads):
     p = nm.make_params(box, v0=64, eta=0.2, include_self=1, seed=workloads.NOISE_SEED)
     X, Y, T = (torch.as_tensor(a).to(dev) for a in (x, y, th))
     tuned = None
+    w_lo, w_hi = nm.suggest_cell_w(n, box, 0.25), nm.suggest_cell_w(n, box, 16.0)
     if args.cell_w:
         ws = nm.Workspace(n, box, args.cell_w, dev, block=args.block)
     else:
+        # the workspace holds the finest grid the re-tuning may pick
+        ws = nm.Workspace(n, box, w_hi, dev, nbytes=nm.Workspace(n, box, w_lo, dev).nbytes)
         cws = sorted({nm.suggest_cell_w(n, box, pc) for pc in (1.0, 2.0, 4.0)})
         ws, tuned = nm.tune_grid(n, box, X, Y, T, k, p, cell_ws=cws, blocks=(0, 4, 6), reps=5,
-                                 device=dev)
+                                 device=dev, ws=ws)
     cell_w, block = ws.grid.cell_w, ws.grid.block
+    grids = {(cell_w, block)}
     log(f"[bench] N={n} k={k} cell_w={cell_w} block={block} "
         f"tuned={ {f'{w}/{b}': round(v, 4) for (w, b), v in tuned.items()} if tuned else None}")
     Xb, Yb, Tb = torch.empty_like(X), torch.empty_like(Y), torch.empty_like(T)
@@ -156,6 +162,18 @@ def bench_single(args, torch, nm, workloads):
 
     def one_step(ev=None):
         s = st
+        if not args.cell_w and args.retune_every > 0 and s["step"] > 0 and s["step"] % args.retune_every == 0:
+            # The flock clusters as it aligns: re-pick the grid among the
+            # neighbours of the current one on the current state (these tuning
+            # steps are part of the timed work).
+            w, b = ws.grid.cell_w, ws.grid.block
+            cand = {(w, b), (w, 0)}
+            for w2 in (w // 2, w * 2):
+                if w_lo <= w2 <= w_hi:
+                    cand.add((w2, 0))
+            nm.tune_grid(n, box, s["x"], s["y"], s["t"], k, p, step_index=s["step"],
+                         pairs=sorted(cand), reps=2, device=dev, ws=ws)
+            grids.add((ws.grid.cell_w, ws.grid.block))
         nm.bin_step(ws, s["x"], s["y"], s["t"], p, s["step"])
         if ev is not None:
             ev[0].record()
@@ -188,8 +206,10 @@ def bench_single(args, torch, nm, workloads):
     kms = [a.elapsed_time(b) for a, b in events]
     k_ms = sum(kms) / len(kms)
     log(f"[bench] timed {args.steps} steps: {ms_step:.4f} ms/step, k-NN+align kernel {k_ms:.4f} ms")
+    log(f"[bench] grids used: {sorted(grids)}")
     return {"x": x, "y": y, "th": th, "ms_step": ms_step, "k_ms": k_ms, "k_p50": pct(kms, 50),
-            "k_p99": pct(kms, 99), "cell_w": cell_w, "block": block, "tuned": tuned}
+            "k_p99": pct(kms, 99), "cell_w": cell_w, "block": block, "tuned": tuned,
+            "grids": sorted(grids)}
 
 
 def bench_metric(args, torch, nm, workloads):
@@ -487,6 +507,7 @@ def main():
                         "k-NN rebuild fused with Eq.2 alignment (vectorial noise eta=0.2) and Eq.1 move "
                         "(v0=64), Philox seed 0, lists rebuilt every step",
             "n": n, "k": k, "box": workloads.BOX, "cell_w": r["cell_w"], "block": r["block"],
+            "grids_used": [list(g) for g in r["grids"]], "retune_every": args.retune_every,
         },
         "neighbor_queries_per_s": value,
         "roofline": {

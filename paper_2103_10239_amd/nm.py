@@ -288,15 +288,21 @@ def knn_align(ws: Workspace, k: int, params: Params, theta, nbr, x_out, y_out, t
 
 
 def tune_grid(n: int, box: int, x, y, theta, k: int, params: Params, step_index: int = 0,
-              cell_ws=None, blocks=(0,), reps: int = 5, device="cuda"):
-    """Time the one-system step over candidate grids (cell widths x block sides)
-    on the given state; returns (Workspace for the fastest grid, {(w, block): ms})."""
-    if cell_ws is None:
-        cell_ws = sorted({suggest_cell_w(n, box, pc) for pc in (1.0, 2.0, 4.0)})
-    cands = [(int(w), int(b)) for w in cell_ws for b in blocks]
+              cell_ws=None, blocks=(0,), reps: int = 5, device="cuda", ws: Workspace | None = None,
+              pairs=None):
+    """Time the one-system step over candidate grids (cell widths x block sides,
+    or the given (w, block) pairs) on the given state; returns (Workspace set to
+    the fastest grid, {(w, block): ms per step}).  An existing workspace is
+    reused if it is large enough for every candidate."""
+    if pairs is None:
+        if cell_ws is None:
+            cell_ws = sorted({suggest_cell_w(n, box, pc) for pc in (1.0, 2.0, 4.0)})
+        pairs = [(w, b) for w in cell_ws for b in blocks]
+    cands = [(int(w), int(b)) for w, b in pairs]
     arr = (Grid * len(cands))(*[Grid(n, box, w, b) for w, b in cands])
     need = max(int(lib().nm_workspace_bytes(ctypes.byref(g))) for g in arr)
-    ws = Workspace(n, box, cands[0][0], device, block=cands[0][1], nbytes=need)
+    if ws is None or ws.nbytes < need:
+        ws = Workspace(n, box, cands[0][0], device, block=cands[0][1], nbytes=need)
     dev = ws.device
     nbr = torch.empty(n * k, dtype=torch.int32, device=dev)
     xo, yo = torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev)
