@@ -76,7 +76,20 @@ def parse():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a device copy of 256 MiB five times (calibrates DRAM counters) and exit")
     return ap.parse_args()
+
+
+def copy_probe(torch):
+    """A plain device-to-device copy of known size: 256 MiB read, 256 MiB written
+    per launch, the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] copy probe: 5 x {a.numel() * 4} bytes")
 
 
 def kernel_source_sha():
@@ -483,6 +496,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(torch)
+        return
     n, k = args.n, args.k
     r = bench_single(args, torch, nm, workloads)
     value = n / (r["ms_step"] * 1e-3)

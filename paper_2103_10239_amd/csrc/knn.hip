@@ -244,10 +244,13 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
 // particles searches global memory instead.  Uncertified queries are flagged
 // for the exact kernel.
 // ---------------------------------------------------------------------------
-constexpr int kTileCells = 1024;  // (T + 2h)^2 <= kTileCells
+constexpr int kTileCells = 2048;  // (T + 2h)^2 <= kTileCells
 constexpr int kTilePts = 3072;    // staged particles
-constexpr int kTileRows = 32;     // T + 2h <= kTileRows
-constexpr int kDeferCap = 256;    // uncertified queries listed in LDS per tile
+constexpr int kTileRows = 45;     // T + 2h <= kTileRows
+constexpr int kDeferCap = 128;    // uncertified queries listed in LDS per tile
+constexpr int kRowStep = kTileRows > 32 ? 32 : 16;  // binary search over <= 2 kRowStep rows
+constexpr int kSortCap = 1024;    // queries of a tile ordered by work (more: tile order)
+constexpr int kBuckets = 64;      // candidate-count buckets of that order
 
 typedef short short2v __attribute__((ext_vector_type(2)));
 
@@ -264,22 +267,27 @@ __device__ __forceinline__ int pack_rel(int rx, int ry) {
 // self: the query's LDS index, pq: its relative position (packed 16-bit pair;
 // wide tiles: the x offset, with the y offset in pqy and staged points as
 // int32 pairs).
+// Block side for a staged query: fixed, or such that the block edge sits
+// `reach` mean k-th-neighbour radii away, the density taken from the 3 x 3
+// cells around the home cell (cx, cy) in halo coordinates.
+__device__ __forceinline__ int lds_block_side(const FastCfg& f, const int* lcell, int W, int cx,
+                                              int cy, int k) {
+  if (f.bfix > 0) return f.bfix;
+  int n9 = 0;
+#pragma unroll
+  for (int dr = -1; dr <= 1; ++dr) n9 += lcell[(cy + dr) * W + cx + 2] - lcell[(cy + dr) * W + cx - 1];
+  const float rk = sqrtf(static_cast<float>(k) * 9.0f / (3.14159265f * fmaxf(static_cast<float>(n9), 0.5f)));
+  return max(static_cast<int>(ceilf(2.0f * f.reach * rk)) + 1, 3);
+}
+
 template <int KMAX, bool kWide>
-__device__ __forceinline__ bool knn_lds(const DevWs& w, const FastCfg& f, const TileCfg& tc,
-                                        const int* lcell, const int* lpos, const int* lslot, int W,
-                                        int cx, int cy, int self, int pq, int pqy, int qx, int qy,
-                                        int k, int (&slot)[KMAX]) {
+__device__ __forceinline__ bool knn_lds(const DevWs& w, const TileCfg& tc, const int* lcell,
+                                        const int* lpos, const int* lslot, int W, int cx, int cy,
+                                        int self, int pq, int pqy, int qx, int qy, int k, int B,
+                                        int (&slot)[KMAX]) {
   constexpr int kPts = kWide ? kTilePts / 2 : kTilePts;
   const int2* lpos2 = reinterpret_cast<const int2*>(lpos);
   constexpr int KT = KMAX + 1;
-  int B = f.bfix;
-  if (B == 0) {
-    int n9 = 0;
-#pragma unroll
-    for (int dr = -1; dr <= 1; ++dr) n9 += lcell[(cy + dr) * W + cx + 2] - lcell[(cy + dr) * W + cx - 1];
-    const float rk = sqrtf(static_cast<float>(k) * 9.0f / (3.14159265f * fmaxf(static_cast<float>(n9), 0.5f)));
-    B = max(static_cast<int>(ceilf(2.0f * f.reach * rk)) + 1, 3);
-  }
   if (B > tc.bmax) return false;
   for (int attempt = 0; attempt < 2; ++attempt) {
     const QBlock b = make_qblock(w, qx, qy, B);
@@ -492,6 +500,12 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   __shared__ int s_psx[kTileRows][3];
   __shared__ int s_defer;
   __shared__ int s_dq[kDeferCap];  // slots of the tile's uncertified queries
+  // Work-sorted query order: per query (bucket of its candidate count, block
+  // side), then the permutation (query, block side), heaviest bucket first.
+  __shared__ uint16_t s_key[kSortCap];
+  __shared__ uint16_t s_perm[kSortCap];
+  __shared__ int s_hist[kBuckets];
+  __shared__ int s_nsorted;
   if (!ws_ready(w)) {
     if (tile == 0 && threadIdx.x == 0) set_err(w.hdr, NM_E_INVAL);
     return;
@@ -573,7 +587,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
     for (int pidx = threadIdx.x; pidx < npts; pidx += kBlock) {
       int rho = 0;
 #pragma unroll
-      for (int step = kTileRows / 2; step > 0; step >>= 1)
+      for (int step = kRowStep; step > 0; step >>= 1)
         if (rho + step < R && s_rbase[rho + step] <= pidx) rho += step;
       const int inrow = pidx - s_rbase[rho];
       const int pi = (inrow >= s_plo[rho][2]) ? 2 : ((inrow >= s_plo[rho][1]) ? 1 : 0);
@@ -590,34 +604,126 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
     __syncthreads();
   }
 
-  for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
-    int rq = 0;  // tile row of query qi
+  auto defer = [&](int slot_s) {
+    const int pos = atomicAdd(&s_defer, 1);
+    if (pos < kDeferCap)
+      s_dq[pos] = slot_s;
+    else
+      w.dflag[slot_s] = 1;  // overflow of the list: found again below by its flag
+  };
+  auto row_of = [&](int qi) {  // tile row of query qi
+    int rq = 0;
 #pragma unroll
-    for (int step = kTileRows / 2; step > 0; step >>= 1)
+    for (int step = kRowStep; step > 0; step >>= 1)
       if (rq + step < tb.ty && s_qoff[rq + step] <= qi) rq += step;
-    const int s = s_qbeg[rq] + (qi - s_qoff[rq]);
-    const int4 q = w.sorted[s];
-    int slot[KMAX];
-    bool ok;
-    if (staged) {
-      const int cx = (q.x >> w.log2_w) - uL, cy = rq + h;
-      const int64_t hc = static_cast<int64_t>(tb.y0 + rq) * G + (q.x >> w.log2_w);
-      const int self = lcell[cy * W + cx] + (s - w.start[hc]);
-      ok = wide ? knn_lds<KMAX, true>(w, f, tc, lcell, lpos, lslot, W, cx, cy, self, q.x - ox0,
-                                      q.y - oy0, q.x, q.y, k, slot)
-                : knn_lds<KMAX, false>(w, f, tc, lcell, lpos, lslot, W, cx, cy, self,
-                                       pack_rel(q.x - ox0, q.y - oy0), 0, q.x, q.y, k, slot);
+    return rq;
+  };
+  // Relative position (halo corner origin) of the staged point with LDS index i.
+  auto rel_pos = [&](int i, int& rx, int& ry) {
+    if (wide) {
+      const int2 p2 = lpos_store[i];
+      rx = p2.x;
+      ry = p2.y;
     } else {
-      ok = knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot);
+      const int p = lpos[i];
+      rx = p & 0xFFFF;
+      ry = p >> 16;
     }
-    if (ok) {
-      finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
-    } else {
-      const int pos = atomicAdd(&s_defer, 1);
-      if (pos < kDeferCap)
-        s_dq[pos] = s;
+  };
+
+  if (staged && nq <= kSortCap) {
+    // Pre-pass: block side and candidate count of every query, from LDS
+    // only; a counting sort by candidate count then gives each wavefront
+    // queries of similar work (a wavefront runs as long as its longest query).
+    if (threadIdx.x < kBuckets) s_hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
+      const int rq = row_of(qi);
+      const int self = lcell[(rq + h) * W + h] + (qi - s_qoff[rq]);
+      int rx, ry;
+      rel_pos(self, rx, ry);
+      const int cx = rx >> w.log2_w, cy = ry >> w.log2_w;
+      const int B = lds_block_side(f, lcell, W, cx, cy, k);
+      int key = 0xFFFF;
+      if (B <= tc.bmax) {
+        const QBlock b = make_qblock(w, rx + ox0, ry + oy0, B);
+        const int row0 = (cy + b.lo_y) * W + cx + b.lo_x;
+        int nc = 0;
+        for (int r = 0; r < B; ++r) nc += lcell[row0 + r * W + B] - lcell[row0 + r * W];
+        const int bk = nc < 128 ? (nc >> 2) : 32 + min((nc - 128) >> 5, kBuckets - 33);
+        atomicAdd(&s_hist[bk], 1);
+        key = (bk << 4) | B;
+      } else {
+        defer(lslot[self]);
+      }
+      s_key[qi] = static_cast<uint16_t>(key);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {  // exclusive offsets, heaviest bucket first
+      const int bk = kBuckets - 1 - lane;
+      const int c = s_hist[bk];
+      int incl = c;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+      }
+      s_hist[bk] = incl - c;
+      if (lane == 63) s_nsorted = incl;
+    }
+    __syncthreads();
+    for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
+      const int key = s_key[qi];
+      if (key == 0xFFFF) continue;
+      const int pos = atomicAdd(&s_hist[key >> 4], 1);
+      s_perm[pos] = static_cast<uint16_t>((qi << 4) | (key & 15));
+    }
+    __syncthreads();
+    const int ns = s_nsorted;
+    for (int j = threadIdx.x; j < ns; j += kBlock) {
+      const int e = s_perm[j];
+      const int qi = e >> 4, B = e & 15;
+      const int rq = row_of(qi);
+      const int self = lcell[(rq + h) * W + h] + (qi - s_qoff[rq]);
+      int rx, ry;
+      rel_pos(self, rx, ry);
+      const int cx = rx >> w.log2_w, cy = ry >> w.log2_w;
+      int slot[KMAX];
+      const bool ok =
+          wide ? knn_lds<KMAX, true>(w, tc, lcell, lpos, lslot, W, cx, cy, self, rx, ry, rx + ox0,
+                                     ry + oy0, k, B, slot)
+               : knn_lds<KMAX, false>(w, tc, lcell, lpos, lslot, W, cx, cy, self, pack_rel(rx, ry), 0,
+                                      rx + ox0, ry + oy0, k, B, slot);
+      const int s = lslot[self];
+      if (ok) {
+        const int4 q = w.sorted[s];
+        finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
+      } else {
+        defer(s);
+      }
+    }
+  } else {
+    for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
+      const int rq = row_of(qi);
+      const int s = s_qbeg[rq] + (qi - s_qoff[rq]);
+      const int4 q = w.sorted[s];
+      int slot[KMAX];
+      bool ok;
+      if (staged) {
+        const int self = lcell[(rq + h) * W + h] + (qi - s_qoff[rq]);
+        const int cx = (q.x >> w.log2_w) - uL, cy = rq + h;
+        const int B = lds_block_side(f, lcell, W, cx, cy, k);
+        ok = wide ? knn_lds<KMAX, true>(w, tc, lcell, lpos, lslot, W, cx, cy, self, q.x - ox0,
+                                        q.y - oy0, q.x, q.y, k, B, slot)
+                  : knn_lds<KMAX, false>(w, tc, lcell, lpos, lslot, W, cx, cy, self,
+                                         pack_rel(q.x - ox0, q.y - oy0), 0, q.x, q.y, k, B, slot);
+      } else {
+        ok = knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot);
+      }
+      if (ok)
+        finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
       else
-        w.dflag[s] = 1;  // overflow of the list: found again below by its flag
+        defer(s);
     }
   }
   __syncthreads();
@@ -804,7 +910,7 @@ hipError_t launch_batch_knn(const BatchRef& b, int k, hipStream_t s) {
 // side, 0 picks it per query, < 0 disables the fast path.
 FastCfg fast_cfg(const DevWs& w, int k, int block) {
   (void)k;
-  FastCfg f{0, 0, 1.6f, 0};
+  FastCfg f{0, 0, 1.25f, 0};
   if (block < 0) return f;
   int bw = kMaxB;  // any span (64-bit distances): the block must not meet itself
   while (bw >= 3 && bw + 2 > w.G) --bw;
