@@ -78,7 +78,7 @@ BatchSys make_batch_sys(const SysSpec& s, int k) {
   d.step_lo = static_cast<uint32_t>(s.step);
   d.step_hi = static_cast<uint32_t>(s.step >> 32);
   d.parity = s.parity;
-  d.ntiles = d.tc.ntx * d.tc.ntx;
+  d.ntiles = d.tc.ntx * d.tc.nty;
   const int64_t big = std::max<int64_t>(lay.C, s.g.n);
   d.nitems[kStInit] = static_cast<int32_t>(
       std::max<int64_t>(1, std::min<int64_t>(64, (big + 4 * kBlock - 1) / (4 * kBlock))));
@@ -201,7 +201,7 @@ int64_t max_items(const nm_batch* b, int s) {
     if (!make_layout(&g, &lay)) continue;
     const DevWs w = dev_ws(&g, lay, nullptr);  // geometry only
     const TileCfg tc = tile_cfg(w, fast_cfg(w, b->k, 0), b->k);
-    const int64_t tiles = static_cast<int64_t>(tc.ntx) * tc.ntx;
+    const int64_t tiles = static_cast<int64_t>(tc.ntx) * tc.nty;
     best = std::max<int64_t>(best, 64 + (g.n + kBlock - 1) / kBlock + lay.nb_scan_c +
                                        (g.n + 4 * kBlock - 1) / (4 * kBlock) + tiles);
   }

@@ -234,23 +234,29 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
 }
 
 // ---------------------------------------------------------------------------
-// Tiles.  A workgroup owns a T x T square of cells (about 256 queries).  It
-// stages the halo of (T + 2h)^2 cells around the tile into LDS: the cell start
-// table, and every particle's position in the tile's periodic image, stored
-// as a pair of 16-bit offsets from the halo's corner (the halo spans fewer
-// than 2^15 grid units), so that a squared distance is one packed subtract
-// and one 16-bit dot product.  Each lane then runs the certified block search
-// of one query on LDS only.  A tile whose halo holds more than kTilePts
-// particles searches global memory instead.  Uncertified queries are flagged
-// for the exact kernel.
+// Strips.  A workgroup owns a strip of tw x th cells (tw = 1 or 2 columns,
+// about 256 queries) and stages the halo of W = tw + 2 hx columns by
+// R = th + 2 hy rows into LDS: the LDS offset of each halo row, and every
+// particle's position in the strip's periodic image relative to the halo
+// corner, with its cell-ordered slot.  A query's block is all W columns of
+// Bq consecutive halo rows around its own, so its candidates are one
+// contiguous LDS range, read several at a time.  Positions are a packed pair
+// of 16-bit offsets whose differences are taken in 16-bit wrap-around
+// arithmetic (exact: every block spans under 2^15 units), so that a squared
+// distance is one packed subtract and one 16-bit dot product; where a block
+// spans more (sparse systems) they are int32 pairs with 64-bit distances.
+// A strip whose halo holds more particles than fit searches global memory.
+// Uncertified queries are finished at the end of the strip by the exact
+// search.
 // ---------------------------------------------------------------------------
-constexpr int kTileCells = 2048;  // (T + 2h)^2 <= kTileCells
-constexpr int kTilePts = 3072;    // staged particles
-constexpr int kTileRows = 45;     // T + 2h <= kTileRows
-constexpr int kDeferCap = 128;    // uncertified queries listed in LDS per tile
-constexpr int kRowStep = kTileRows > 32 ? 32 : 16;  // binary search over <= 2 kRowStep rows
-constexpr int kSortCap = 1024;    // queries of a tile ordered by work (more: tile order)
+constexpr int kStripPts = 2560;   // staged particles (wide strips: half)
+constexpr int kStripRows = 256;   // R <= kStripRows
+constexpr int kRowStep = kStripRows / 2;  // binary search over <= kStripRows rows
+constexpr int kDeferCap = 128;    // uncertified queries listed in LDS per strip
+constexpr int kSortCap = 1024;    // queries of a strip ordered by work (more: strip order)
 constexpr int kBuckets = 64;      // candidate-count buckets of that order
+constexpr int kUnroll = 4;        // candidates read per round of the block loop
+constexpr double kReachX = 1.25;  // strip half width, in mean k-th-neighbour radii
 
 typedef short short2v __attribute__((ext_vector_type(2)));
 
@@ -263,87 +269,95 @@ __device__ __forceinline__ int pack_rel(int rx, int ry) {
   return (rx & 0xFFFF) | (ry << 16);
 }
 
-// Block search on the staged tile.  (cx, cy): home cell in halo coordinates,
-// self: the query's LDS index, pq: its relative position (packed 16-bit pair;
-// wide tiles: the x offset, with the y offset in pqy and staged points as
-// int32 pairs).
-// Block side for a staged query: fixed, or such that the block edge sits
-// `reach` mean k-th-neighbour radii away, the density taken from the 3 x 3
-// cells around the home cell (cx, cy) in halo coordinates.
-__device__ __forceinline__ int lds_block_side(const FastCfg& f, const int* lcell, int W, int cx,
-                                              int cy, int k) {
+// Block height for a staged query: fixed, or such that the block edge sits
+// `reach` mean k-th-neighbour radii away, the density taken from the three
+// halo rows around the query's (3 W cells).
+__device__ __forceinline__ int strip_block_rows(const FastCfg& f, const int* rbase, int W, int cy,
+                                                int k) {
   if (f.bfix > 0) return f.bfix;
-  int n9 = 0;
-#pragma unroll
-  for (int dr = -1; dr <= 1; ++dr) n9 += lcell[(cy + dr) * W + cx + 2] - lcell[(cy + dr) * W + cx - 1];
-  const float rk = sqrtf(static_cast<float>(k) * 9.0f / (3.14159265f * fmaxf(static_cast<float>(n9), 0.5f)));
-  return max(static_cast<int>(ceilf(2.0f * f.reach * rk)) + 1, 3);
+  const int n3 = rbase[cy + 2] - rbase[cy - 1];
+  const float rk = sqrtf(static_cast<float>(k) * static_cast<float>(3 * W) /
+                         (3.14159265f * fmaxf(static_cast<float>(n3), 0.5f)));
+  return max(static_cast<int>(ceilf(2.0f * f.reach * rk)) + 1, 1);
 }
 
+// Geometry of a query's block in a strip: halo rows [r0, r0 + Bq), all W
+// columns; squared distance to the nearest point outside it, and the shift
+// that fits that bound in the distance field of a 32-bit key.
+struct StripBlock {
+  int r0;
+  long long bound;
+  int sh;
+};
+
+__device__ __forceinline__ StripBlock strip_block(int rx, int oy, int cy, int Bq, int W, int lw) {
+  const int cw = 1 << lw;
+  const int half = Bq >> 1;
+  const int lo = (Bq & 1) ? -half : -half + (oy >= (cw >> 1) ? 1 : 0);
+  StripBlock b;
+  b.r0 = cy + lo;
+  const int gl = rx + 1, gr = W * cw - rx;
+  const int gd = oy - lo * cw + 1, gu = (lo + Bq) * cw - oy;
+  const long long m = min(min(gl, gr), min(gd, gu));
+  b.bound = m * m;
+  const int bits = 64 - __clzll(b.bound);
+  b.sh = bits > kDBits ? bits - kDBits : 0;
+  return b;
+}
+
+// Certified search of one staged query over LDS.  self: the query's LDS
+// index; (pq, pqy): its relative position (narrow: packed pair in pq);
+// (rx, oy): its x offset from the halo corner and y offset in its cell; cy:
+// its halo row.  True with `slot` filled when the k nearest are certified.
 template <int KMAX, bool kWide>
-__device__ __forceinline__ bool knn_lds(const DevWs& w, const TileCfg& tc, const int* lcell,
-                                        const int* lpos, const int* lslot, int W, int cx, int cy,
-                                        int self, int pq, int pqy, int qx, int qy, int k, int B,
-                                        int (&slot)[KMAX]) {
-  constexpr int kPts = kWide ? kTilePts / 2 : kTilePts;
-  const int2* lpos2 = reinterpret_cast<const int2*>(lpos);
+__device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, const int* rbase,
+                                             const int* lpos, const int* lslot, int W, int self,
+                                             int pq, int pqy, int rx, int oy, int cy, int qx,
+                                             int qy, int k, int Bq, int (&slot)[KMAX]) {
+  constexpr int kPts = kWide ? kStripPts / 2 : kStripPts;
   constexpr int KT = KMAX + 1;
-  if (B > tc.bmax) return false;
+  const int2* lpos2 = reinterpret_cast<const int2*>(lpos);
+  if (Bq > tc.bmax) return false;
   for (int attempt = 0; attempt < 2; ++attempt) {
-    const QBlock b = make_qblock(w, qx, qy, B);
+    const StripBlock b = strip_block(rx, oy, cy, Bq, W, w.log2_w);
     uint32_t key[KT];
 #pragma unroll
     for (int t = 0; t < KT; ++t) key[t] = (t < KT - (k + 1)) ? 0u : kKey32Inf;
-    const uint32_t clampd = static_cast<uint32_t>(b.bound);
     const int sh = b.sh;
-    // The block's rows as one flat sequence of LDS indices: a single loop over
-    // every candidate of every row (the row switch is a predicated update), so
-    // a wavefront runs as many iterations as its longest query, not as the sum
-    // of its longest rows.  The query itself gets the key INF.
-    const int row0 = (cy + b.lo_y) * W + cx + b.lo_x;
-    int ncand = 0;
-    for (int r = 0; r < B; ++r) ncand += lcell[row0 + r * W + B] - lcell[row0 + r * W];
-    int r = 0, i = lcell[row0], e = lcell[row0 + B];
-    while (i == e && r + 1 < B) {
-      ++r;
-      i = lcell[row0 + r * W];
-      e = lcell[row0 + r * W + B];
-    }
-    // (with no candidate at all, the first read is a harmless in-bounds one)
-    int pc = 0;
-    int2 pc2 = make_int2(0, 0);
-    if (kWide)
-      pc2 = lpos2[min(i, kPts - 1)];
-    else
-      pc = lpos[min(i, kPts - 1)];
-    for (int c = 0; c < ncand; ++c) {
-      const int icur = i, pcur = pc;
-      const int2 pcur2 = pc2;
-      ++i;
-      while (i == e && r + 1 < B) {
-        ++r;
-        i = lcell[row0 + r * W];
-        e = lcell[row0 + r * W + B];
-      }
-      uint32_t kk;
+    const int a = rbase[b.r0], e = rbase[b.r0 + Bq];
+    for (int i = a; i < e; i += kUnroll) {
+      uint32_t kk[kUnroll];
       if (kWide) {
-        pc2 = lpos2[min(i, kPts - 1)];
-        const long long dx = pcur2.x - pq, dy = pcur2.y - pqy;
-        const unsigned long long d2 = static_cast<unsigned long long>(dx * dx + dy * dy);
-        kk = (static_cast<uint32_t>(min(d2, static_cast<unsigned long long>(b.bound)) >> sh) << 13) |
-             static_cast<uint32_t>(icur);
+        int2 pc[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) pc[u] = lpos2[min(i + u, kPts - 1)];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const long long dx = pc[u].x - pq, dy = pc[u].y - pqy;
+          const unsigned long long d2 = static_cast<unsigned long long>(dx * dx + dy * dy);
+          kk[u] = (static_cast<uint32_t>(min(d2, static_cast<unsigned long long>(b.bound)) >> sh) << 13) |
+                  static_cast<uint32_t>(i + u);
+        }
       } else {
-        pc = lpos[min(i, kPts - 1)];
-        const uint32_t d2 = static_cast<uint32_t>(rel_d2(pcur, pq));
-        kk = ((min(d2, clampd) >> sh) << 13) | static_cast<uint32_t>(icur);
+        int pc[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) pc[u] = lpos[min(i + u, kPts - 1)];
+        const uint32_t clampd = static_cast<uint32_t>(b.bound);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const uint32_t d2 = static_cast<uint32_t>(rel_d2(pc[u], pq));
+          kk[u] = ((min(d2, clampd) >> sh) << 13) | static_cast<uint32_t>(i + u);
+        }
       }
-      net_insert(key, icur == self ? kKey32Inf : kk);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        net_insert(key, (i + u == self || i + u >= e) ? kKey32Inf : kk[u]);
     }
     const uint32_t kth = key[KT - 2];
     const long long dmax = (static_cast<long long>(key32_d(kth) + 1) << sh) - 1;
     if (kth == kKey32Inf || dmax >= b.bound) {
-      if (attempt == 0 && B + 2 <= tc.bmax) {
-        B += 2;
+      if (attempt == 0 && Bq + 2 <= tc.bmax) {
+        Bq += 2;
         continue;
       }
       return false;
@@ -464,19 +478,41 @@ __device__ __forceinline__ void exact_lane(const DevWs& w, int s, int k, int tot
     set_err(w.hdr, NM_E_RANGE);  // fewer than k other particles were binned
 }
 
-// Cells of tile `tile`: columns [x0, x0 + tx), rows [y0, y0 + ty).
-struct TileBox {
-  int x0, y0, tx, ty;
+// Cells of strip `tile`: columns [x0, x0 + tw), rows [y0, y0 + ty).
+struct StripBox {
+  int x0, y0, ty;
 };
 
-__device__ __forceinline__ TileBox tile_box(const DevWs& w, const TileCfg& tc, int tile) {
-  TileBox b;
+__device__ __forceinline__ StripBox strip_box(const DevWs& w, const TileCfg& tc, int tile) {
+  StripBox b;
   const int tyi = tile / tc.ntx, txi = tile - tyi * tc.ntx;
-  b.x0 = txi * tc.t;
-  b.y0 = tyi * tc.t;
-  b.tx = min(tc.t, w.G - b.x0);
-  b.ty = min(tc.t, w.G - b.y0);
+  b.x0 = txi * tc.tw;
+  b.y0 = tyi * tc.th;
+  b.ty = min(tc.th, w.G - b.y0);
   return b;
+}
+
+// Exclusive prefix sum of v over the workgroup (thread order); *total gets
+// the sum.  Uses s_wsum[kBlock / 64].
+__device__ __forceinline__ int block_exclusive_scan(int v, int* s_wsum, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) s_wsum[wave] = incl;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int q = 0; q < kBlock / 64; ++q) {
+    if (q < wave) before += s_wsum[q];
+    all += s_wsum[q];
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
 }
 
 template <int KMAX, bool kAlign>
@@ -484,121 +520,107 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
                                               int k, int32_t* __restrict__ nbr,
                                               long long* __restrict__ d2out, const AlignArgs& a,
                                               int tile) {
-  __shared__ int lcell[kTileCells + 1];
-  __shared__ int2 lpos_store[kTilePts / 2];  // packed 16-bit pairs, or int32 pairs (wide)
-  int* lpos = reinterpret_cast<int*>(lpos_store);
-  __shared__ int lslot[kTilePts];
-  __shared__ int s_qoff[kTileRows + 1];   // query prefix over the tile's rows
-  __shared__ int s_qbeg[kTileRows];       // first slot of each tile row
-  __shared__ int s_rbase[kTileRows + 1];  // LDS offset of each halo row
-  // Each halo row is up to three physically contiguous pieces (it may wrap
-  // around the box in x): first unwrapped column, first slot, LDS offset
-  // within the row, and image shift of x.
-  __shared__ int s_pu[kTileRows][3];
-  __shared__ int s_pga[kTileRows][3];
-  __shared__ int s_plo[kTileRows][4];
-  __shared__ int s_psx[kTileRows][3];
+  __shared__ int2 lpos_store[kStripPts / 2];  // packed 16-bit pairs, or int32 pairs (wide)
+  __shared__ int lslot[kStripPts];
+  __shared__ int s_rbase[kStripRows + 1];  // LDS offset of each halo row
+  __shared__ int s_ga0[kStripRows];        // first slot of the row's first piece
+  __shared__ int s_n0[kStripRows];         // particles in the row's first piece
+  __shared__ int s_ga1[kStripRows];        // first slot of its second piece (x wrap)
+  __shared__ int s_qoff[kStripRows + 1];   // query prefix over the strip's rows
+  __shared__ int s_tself[kStripRows];      // LDS index of each strip row's first query
+  __shared__ int s_wsum[kBlock / 64];
   __shared__ int s_defer;
-  __shared__ int s_dq[kDeferCap];  // slots of the tile's uncertified queries
+  __shared__ int s_dq[kDeferCap];  // slots of the strip's uncertified queries
   // Work-sorted query order: per query (bucket of its candidate count, block
-  // side), then the permutation (query, block side), heaviest bucket first.
+  // height), then the permutation (query, block height), heaviest first.
   __shared__ uint16_t s_key[kSortCap];
   __shared__ uint16_t s_perm[kSortCap];
   __shared__ int s_hist[kBuckets];
   __shared__ int s_nsorted;
+  int* lpos = reinterpret_cast<int*>(lpos_store);
   if (!ws_ready(w)) {
     if (tile == 0 && threadIdx.x == 0) set_err(w.hdr, NM_E_INVAL);
     return;
   }
-  const TileBox tb = tile_box(w, tc, tile);
-  const int G = w.G, L = w.box, gm = G - 1;
+  const StripBox tb = strip_box(w, tc, tile);
+  const int G = w.G, L = w.box, gm = G - 1, lw = w.log2_w;
   const int total = min(w.start[w.C], w.n);
-  const int h = tc.h, W = tb.tx + 2 * h, R = tb.ty + 2 * h;
-  const int uL = tb.x0 - h, uR = tb.x0 + tb.tx + h - 1;
+  const int tw = tc.tw, hx = tc.hx, hy = tc.hy;
+  const int W = tw + 2 * hx, R = tb.ty + 2 * hy;
+  const int uL = tb.x0 - hx, uR = tb.x0 + tw + hx - 1;
   const int lane = threadIdx.x & 63;
-  const int ox0 = uL << w.log2_w, oy0 = (tb.y0 - h) << w.log2_w;  // halo corner (tile image)
+  const int ox0 = uL << lw, oy0 = (tb.y0 - hy) << lw;  // halo corner (strip image)
+  const bool wide = tc.wide != 0;
 
-  // Wave 0: query rows of the tile, and the pieces and length of each halo row.
-  if (threadIdx.x < 64) {
-    int qlen = 0, rlen = 0;
-    if (lane < tb.ty) {
-      const int64_t row = static_cast<int64_t>(tb.y0 + lane) * G;
-      const int a0 = w.start[row + tb.x0];
-      s_qbeg[lane] = a0;
-      qlen = max(min(w.start[row + tb.x0 + tb.tx], total) - a0, 0);
-    }
-    if (h > 0 && lane < R) {
-      const int64_t prow = static_cast<int64_t>((tb.y0 - h + lane) & gm) * G;
-      int np = 0;
-      for (int p0 = uL; p0 <= uR && np < 3; ++np) {
-        const int p1 = p0 < 0 ? min(uR, -1) : (p0 < G ? min(uR, G - 1) : uR);
-        const int ga = w.start[prow + (p0 & gm)];
-        s_pu[lane][np] = p0;
-        s_pga[lane][np] = ga;
-        s_plo[lane][np] = rlen;
-        s_psx[lane][np] = (p0 < 0 ? -L : (p0 >= G ? L : 0)) - ox0;
-        rlen += w.start[prow + (p1 & gm) + 1] - ga;
-        p0 = p1 + 1;
+  // Each halo row (one per thread): its one or two slot ranges (the columns
+  // [uL, uR] wrap around the box at most once since W <= G) and, for the
+  // strip's own rows, the query range.
+  int rlen = 0, qlen = 0, qrow_off = 0;
+  const int rho = threadIdx.x;
+  if (rho < R) {
+    const int v = tb.y0 - hy + rho;
+    const int64_t prow = static_cast<int64_t>(v & gm) * G;
+    if (hx > 0) {
+      const int e0 = uL < 0 ? -1 : min(uR, G - 1);  // last column of the first piece
+      const int ga0 = w.start[prow + (uL & gm)];
+      const int n0 = w.start[prow + (e0 & gm) + 1] - ga0;
+      int n1 = 0, ga1 = 0;
+      if (e0 < uR) {
+        ga1 = w.start[prow + ((e0 + 1) & gm)];
+        n1 = w.start[prow + (uR & gm) + 1] - ga1;
       }
-      for (int q = np; q < 3; ++q) {
-        s_pu[lane][q] = 0x7FFFFFFF;
-        s_pga[lane][q] = 0;
-        s_plo[lane][q] = rlen;
-        s_psx[lane][q] = 0;
-      }
-      s_plo[lane][3] = rlen;
+      s_ga0[rho] = ga0;
+      s_n0[rho] = n0;
+      s_ga1[rho] = ga1;
+      rlen = n0 + n1;
+      // the strip's own columns start at unwrapped column x0 (in [0, G)):
+      // in the second piece when the first one is the wrapped left edge
+      qrow_off = uL < 0 ? n0 + (w.start[prow + tb.x0] - ga1) : w.start[prow + tb.x0] - ga0;
     }
-    int qi = qlen, ri = rlen;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int t1 = __shfl_up(qi, off, 64), t2 = __shfl_up(ri, off, 64);
-      if (lane >= off) {
-        qi += t1;
-        ri += t2;
-      }
+    const int rq = rho - hy;
+    if (rq >= 0 && rq < tb.ty) {
+      const int a0 = w.start[prow + tb.x0];
+      qlen = max(min(w.start[prow + tb.x0 + tw], total) - a0, 0);
     }
-    if (lane <= kTileRows) {
-      if (lane <= tb.ty) s_qoff[lane] = qi - qlen;
-      if (lane <= R) s_rbase[lane] = ri - rlen;
-    }
-    if (lane == 0) s_defer = 0;
+  }
+  int npts, nq;
+  const int rb = block_exclusive_scan(rlen, s_wsum, &npts);
+  if (rho < R) s_rbase[rho] = rb;
+  const int rq = rho - hy;
+  const bool qrow = rho < R && rq >= 0 && rq < tb.ty;
+  const int qo = block_exclusive_scan(qrow ? qlen : 0, s_wsum, &nq);
+  if (qrow) {
+    s_qoff[rq] = qo;
+    s_tself[rq] = rb + qrow_off;
+  }
+  if (threadIdx.x == 0) {
+    s_rbase[R] = npts;
+    s_qoff[tb.ty] = nq;
+    s_defer = 0;
   }
   __syncthreads();
-  const int nq = s_qoff[tb.ty];
   if (nq == 0) return;
-  const bool wide = tc.wide != 0;
-  const bool staged = h > 0 && s_rbase[R] <= (wide ? kTilePts / 2 : kTilePts);
+  const bool staged = hx > 0 && npts <= (wide ? kStripPts / 2 : kStripPts);
   if (staged) {
-    // Cell table: LDS offset of every halo cell, from the start table.
-    for (int c = threadIdx.x; c <= R * W; c += kBlock) {
-      if (c == R * W) {
-        lcell[c] = s_rbase[R];
-        continue;
-      }
-      const int rho = c / W, u = uL + (c - rho * W);
-      const int pi = (u >= s_pu[rho][2]) ? 2 : ((u >= s_pu[rho][1]) ? 1 : 0);
-      const int64_t cell = static_cast<int64_t>((tb.y0 - h + rho) & gm) * G + (u & gm);
-      lcell[c] = s_rbase[rho] + s_plo[rho][pi] + (w.start[cell] - s_pga[rho][pi]);
-    }
-    // Particles as packed 16-bit offsets from the halo corner, one per thread
-    // per round: find the halo row (binary search over the row offsets) and
-    // the piece, then the source slot.
-    const int npts = s_rbase[R];
+    // Particles as offsets from the halo corner, one per thread per round:
+    // find the halo row (binary search over the row offsets) and the piece.
     for (int pidx = threadIdx.x; pidx < npts; pidx += kBlock) {
-      int rho = 0;
+      int r = 0;
 #pragma unroll
       for (int step = kRowStep; step > 0; step >>= 1)
-        if (rho + step < R && s_rbase[rho + step] <= pidx) rho += step;
-      const int inrow = pidx - s_rbase[rho];
-      const int pi = (inrow >= s_plo[rho][2]) ? 2 : ((inrow >= s_plo[rho][1]) ? 1 : 0);
-      const int src = s_pga[rho][pi] + (inrow - s_plo[rho][pi]);
-      const int v = tb.y0 - h + rho;
+        if (r + step < R && s_rbase[r + step] <= pidx) r += step;
+      const int inrow = pidx - s_rbase[r];
+      const int n0 = s_n0[r];
+      const bool second = inrow >= n0;
+      const int src = second ? s_ga1[r] + (inrow - n0) : s_ga0[r] + inrow;
+      const int sx = (second ? (uL < 0 ? 0 : L) : (uL < 0 ? -L : 0)) - ox0;
+      const int v = tb.y0 - hy + r;
       const int sy = (v < 0 ? -L : (v >= G ? L : 0)) - oy0;
       const int2 e = reinterpret_cast<const int2*>(w.sorted)[2 * src];
       if (wide)
-        lpos_store[pidx] = make_int2(e.x + s_psx[rho][pi], e.y + sy);
+        lpos_store[pidx] = make_int2(e.x + sx, e.y + sy);
       else
-        lpos[pidx] = pack_rel(e.x + s_psx[rho][pi], e.y + sy);
+        lpos[pidx] = pack_rel(e.x + sx, e.y + sy);
       lslot[pidx] = src;
     }
     __syncthreads();
@@ -611,48 +633,64 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
     else
       w.dflag[slot_s] = 1;  // overflow of the list: found again below by its flag
   };
-  auto row_of = [&](int qi) {  // tile row of query qi
-    int rq = 0;
+  auto row_of = [&](int qi) {  // strip row of query qi
+    int r = 0;
 #pragma unroll
     for (int step = kRowStep; step > 0; step >>= 1)
-      if (rq + step < tb.ty && s_qoff[rq + step] <= qi) rq += step;
-    return rq;
+      if (r + step < tb.ty && s_qoff[r + step] <= qi) r += step;
+    return r;
   };
-  // Relative position (halo corner origin) of the staged point with LDS index i.
-  auto rel_pos = [&](int i, int& rx, int& ry) {
+  // x offset from the halo corner and y offset inside its cell of the staged
+  // point with LDS index i (narrow y is kept modulo 2^16, a multiple of w).
+  auto rel_pos = [&](int i, int& rx, int& oy) {
     if (wide) {
       const int2 p2 = lpos_store[i];
       rx = p2.x;
-      ry = p2.y;
+      oy = p2.y & ((1 << lw) - 1);
     } else {
       const int p = lpos[i];
       rx = p & 0xFFFF;
-      ry = p >> 16;
+      oy = (p >> 16) & ((1 << lw) - 1);
     }
+  };
+  auto search = [&](int qi, int Bq, int& s_out, int (&slot)[KMAX]) {
+    const int r = row_of(qi);
+    const int self = s_tself[r] + (qi - s_qoff[r]);
+    int rx, oy;
+    rel_pos(self, rx, oy);
+    const int cy = r + hy;
+    s_out = lslot[self];
+    const int qx = rx + ox0, qy = ((cy << lw) | oy) + oy0;  // strip-image coordinates
+    if (Bq < 0) Bq = strip_block_rows(f, s_rbase, W, cy, k);
+    if (wide) {
+      const int2 p2 = lpos_store[self];
+      return strip_search<KMAX, true>(w, tc, s_rbase, lpos, lslot, W, self, p2.x, p2.y, rx, oy, cy,
+                                      qx, qy, k, Bq, slot);
+    }
+    return strip_search<KMAX, false>(w, tc, s_rbase, lpos, lslot, W, self, lpos[self], 0, rx, oy,
+                                     cy, qx, qy, k, Bq, slot);
   };
 
   if (staged && nq <= kSortCap) {
-    // Pre-pass: block side and candidate count of every query, from LDS
+    // Pre-pass: block height and candidate count of every query, from LDS
     // only; a counting sort by candidate count then gives each wavefront
     // queries of similar work (a wavefront runs as long as its longest query).
     if (threadIdx.x < kBuckets) s_hist[threadIdx.x] = 0;
     __syncthreads();
     for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
-      const int rq = row_of(qi);
-      const int self = lcell[(rq + h) * W + h] + (qi - s_qoff[rq]);
-      int rx, ry;
-      rel_pos(self, rx, ry);
-      const int cx = rx >> w.log2_w, cy = ry >> w.log2_w;
-      const int B = lds_block_side(f, lcell, W, cx, cy, k);
+      const int r = row_of(qi);
+      const int self = s_tself[r] + (qi - s_qoff[r]);
+      int rx, oy;
+      rel_pos(self, rx, oy);
+      const int cy = r + hy;
+      const int Bq = strip_block_rows(f, s_rbase, W, cy, k);
       int key = 0xFFFF;
-      if (B <= tc.bmax) {
-        const QBlock b = make_qblock(w, rx + ox0, ry + oy0, B);
-        const int row0 = (cy + b.lo_y) * W + cx + b.lo_x;
-        int nc = 0;
-        for (int r = 0; r < B; ++r) nc += lcell[row0 + r * W + B] - lcell[row0 + r * W];
+      if (Bq <= tc.bmax) {
+        const StripBlock b = strip_block(rx, oy, cy, Bq, W, lw);
+        const int nc = s_rbase[b.r0 + Bq] - s_rbase[b.r0];
         const int bk = nc < 128 ? (nc >> 2) : 32 + min((nc - 128) >> 5, kBuckets - 33);
         atomicAdd(&s_hist[bk], 1);
-        key = (bk << 4) | B;
+        key = (bk << 5) | Bq;
       } else {
         defer(lslot[self]);
       }
@@ -675,62 +713,44 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
     for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
       const int key = s_key[qi];
       if (key == 0xFFFF) continue;
-      const int pos = atomicAdd(&s_hist[key >> 4], 1);
-      s_perm[pos] = static_cast<uint16_t>((qi << 4) | (key & 15));
+      const int pos = atomicAdd(&s_hist[key >> 5], 1);
+      s_perm[pos] = static_cast<uint16_t>((qi << 5) | (key & 31));
     }
     __syncthreads();
     const int ns = s_nsorted;
     for (int j = threadIdx.x; j < ns; j += kBlock) {
       const int e = s_perm[j];
-      const int qi = e >> 4, B = e & 15;
-      const int rq = row_of(qi);
-      const int self = lcell[(rq + h) * W + h] + (qi - s_qoff[rq]);
-      int rx, ry;
-      rel_pos(self, rx, ry);
-      const int cx = rx >> w.log2_w, cy = ry >> w.log2_w;
-      int slot[KMAX];
-      const bool ok =
-          wide ? knn_lds<KMAX, true>(w, tc, lcell, lpos, lslot, W, cx, cy, self, rx, ry, rx + ox0,
-                                     ry + oy0, k, B, slot)
-               : knn_lds<KMAX, false>(w, tc, lcell, lpos, lslot, W, cx, cy, self, pack_rel(rx, ry), 0,
-                                      rx + ox0, ry + oy0, k, B, slot);
-      const int s = lslot[self];
-      if (ok) {
-        const int4 q = w.sorted[s];
-        finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
-      } else {
+      int s, slot[KMAX];
+      if (search(e >> 5, e & 31, s, slot))
+        finish_query<KMAX, kAlign>(w, s, w.sorted[s], slot, k, nbr, d2out, a);
+      else
         defer(s);
-      }
     }
   } else {
     for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
-      const int rq = row_of(qi);
-      const int s = s_qbeg[rq] + (qi - s_qoff[rq]);
-      const int4 q = w.sorted[s];
       int slot[KMAX];
-      bool ok;
       if (staged) {
-        const int self = lcell[(rq + h) * W + h] + (qi - s_qoff[rq]);
-        const int cx = (q.x >> w.log2_w) - uL, cy = rq + h;
-        const int B = lds_block_side(f, lcell, W, cx, cy, k);
-        ok = wide ? knn_lds<KMAX, true>(w, tc, lcell, lpos, lslot, W, cx, cy, self, q.x - ox0,
-                                        q.y - oy0, q.x, q.y, k, B, slot)
-                  : knn_lds<KMAX, false>(w, tc, lcell, lpos, lslot, W, cx, cy, self,
-                                         pack_rel(q.x - ox0, q.y - oy0), 0, q.x, q.y, k, B, slot);
+        int s;
+        if (search(qi, -1, s, slot))
+          finish_query<KMAX, kAlign>(w, s, w.sorted[s], slot, k, nbr, d2out, a);
+        else
+          defer(s);
       } else {
-        ok = knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot);
+        const int r = row_of(qi);
+        const int s = w.start[static_cast<int64_t>(tb.y0 + r) * G + tb.x0] + (qi - s_qoff[r]);
+        const int4 q = w.sorted[s];
+        if (knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot))
+          finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
+        else
+          defer(s);
       }
-      if (ok)
-        finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
-      else
-        defer(s);
     }
   }
   __syncthreads();
   const int nd = s_defer;
   if (nd == 0) return;
 
-  // The tile's uncertified queries, by the exact ring search.  With many,
+  // The strip's uncertified queries, by the exact ring search.  With many,
   // each lane searches its own; with a few, a wavefront searches one at a
   // time, so that a single long search is not one lane's serial chain.
   const int nl = min(nd, kDeferCap);
@@ -752,7 +772,8 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   }
   if (nd > kDeferCap) {
     for (int r = 0; r < tb.ty; ++r) {
-      const int a0 = s_qbeg[r], a1 = a0 + (s_qoff[r + 1] - s_qoff[r]);
+      const int a0 = w.start[static_cast<int64_t>(tb.y0 + r) * G + tb.x0];
+      const int a1 = a0 + (s_qoff[r + 1] - s_qoff[r]);
       for (int sq = a0 + threadIdx.x; sq < a1; sq += kBlock) {
         if (w.dflag[sq]) {
           w.dflag[sq] = 0;
@@ -815,52 +836,59 @@ __global__ __launch_bounds__(kBlock) void k_bb_knn(BatchRef b, int k) {
   }
 }
 
-// Tile geometry.  The halo h holds the blocks a query is expected to use
-// (side ~ 2 * reach * r_k / w + 1, plus one widening step); the tile side aims
-// at about 256 queries; the halo must span under 2^15 grid units for the
-// 16-bit offsets, and must not meet itself around the box.
+// Strip geometry.  Block rows: up to the expected block height plus one
+// widening step (hy); block width: all W = tw + 2 hx columns, hx the expected
+// half width.  The strip height aims at about 256 queries; the halo must fit
+// the staging buffer and the row table, W <= G (a block never meets itself
+// around the box), and narrow strips keep every block under 2^15 units.
 TileCfg tile_cfg_impl(const DevWs& w, const FastCfg& f, int k) {
-  TileCfg t{1, 0, w.G, 0, 0};
+  TileCfg t{1, 1, 0, 0, w.G, w.G, 0, 0};
   const double rho = static_cast<double>(w.n) / static_cast<double>(w.C);  // particles per cell
   const double rr = rho > 1e-12 ? rho : 1e-12;
   const double rk = sqrt(static_cast<double>(k) / (3.141592653589793 * rr));
-  const int bexp = (f.bfix > 0 ? f.bfix : static_cast<int>(ceil(2.0 * f.reach * rk)) + 1) + 2;
-  const int side0 = max(1, min(static_cast<int>(lround(sqrt(256.0 / rr))), w.G));
-  // Narrow tiles: packed 16-bit offsets, the halo spans under 2^15 units.
-  int h = f.bmax > 0 ? min((bexp + 1) / 2, (f.bmax + 1) / 2) : 0;
-  while (h > 0 && (w.G < 2 * h + 2 || ((static_cast<long long>(2 * h + 1) << w.log2_w) > 32768))) --h;
-  int side = side0;
-  if (h > 0) {
-    while (side > 1 && ((static_cast<long long>(side + 2 * h) << w.log2_w) > 32768 || side + 2 * h > kTileRows ||
-                        (side + 2 * h) * (side + 2 * h) > kTileCells ||
-                        (side + 2 * h) * (side + 2 * h) * rho > 0.75 * kTilePts))
-      --side;
-    if ((static_cast<long long>(side + 2 * h) << w.log2_w) > 32768 || side + 2 * h > kTileRows) h = 0;
-  }
-  // A halo of at least the expected block that narrow offsets cannot span:
-  // wide tiles (int32 offset pairs, half as many staged points).
-  const int hw = f.bmax_w > 0 ? min((bexp + 1) / 2, (f.bmax_w + 1) / 2) : 0;
-  if (h < hw && 2 * h + 1 < bexp) {
-    int h2 = hw;
-    while (h2 > 0 && w.G < 2 * h2 + 2) --h2;
-    int s2 = side0;
-    while (s2 > 1 && (s2 + 2 * h2 > kTileRows || (s2 + 2 * h2) * (s2 + 2 * h2) > kTileCells ||
-                      (s2 + 2 * h2) * (s2 + 2 * h2) * rho > 0.375 * kTilePts))
-      --s2;
-    if (h2 > 0 && s2 + 2 * h2 <= kTileRows && (s2 + 2 * h2) * (s2 + 2 * h2) <= kTileCells) {
-      t.t = s2;
-      t.h = h2;
-      t.ntx = (w.G + s2 - 1) / s2;
-      t.bmax = min(2 * h2 + 1, f.bmax_w);
-      t.wide = 1;
-      return t;
-    }
-  }
-  if (h == 0) side = max(1, min(side, kTileRows));
-  t.t = side;
-  t.h = h;
-  t.ntx = (w.G + side - 1) / side;
-  t.bmax = h > 0 ? min(2 * h + 1, f.bmax) : 0;
+  const int bmax_all = max(f.bmax, f.bmax_w);
+  auto plain = [&]() {  // no staging: one row of queries per strip, global search
+    t.tw = 1;
+    t.hx = t.hy = 0;
+    t.th = max(1, min(w.G, static_cast<int>(lround(256.0 / (rr * 1.0)))));
+    t.th = min(t.th, kStripRows);
+    t.ntx = w.G;
+    t.nty = (w.G + t.th - 1) / t.th;
+    t.bmax = 0;
+    return t;
+  };
+  if (bmax_all < 1) return plain();
+  const int bq = f.bfix > 0 ? f.bfix : static_cast<int>(ceil(2.0 * f.reach * rk)) + 1;
+  // (block heights travel in 5 bits of the work-sorted order: hy <= 15)
+  int hy = min((bq + 2) / 2, 15);  // rows for the block plus one widening step
+  // The block width is fixed per strip, so it covers the tail of the k-th
+  // neighbour distance, not only its mean.
+  int hx = min(max(1, static_cast<int>(ceil(kReachX * rk))), 15);
+  if (f.bfix > 0) hx = min(max(hx, f.bfix / 2), 15);
+  // Strip width: two columns once the halo is wide, and at least the
+  // narrowest power of two whose strips reach ~256 queries within the row
+  // limit.
+  int tw = hx >= 3 ? 2 : 1;  // (wider strips stage each particle fewer times)
+  while (tw < 16 && 2 * tw <= w.G && 256.0 / (tw * rr) > 1.1 * (kStripRows - 2 * hy)) tw *= 2;
+  while (hx > 1 && tw + 2 * hx > w.G) --hx;
+  while (hy > 1 && 2 * hy + 1 > w.G) --hy;
+  if (tw + 2 * hx > w.G || 2 * hy + 1 > w.G) return plain();
+  const int W = tw + 2 * hx;
+  const bool narrow = (static_cast<long long>(W) << w.log2_w) < 32768 &&
+                      (static_cast<long long>(2 * hy + 1) << w.log2_w) < 32768;
+  const int cap = narrow ? kStripPts : kStripPts / 2;
+  int th = static_cast<int>(ceil(256.0 / (tw * rr)));
+  th = max(1, min(th, w.G));
+  while (th > 1 && (th + 2 * hy > kStripRows || (th + 2 * hy) * W * rho > 0.75 * cap)) --th;
+  if (th + 2 * hy > kStripRows) return plain();
+  t.tw = tw;
+  t.th = th;
+  t.hx = hx;
+  t.hy = hy;
+  t.ntx = w.G / tw;
+  t.nty = (w.G + th - 1) / th;
+  t.bmax = min(2 * hy + 1, w.G);
+  t.wide = narrow ? 0 : 1;
   return t;
 }
 
@@ -868,7 +896,7 @@ template <int KMAX, bool kAlign>
 hipError_t launch_t(const DevWs& w, const FastCfg& f, int k, int32_t* nbr, long long* d2,
                     const AlignArgs& a, hipStream_t s) {
   const TileCfg tc = tile_cfg_impl(w, f, k);
-  const int ntiles = tc.ntx * tc.ntx;
+  const int ntiles = tc.ntx * tc.nty;
   hipLaunchKernelGGL((k_knn<KMAX, kAlign>), dim3(ntiles), dim3(kBlock), 0, s, w, f, tc, k, nbr, d2, a);
   return hipGetLastError();
 }

@@ -421,15 +421,16 @@ __device__ __forceinline__ int tag_slot(const DevWs& w, const QBlock& b, uint32_
   return w.start[g.cell0] + static_cast<int>(tag & 255u);
 }
 
-// k-NN tile geometry (knn.hip): a workgroup owns a t x t square of cells and
-// stages a halo of h cells around it.
+// k-NN strip geometry (knn.hip): a workgroup owns a strip of tw x th cells
+// and stages a halo of hx columns and hy rows around it.
 struct TileCfg {
-  int t;     // tile side in cells
-  int h;     // halo in cells (0: no staging)
-  int ntx;   // tiles per side
-  int bmax;  // largest block side the halo supports
-  int wide;  // 1: staged offsets are int32 pairs and distances 64-bit (halo
-             // spans 2^15 units or more); 0: packed 16-bit offsets
+  int tw, th;  // strip width and height in cells
+  int hx, hy;  // halo in cells (hx = 0: no staging)
+  int ntx;     // strips across (G / tw)
+  int nty;     // strips down
+  int bmax;    // largest block height (rows) the halo supports
+  int wide;    // 1: staged offsets are int32 pairs and distances 64-bit (a
+               // block spans 2^15 units or more); 0: packed 16-bit offsets
 };
 
 // Parameters and outputs of the fused Eq. (2) / Eq. (1) epilogue.
