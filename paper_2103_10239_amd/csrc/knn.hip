@@ -534,7 +534,8 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   // Work-sorted query order: per query (bucket of its candidate count, block
   // height), then the permutation (query, block height), heaviest first.
   __shared__ uint16_t s_key[kSortCap];
-  __shared__ uint16_t s_perm[kSortCap];
+  __shared__ uint32_t s_perm[kSortCap];
+  __shared__ uint8_t s_rowid[kStripPts];   // halo row of each staged particle
   __shared__ int s_hist[kBuckets];
   __shared__ int s_nsorted;
   int* lpos = reinterpret_cast<int*>(lpos_store);
@@ -602,13 +603,13 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   if (nq == 0) return;
   const bool staged = hx > 0 && npts <= (wide ? kStripPts / 2 : kStripPts);
   if (staged) {
-    // Particles as offsets from the halo corner, one per thread per round:
-    // find the halo row (binary search over the row offsets) and the piece.
+    // Row of every staged particle (one thread per halo row), then the
+    // particles as offsets from the halo corner, one per thread per round.
+    if (rho < R)
+      for (int p = rb; p < rb + rlen; ++p) s_rowid[p] = static_cast<uint8_t>(rho);
+    __syncthreads();
     for (int pidx = threadIdx.x; pidx < npts; pidx += kBlock) {
-      int r = 0;
-#pragma unroll
-      for (int step = kRowStep; step > 0; step >>= 1)
-        if (r + step < R && s_rbase[r + step] <= pidx) r += step;
+      const int r = s_rowid[pidx];
       const int inrow = pidx - s_rbase[r];
       const int n0 = s_n0[r];
       const bool second = inrow >= n0;
@@ -653,12 +654,9 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
       oy = (p >> 16) & ((1 << lw) - 1);
     }
   };
-  auto search = [&](int qi, int Bq, int& s_out, int (&slot)[KMAX]) {
-    const int r = row_of(qi);
-    const int self = s_tself[r] + (qi - s_qoff[r]);
+  auto search = [&](int self, int cy, int Bq, int& s_out, int (&slot)[KMAX]) {
     int rx, oy;
     rel_pos(self, rx, oy);
-    const int cy = r + hy;
     s_out = lslot[self];
     const int qx = rx + ox0, qy = ((cy << lw) | oy) + oy0;  // strip-image coordinates
     if (Bq < 0) Bq = strip_block_rows(f, s_rbase, W, cy, k);
@@ -714,14 +712,18 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
       const int key = s_key[qi];
       if (key == 0xFFFF) continue;
       const int pos = atomicAdd(&s_hist[key >> 5], 1);
-      s_perm[pos] = static_cast<uint16_t>((qi << 5) | (key & 31));
+      const int r = row_of(qi);
+      const int self = s_tself[r] + (qi - s_qoff[r]);
+      // (LDS index, halo row, block height)
+      s_perm[pos] = (static_cast<uint32_t>(self) << 13) | (static_cast<uint32_t>(r + hy) << 5) |
+                    static_cast<uint32_t>(key & 31);
     }
     __syncthreads();
     const int ns = s_nsorted;
     for (int j = threadIdx.x; j < ns; j += kBlock) {
-      const int e = s_perm[j];
+      const uint32_t e = s_perm[j];
       int s, slot[KMAX];
-      if (search(e >> 5, e & 31, s, slot))
+      if (search(static_cast<int>(e >> 13), static_cast<int>((e >> 5) & 255u), static_cast<int>(e & 31u), s, slot))
         finish_query<KMAX, kAlign>(w, s, w.sorted[s], slot, k, nbr, d2out, a);
       else
         defer(s);
@@ -731,7 +733,8 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
       int slot[KMAX];
       if (staged) {
         int s;
-        if (search(qi, -1, s, slot))
+        const int r = row_of(qi);
+        if (search(s_tself[r] + (qi - s_qoff[r]), r + hy, -1, s, slot))
           finish_query<KMAX, kAlign>(w, s, w.sorted[s], slot, k, nbr, d2out, a);
         else
           defer(s);
