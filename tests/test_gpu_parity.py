@@ -177,6 +177,38 @@ def test_fused_step_matches_oracle(kind, n, k, w):
     assert _angle_err(sysm.theta.cpu().numpy(), rt).max() <= TOL
 
 
+@pytest.mark.parametrize("w", [1024, 4096])
+def test_rebuild_after_arbitrary_new_positions(w):
+    # A build walks the particles in the previous build's cell order; that
+    # order must stay a complete walk whatever the new positions are.
+    n, k = 20013, 7
+    x1, y1, _ = workloads.uniform(n, seed_pos=31)
+    x2, y2, _ = workloads.clustered(n, seed=32)
+    ws = nm.Workspace(n, L, w)
+    for x, y in ((x1, y1), (x2, y2), (x1, y1), (x1, y1)):
+        nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+        nbr, d2 = nm.knn(ws, k, with_d2=True)
+        assert nm.check(ws) == 0
+        rn, rd = oracle.knn(x, y, L, k)
+        assert np.array_equal(nbr.cpu().numpy(), rn) and np.array_equal(d2.cpu().numpy(), rd)
+
+
+def test_rebuild_after_out_of_range_build():
+    # an incomplete build (a coordinate outside the box) must not be walked
+    n, k = 5000, 7
+    x, y, _ = workloads.uniform(n, seed_pos=41)
+    ws = nm.Workspace(n, L, 2048)
+    bad = x.copy()
+    bad[123] = L + 7
+    nm.build_cells(ws, _dev(bad, torch.int32), _dev(y, torch.int32))
+    assert nm.check(ws) == nm.NM_E_RANGE
+    nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+    nbr, d2 = nm.knn(ws, k, with_d2=True)
+    assert nm.check(ws) == 0
+    rn, rd = oracle.knn(x, y, L, k)
+    assert np.array_equal(nbr.cpu().numpy(), rn) and np.array_equal(d2.cpu().numpy(), rd)
+
+
 def test_fused_step_equals_separate_calls():
     n, k = 20013, 7
     x, y, th = workloads.clustered(n)
