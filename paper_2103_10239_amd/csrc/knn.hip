@@ -314,7 +314,6 @@ __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, 
                                              const int* lpos, const int* lslot, int W, int self,
                                              int pq, int pqy, int rx, int oy, int cy, int qx,
                                              int qy, int k, int Bq, int (&slot)[KMAX]) {
-  constexpr int kPts = kWide ? kStripPts / 2 : kStripPts;
   constexpr int KT = KMAX + 1;
   const int2* lpos2 = reinterpret_cast<const int2*>(lpos);
   if (Bq > tc.bmax) return false;
@@ -330,7 +329,7 @@ __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, 
       if (kWide) {
         int2 pc[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) pc[u] = lpos2[min(i + u, kPts - 1)];
+        for (int u = 0; u < kUnroll; ++u) pc[u] = lpos2[i + u];  // (buffer padded by kUnroll)
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const long long dx = pc[u].x - pq, dy = pc[u].y - pqy;
@@ -341,7 +340,7 @@ __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, 
       } else {
         int pc[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) pc[u] = lpos[min(i + u, kPts - 1)];
+        for (int u = 0; u < kUnroll; ++u) pc[u] = lpos[i + u];  // (buffer padded by kUnroll)
         const uint32_t clampd = static_cast<uint32_t>(b.bound);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -520,7 +519,9 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
                                               int k, int32_t* __restrict__ nbr,
                                               long long* __restrict__ d2out, const AlignArgs& a,
                                               int tile) {
-  __shared__ int2 lpos_store[kStripPts / 2];  // packed 16-bit pairs, or int32 pairs (wide)
+  // packed 16-bit pairs, or int32 pairs (wide); padded so that a round of
+  // kUnroll reads past a block's last candidate stays inside the buffer
+  __shared__ int2 lpos_store[kStripPts / 2 + kUnroll];
   __shared__ int lslot[kStripPts];
   __shared__ int s_rbase[kStripRows + 1];  // LDS offset of each halo row
   __shared__ int s_ga0[kStripRows];        // first slot of the row's first piece
