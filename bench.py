@@ -51,7 +51,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "particle-steps/s (k=7 kNN rebuild + align) at N=1M; batched p50/p99 latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_knn_align_uniform_1m_k7.json")
-KERNEL_SOURCES = ("knn.hip", "nm_internal.h")
+KERNEL_SOURCES = ("knn.hip", "strip.h", "nm_internal.h")
 
 
 def log(*a):

@@ -67,6 +67,9 @@ bool make_layout(const nm_grid* g, Layout* out) {
   off += round_up(32 * static_cast<int64_t>(g->n));
   L.off_dflag = off;
   off += round_up(static_cast<int64_t>(g->n));
+  L.chunk_cap = g->n / 32 + 1024;
+  L.off_chunks = off;
+  off += round_up(16 * static_cast<int64_t>(L.chunk_cap));
   L.total = off;
   *out = L;
   return true;
@@ -84,6 +87,8 @@ DevWs dev_ws(const nm_grid* g, const Layout& lay, void* ws) {
   w.sorted = reinterpret_cast<int4*>(b + lay.off_sorted);
   w.cs = reinterpret_cast<double2*>(b + lay.off_cs);
   w.dflag = reinterpret_cast<uint8_t*>(b + lay.off_dflag);
+  w.chunks = reinterpret_cast<int4*>(b + lay.off_chunks);
+  w.chunk_cap = lay.chunk_cap;
   w.n = g->n;
   w.box = g->box;
   w.cell_w = g->cell_w;

@@ -44,8 +44,10 @@ __device__ __forceinline__ void ws_init_body(const DevWs& w, int b, int nb) {
       w.hdr->box = w.box;
       w.hdr->cell_w = w.cell_w;
       w.hdr->built = 0u;
-      w.hdr->qcount = 0u;
-      w.hdr->qdone = 0u;
+      for (int ph = 0; ph < 2; ++ph) {
+        w.hdr->ndefer[ph] = 0u;
+        w.hdr->nchunk[ph] = 0u;
+      }
     }
   }
 }

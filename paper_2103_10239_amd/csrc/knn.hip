@@ -22,7 +22,7 @@
 // fp64 unit vectors stored beside the cell-ordered copy (the neighbours'
 // entries sit in the cells just scanned, so they are cache hits) and writes
 // the list, the new position and the new heading at the particle's index.
-#include "nm_internal.h"
+#include "strip.h"
 
 namespace nm {
 
@@ -249,25 +249,11 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
 // Uncertified queries are finished at the end of the strip by the exact
 // search.
 // ---------------------------------------------------------------------------
-constexpr int kStripPts = 2560;   // staged particles (wide strips: half)
-constexpr int kStripRows = 256;   // R <= kStripRows
-constexpr int kRowStep = kStripRows / 2;  // binary search over <= kStripRows rows
 constexpr int kDeferCap = 128;    // uncertified queries listed in LDS per strip
 constexpr int kSortCap = 1024;    // queries of a strip ordered by work (more: strip order)
 constexpr int kBuckets = 64;      // candidate-count buckets of that order
-constexpr int kUnroll = 4;        // candidates read per round of the block loop
 constexpr double kReachX = 1.25;  // strip half width, in mean k-th-neighbour radii
 
-typedef short short2v __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ int rel_d2(int packed_c, int packed_q) {
-  const short2v d = __builtin_bit_cast(short2v, packed_c) - __builtin_bit_cast(short2v, packed_q);
-  return __builtin_amdgcn_sdot2(d, d, 0, false);
-}
-
-__device__ __forceinline__ int pack_rel(int rx, int ry) {
-  return (rx & 0xFFFF) | (ry << 16);
-}
 
 // Block height for a staged query: fixed, or such that the block edge sits
 // `reach` mean k-th-neighbour radii away, the density taken from the three
@@ -491,28 +477,6 @@ __device__ __forceinline__ StripBox strip_box(const DevWs& w, const TileCfg& tc,
   return b;
 }
 
-// Exclusive prefix sum of v over the workgroup (thread order); *total gets
-// the sum.  Uses s_wsum[kBlock / 64].
-__device__ __forceinline__ int block_exclusive_scan(int v, int* s_wsum, int* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int incl = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int t = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += t;
-  }
-  if (lane == 63) s_wsum[wave] = incl;
-  __syncthreads();
-  int before = 0, all = 0;
-#pragma unroll
-  for (int q = 0; q < kBlock / 64; ++q) {
-    if (q < wave) before += s_wsum[q];
-    all += s_wsum[q];
-  }
-  __syncthreads();
-  *total = all;
-  return before + incl - v;
-}
 
 template <int KMAX, bool kAlign>
 __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, const TileCfg& tc,
@@ -545,88 +509,21 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
     return;
   }
   const StripBox tb = strip_box(w, tc, tile);
-  const int G = w.G, L = w.box, gm = G - 1, lw = w.log2_w;
+  const int G = w.G, lw = w.log2_w;
   const int total = min(w.start[w.C], w.n);
   const int tw = tc.tw, hx = tc.hx, hy = tc.hy;
-  const int W = tw + 2 * hx, R = tb.ty + 2 * hy;
-  const int uL = tb.x0 - hx, uR = tb.x0 + tw + hx - 1;
+  const int W = tw + 2 * hx;
+  const int uL = tb.x0 - hx;
   const int lane = threadIdx.x & 63;
   const int ox0 = uL << lw, oy0 = (tb.y0 - hy) << lw;  // halo corner (strip image)
   const bool wide = tc.wide != 0;
 
-  // Each halo row (one per thread): its one or two slot ranges (the columns
-  // [uL, uR] wrap around the box at most once since W <= G) and, for the
-  // strip's own rows, the query range.
-  int rlen = 0, qlen = 0, qrow_off = 0;
-  const int rho = threadIdx.x;
-  if (rho < R) {
-    const int v = tb.y0 - hy + rho;
-    const int64_t prow = static_cast<int64_t>(v & gm) * G;
-    if (hx > 0) {
-      const int e0 = uL < 0 ? -1 : min(uR, G - 1);  // last column of the first piece
-      const int ga0 = w.start[prow + (uL & gm)];
-      const int n0 = w.start[prow + (e0 & gm) + 1] - ga0;
-      int n1 = 0, ga1 = 0;
-      if (e0 < uR) {
-        ga1 = w.start[prow + ((e0 + 1) & gm)];
-        n1 = w.start[prow + (uR & gm) + 1] - ga1;
-      }
-      s_ga0[rho] = ga0;
-      s_n0[rho] = n0;
-      s_ga1[rho] = ga1;
-      rlen = n0 + n1;
-      // the strip's own columns start at unwrapped column x0 (in [0, G)):
-      // in the second piece when the first one is the wrapped left edge
-      qrow_off = uL < 0 ? n0 + (w.start[prow + tb.x0] - ga1) : w.start[prow + tb.x0] - ga0;
-    }
-    const int rq = rho - hy;
-    if (rq >= 0 && rq < tb.ty) {
-      const int a0 = w.start[prow + tb.x0];
-      qlen = max(min(w.start[prow + tb.x0 + tw], total) - a0, 0);
-    }
-  }
   int npts, nq;
-  const int rb = block_exclusive_scan(rlen, s_wsum, &npts);
-  if (rho < R) s_rbase[rho] = rb;
-  const int rq = rho - hy;
-  const bool qrow = rho < R && rq >= 0 && rq < tb.ty;
-  const int qo = block_exclusive_scan(qrow ? qlen : 0, s_wsum, &nq);
-  if (qrow) {
-    s_qoff[rq] = qo;
-    s_tself[rq] = rb + qrow_off;
-  }
-  if (threadIdx.x == 0) {
-    s_rbase[R] = npts;
-    s_qoff[tb.ty] = nq;
-    s_defer = 0;
-  }
-  __syncthreads();
+  const StripGeo geo{tb.x0, tb.y0, tb.ty, tw, hx, hy, wide};
+  const StripLds lds{lpos_store, lslot, s_rbase, s_ga0, s_n0, s_ga1, s_qoff, s_tself, s_wsum, s_rowid};
+  if (threadIdx.x == 0) s_defer = 0;
+  const bool staged = strip_stage<false>(w, geo, lds, total, npts, nq);
   if (nq == 0) return;
-  const bool staged = hx > 0 && npts <= (wide ? kStripPts / 2 : kStripPts);
-  if (staged) {
-    // Row of every staged particle (one thread per halo row), then the
-    // particles as offsets from the halo corner, one per thread per round.
-    if (rho < R)
-      for (int p = rb; p < rb + rlen; ++p) s_rowid[p] = static_cast<uint8_t>(rho);
-    __syncthreads();
-    for (int pidx = threadIdx.x; pidx < npts; pidx += kBlock) {
-      const int r = s_rowid[pidx];
-      const int inrow = pidx - s_rbase[r];
-      const int n0 = s_n0[r];
-      const bool second = inrow >= n0;
-      const int src = second ? s_ga1[r] + (inrow - n0) : s_ga0[r] + inrow;
-      const int sx = (second ? (uL < 0 ? 0 : L) : (uL < 0 ? -L : 0)) - ox0;
-      const int v = tb.y0 - hy + r;
-      const int sy = (v < 0 ? -L : (v >= G ? L : 0)) - oy0;
-      const int2 e = reinterpret_cast<const int2*>(w.sorted)[2 * src];
-      if (wide)
-        lpos_store[pidx] = make_int2(e.x + sx, e.y + sy);
-      else
-        lpos[pidx] = pack_rel(e.x + sx, e.y + sy);
-      lslot[pidx] = src;
-    }
-    __syncthreads();
-  }
 
   auto defer = [&](int slot_s) {
     const int pos = atomicAdd(&s_defer, 1);

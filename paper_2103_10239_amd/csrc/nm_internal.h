@@ -12,6 +12,7 @@
 //                            of the noise, fused step only
 //   dflag       uint8[n]     1 for a slot whose k-NN search is deferred (kept 0
 //                            between launches)
+//   chunks      int4[cap]    row chunks of dense metric strips, cap = n / 32 + 1024
 // C = G^2 cells, G = L / w.  Cells are numbered row-major: c = cy * G + cx.
 #pragma once
 
@@ -37,9 +38,9 @@ struct WsHeader {
   int32_t err;
   int32_t n, box, cell_w;
   uint32_t built;
-  uint32_t qcount;  // queries deferred to the exact k-NN search
-  uint32_t qdone;   // blocks of the exact-search kernel that have finished
-  int32_t pad[56];
+  uint32_t ndefer[2];  // metric rows deferred to the wave kernels (count, fill pass)
+  uint32_t nchunk[2];  // metric strip chunks pushed to the chunk kernels (count, fill pass)
+  int32_t pad[54];
 };
 static_assert(sizeof(WsHeader) == 256, "header is one 256-byte block");
 
@@ -56,10 +57,12 @@ struct DevWs {
   ScanState* scan_m;
   int32_t* count;
   int32_t* start;
-  int32_t* rank;
+  int32_t* rank;  // in-cell rank while binning; then the metric kernels' deferred list
   int4* sorted;
   double2* cs;
   uint8_t* dflag;
+  int4* chunks;
+  int32_t chunk_cap;
   int32_t n;
   int32_t box;
   int32_t cell_w;
@@ -73,8 +76,8 @@ struct DevWs {
 
 struct Layout {
   int64_t off_scan_c, off_scan_m, off_count, off_start, off_rank, off_sorted, off_cs,
-      off_dflag, total;
-  int32_t log2_box, log2_w, G, nb_scan_c, nb_scan_m;
+      off_dflag, off_chunks, total;
+  int32_t log2_box, log2_w, G, nb_scan_c, nb_scan_m, chunk_cap;
   int64_t C;
 };
 

@@ -447,6 +447,66 @@ def test_metric_fast_block_matches_oracle(kind, n, mean, w):
     assert np.array_equal(offs, ro) and np.array_equal(idx, ri)
 
 
+def _dense_patch(n_patch, n_rest, side, seed):
+    rng = np.random.default_rng(seed)
+    x = np.concatenate([500000 + rng.integers(0, side, n_patch), rng.integers(0, L, n_rest)])
+    y = np.concatenate([700000 + rng.integers(0, side, n_patch), rng.integers(0, L, n_rest)])
+    return x.astype(np.int32), y.astype(np.int32)
+
+
+@pytest.mark.parametrize("case", ["narrow", "wide_cells", "wide_halo", "box_sized_halo", "dense_patch"])
+def test_metric_strip_layouts(case):
+    # narrow: 16-bit staged offsets; wide_cells / wide_halo: int32 offsets because
+    # the halo spans 2^15 or more (large cells, or a halo of ~22 cells); box_sized_halo:
+    # 2h + 1 > G, rows walked in global memory; dense_patch: 3000 particles in a
+    # 2000 x 2000 patch overflow the staged strip and fall back beside staged ones.
+    if case == "dense_patch":
+        x, y = _dense_patch(3000, 1000, 2000, 5)
+        rc2, w = 100 ** 2, 1024
+    else:
+        n = 20013
+        x, y, _ = workloads.uniform(n)
+        mean, w = {"narrow": (7.0, 2048), "wide_cells": (7.0, 16384), "wide_halo": (30.0, 1024),
+                   "box_sized_halo": (7.0, L // 4)}[case]
+        rc2 = workloads.rc2_for_mean(n, mean)
+        if case == "box_sized_halo":  # G = 4 cells a side, h = 2
+            rc2 = (L // 4 + 100) ** 2
+            x, y = x[:500], y[:500]
+    offs, idx = _gpu_metric(x, y, rc2, w)
+    ro, ri, _ = oracle.metric_list(x, y, L, rc2)
+    assert np.array_equal(offs, ro) and np.array_equal(idx, ri)
+
+
+def test_metric_rows_longer_than_a_wave_sort():
+    # 700 coincident points: rows of 699 entries, beyond what one wave sorts in LDS,
+    # take the chunked selection; 300 more points in a ring keep other rows mid-sized.
+    rng = np.random.default_rng(9)
+    ang = rng.uniform(0, 2 * np.pi, 300)
+    x = np.concatenate([np.full(700, 300000), 300000 + np.round(80 * np.cos(ang))]).astype(np.int32)
+    y = np.concatenate([np.full(700, 90000), 90000 + np.round(80 * np.sin(ang))]).astype(np.int32)
+    offs, idx = _gpu_metric(x, y, 100 ** 2, 2048)
+    ro, ri, _ = oracle.metric_list(x, y, L, 100 ** 2)
+    assert np.array_equal(offs, ro) and np.array_equal(idx, ri)
+
+
+def test_metric_heavy_rows_sorted_by_a_wave():
+    # 300 coincident points and 150 in a 150 x 150 square beside them: rows of
+    # 200-450 entries over ~450 staged candidates are gathered and sorted by a
+    # whole wave (with many equal distances, ordered by index); sparse uniform
+    # points elsewhere keep light rows in the same launch.
+    rng = np.random.default_rng(21)
+    x = np.concatenate([np.full(300, 700000), 700000 + rng.integers(-75, 75, 150),
+                        rng.integers(0, L, 2000)]).astype(np.int32)
+    y = np.concatenate([np.full(300, 400000), 400000 + rng.integers(-75, 75, 150),
+                        rng.integers(0, L, 2000)]).astype(np.int32)
+    rc2 = 120 ** 2
+    for w in (1024, 8192):
+        offs, idx = _gpu_metric(x, y, rc2, w)
+        ro, ri, _ = oracle.metric_list(x, y, L, rc2)
+        assert np.array_equal(offs, ro) and np.array_equal(idx, ri)
+        assert (np.diff(ro)[:450] > 150).all()
+
+
 def test_knn_fast_path_query_last_in_home_row():
     # Particle 0 is the only particle in its block row, so both parts of its home
     # row around its own slot are empty; its nearest neighbour (1) lies in the next
