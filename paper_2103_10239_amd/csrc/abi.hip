@@ -70,6 +70,21 @@ bool make_layout(const nm_grid* g, Layout* out) {
   L.chunk_cap = g->n / 32 + 1024;
   L.off_chunks = off;
   off += round_up(16 * static_cast<int64_t>(L.chunk_cap));
+  // two-level binning when a coarse bin of at most kFineCells cells suffices
+  L.sb = 0;
+  while ((L.C >> L.sb) > kCoarseBins) ++L.sb;
+  if ((int64_t(1) << L.sb) <= kFineCells) {
+    L.nbins = static_cast<int32_t>((L.C + (int64_t(1) << L.sb) - 1) >> L.sb);
+    L.nblk = (g->n + kCoarseP - 1) / kCoarseP;
+    const int64_t hsize = static_cast<int64_t>(L.nbins) * L.nblk + 1;
+    L.nb_scan_h = static_cast<int32_t>((hsize + kScanTile - 1) / kScanTile);
+    L.off_coarse = off;
+    off += round_up(16 * static_cast<int64_t>(g->n));
+    L.off_hist = off;
+    off += round_up(4 * hsize);
+    L.off_scan_h = off;
+    off += round_up(256 + 8 * static_cast<int64_t>(L.nb_scan_h));
+  }
   L.total = off;
   *out = L;
   return true;
@@ -89,6 +104,15 @@ DevWs dev_ws(const nm_grid* g, const Layout& lay, void* ws) {
   w.dflag = reinterpret_cast<uint8_t*>(b + lay.off_dflag);
   w.chunks = reinterpret_cast<int4*>(b + lay.off_chunks);
   w.chunk_cap = lay.chunk_cap;
+  w.sb = lay.sb;
+  w.nbins = lay.nbins;
+  w.nblk = lay.nblk;
+  w.nb_scan_h = lay.nb_scan_h;
+  if (lay.nbins > 0) {
+    w.coarse = reinterpret_cast<int4*>(b + lay.off_coarse);
+    w.hist = reinterpret_cast<int32_t*>(b + lay.off_hist);
+    w.scan_h = reinterpret_cast<ScanState*>(b + lay.off_scan_h);
+  }
   w.n = g->n;
   w.box = g->box;
   w.cell_w = g->cell_w;

@@ -246,6 +246,169 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* __restric
 }
 
 // ---------------------------------------------------------------------------
+// Two-level binning for one system per launch: no device-wide atomics, and
+// the sorted copy is written bin by bin.
+//   coarse_count    workgroup b takes particles [b P, (b+1) P) and counts
+//                   them per coarse bin (2^sb consecutive cells) in LDS;
+//                   hist[bin * nblk + b] = that count
+//   scan            exclusive prefix sum of hist (bin-major order): the first
+//                   coarse-order slot of each (bin, workgroup)
+//   coarse_scatter  each particle, with its heading bits, to its
+//                   (bin, workgroup) range (order inside by LDS atomics)
+//   fine_sort       one workgroup per bin: counting sort of the bin's
+//                   particles by cell in LDS, the bin's part of the cell
+//                   start table, and the sorted copy (the fused step also
+//                   draws the Philox noise word and stores the fp64 unit
+//                   vectors here)
+// The result is the same cell start table and the same cell-ordered copy as
+// the one-level binning, up to the order inside each cell.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool ws_header_ok(const DevWs& w) {
+  const WsHeader* h = w.hdr;
+  return h->magic == kMagic && h->n == w.n && h->box == w.box && h->cell_w == w.cell_w;
+}
+
+__device__ __forceinline__ bool in_box(int xi, int yi, const DevWs& w) {
+  return static_cast<uint32_t>(xi) < static_cast<uint32_t>(w.box) &&
+         static_cast<uint32_t>(yi) < static_cast<uint32_t>(w.box);
+}
+
+__global__ __launch_bounds__(kBlock) void k_coarse_count(const int32_t* __restrict__ x,
+                                                         const int32_t* __restrict__ y, DevWs w) {
+  __shared__ int h[kCoarseBins];
+  const int b = blockIdx.x;
+  if (b == 0) {
+    reset_scan(w.scan_h, w.nb_scan_h);
+    if (threadIdx.x == 0) {
+      if (!ws_header_ok(w)) set_err(w.hdr, NM_E_INVAL);
+      w.hdr->built = 0u;
+    }
+  }
+  for (int t = threadIdx.x; t < w.nbins; t += kBlock) h[t] = 0;
+  __syncthreads();
+  const int i1 = min((b + 1) * kCoarseP, w.n);
+  for (int i = b * kCoarseP + threadIdx.x; i < i1; i += kBlock) {
+    const int xi = x[i], yi = y[i];
+    if (!in_box(xi, yi, w)) {
+      set_err(w.hdr, NM_E_RANGE);
+      continue;
+    }
+    const int64_t c = static_cast<int64_t>(yi >> w.log2_w) * w.G + (xi >> w.log2_w);
+    atomicAdd(&h[static_cast<int>(c >> w.sb)], 1);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < w.nbins; t += kBlock)
+    w.hist[static_cast<int64_t>(t) * w.nblk + b] = h[t];
+}
+
+template <bool kFused>
+__global__ __launch_bounds__(kBlock) void k_coarse_scatter(const int32_t* __restrict__ x,
+                                                           const int32_t* __restrict__ y,
+                                                           const float* __restrict__ theta, DevWs w) {
+  __shared__ int cur[kCoarseBins];
+  if (!ws_header_ok(w)) return;
+  const int b = blockIdx.x;
+  for (int t = threadIdx.x; t < w.nbins; t += kBlock) cur[t] = w.hist[static_cast<int64_t>(t) * w.nblk + b];
+  __syncthreads();
+  const int i1 = min((b + 1) * kCoarseP, w.n);
+  for (int i = b * kCoarseP + threadIdx.x; i < i1; i += kBlock) {
+    const int xi = x[i], yi = y[i];
+    if (!in_box(xi, yi, w)) continue;
+    const int64_t c = static_cast<int64_t>(yi >> w.log2_w) * w.G + (xi >> w.log2_w);
+    const int pos = atomicAdd(&cur[static_cast<int>(c >> w.sb)], 1);
+    if (static_cast<uint32_t>(pos) >= static_cast<uint32_t>(w.n)) {  // inconsistent table
+      set_err(w.hdr, NM_E_INVAL);
+      continue;
+    }
+    w.coarse[pos] = make_int4(xi, yi, i, kFused ? __float_as_int(theta[i]) : 0);
+  }
+}
+
+template <bool kFused>
+__global__ __launch_bounds__(kBlock) void k_fine_sort(DevWs w, uint32_t step_lo, uint32_t step_hi,
+                                                      uint32_t sys_id, uint32_t seed_lo,
+                                                      uint32_t seed_hi) {
+  __shared__ int h[kFineCells];
+  __shared__ int s_wsum[kBlock / 64];
+  if (!ws_header_ok(w)) return;
+  const int bin = blockIdx.x;
+  const int64_t m = static_cast<int64_t>(w.nbins) * w.nblk;
+  const int b0 = w.hist[static_cast<int64_t>(bin) * w.nblk];
+  const int b1 = bin + 1 < w.nbins ? w.hist[static_cast<int64_t>(bin + 1) * w.nblk] : w.hist[m];
+  const int64_t c0 = static_cast<int64_t>(bin) << w.sb;
+  const int S = static_cast<int>(min(static_cast<int64_t>(1) << w.sb, w.C - c0));
+  if (b0 < 0 || b1 < b0 || b1 > w.n) {  // inconsistent table
+    if (threadIdx.x == 0) set_err(w.hdr, NM_E_INVAL);
+    return;
+  }
+  for (int t = threadIdx.x; t < S; t += kBlock) h[t] = 0;
+  __syncthreads();
+  auto cell_of = [&](const int4& e) {
+    return static_cast<int>(static_cast<int64_t>(e.y >> w.log2_w) * w.G + (e.x >> w.log2_w) - c0);
+  };
+  for (int p = b0 + threadIdx.x; p < b1; p += kBlock) {
+    const int cl = cell_of(w.coarse[p]);
+    if (static_cast<uint32_t>(cl) < static_cast<uint32_t>(S))
+      atomicAdd(&h[cl], 1);
+    else
+      set_err(w.hdr, NM_E_INVAL);  // inconsistent table
+  }
+  __syncthreads();
+  // exclusive prefix over the bin's cells: kFineCells / kBlock consecutive cells per lane
+  constexpr int kPer = kFineCells / kBlock;
+  const int j0 = threadIdx.x * kPer;
+  int cnt[kPer];
+  int sum = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    cnt[j] = j0 + j < S ? h[j0 + j] : 0;
+    sum += cnt[j];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) s_wsum[wave] = incl;
+  __syncthreads();
+  int run = incl - sum;
+#pragma unroll
+  for (int q = 0; q < kBlock / 64; ++q)
+    if (q < wave) run += s_wsum[q];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    if (j0 + j < S) {
+      h[j0 + j] = run;
+      w.start[c0 + j0 + j] = b0 + run;
+    }
+    run += cnt[j];
+  }
+  if (bin == w.nbins - 1 && threadIdx.x == 0) w.start[w.C] = b1;
+  __syncthreads();
+  for (int p = b0 + threadIdx.x; p < b1; p += kBlock) {
+    const int4 e = w.coarse[p];
+    const int cl = cell_of(e);
+    if (static_cast<uint32_t>(cl) >= static_cast<uint32_t>(S)) continue;
+    const int pos = b0 + atomicAdd(&h[cl], 1);
+    uint32_t word = 0u;
+    if (kFused) {
+      const uint4 blk = Philox::block(make_uint4(static_cast<uint32_t>(e.z) >> 2, step_lo, step_hi, sys_id),
+                                      seed_lo, seed_hi);
+      word = uint4_word(blk, e.z & 3);
+      double sn, cs, xs, xc;
+      sincos(static_cast<double>(__int_as_float(e.w)), &sn, &cs);
+      sincos(noise_angle(word), &xs, &xc);
+      w.cs[2 * pos] = make_double2(cs, sn);      // unit vector of the heading at time t
+      w.cs[2 * pos + 1] = make_double2(xc, xs);  // the random unit vector xi of Eq. (2)
+    }
+    w.sorted[pos] = make_int4(e.x, e.y, e.z, static_cast<int>(word));
+  }
+  if (bin == 0 && threadIdx.x == 0) w.hdr->built = kBuilt;
+}
+
+// ---------------------------------------------------------------------------
 // Batched stages.  Workgroup g of a persistent launch takes the stage's items
 // g, g + gridDim.x, ...; an item is one workgroup's share of one system.
 // ---------------------------------------------------------------------------
@@ -307,6 +470,25 @@ hipError_t launch_ws_init(const DevWs& w, hipStream_t s) {
 
 hipError_t launch_build(const DevWs& w, const int32_t* x, const int32_t* y, const float* theta,
                         const nm_params* p, uint64_t step, hipStream_t s) {
+  const bool fused = theta != nullptr && p != nullptr;
+  if (w.nbins > 0) {  // two-level
+    hipLaunchKernelGGL(k_coarse_count, dim3(w.nblk), dim3(kBlock), 0, s, x, y, w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t m = static_cast<int64_t>(w.nbins) * w.nblk;
+    e = launch_scan_rows(w.hist, m, w.scan_h, static_cast<int>((m + kScanTile - 1) / kScanTile), w.hdr, s);
+    if (e != hipSuccess) return e;
+    if (fused) {
+      hipLaunchKernelGGL(k_coarse_scatter<true>, dim3(w.nblk), dim3(kBlock), 0, s, x, y, theta, w);
+      hipLaunchKernelGGL(k_fine_sort<true>, dim3(w.nbins), dim3(kBlock), 0, s, w,
+                         static_cast<uint32_t>(step), static_cast<uint32_t>(step >> 32), p->sys_id,
+                         static_cast<uint32_t>(p->seed), static_cast<uint32_t>(p->seed >> 32));
+    } else {
+      hipLaunchKernelGGL(k_coarse_scatter<false>, dim3(w.nblk), dim3(kBlock), 0, s, x, y, theta, w);
+      hipLaunchKernelGGL(k_fine_sort<false>, dim3(w.nbins), dim3(kBlock), 0, s, w, 0u, 0u, 0u, 0u, 0u);
+    }
+    return hipGetLastError();
+  }
   const int nb = (w.n + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_bin_count, dim3(nb), dim3(kBlock), 0, s, x, y, w);
   hipError_t e = hipGetLastError();
@@ -316,7 +498,7 @@ hipError_t launch_build(const DevWs& w, const int32_t* x, const int32_t* y, cons
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int nq = (w.n + 4 * kBlock - 1) / (4 * kBlock);
-  if (theta != nullptr && p != nullptr) {
+  if (fused) {
     hipLaunchKernelGGL(k_bin_scatter<true>, dim3(nq), dim3(kBlock), 0, s, x, y, theta, w,
                        static_cast<uint32_t>(step), static_cast<uint32_t>(step >> 32), p->sys_id,
                        static_cast<uint32_t>(p->seed), static_cast<uint32_t>(p->seed >> 32));

@@ -13,6 +13,10 @@
 //   dflag       uint8[n]     1 for a slot whose k-NN search is deferred (kept 0
 //                            between launches)
 //   chunks      int4[cap]    row chunks of dense metric strips, cap = n / 32 + 1024
+//   coarse      int4[n]      particles in coarse-bin order (two-level binning)
+//   hist        int32[nbins * nblk + 1]  per-workgroup coarse-bin counts, then
+//                            their exclusive prefix sum (bin-major)
+//   scan_hist   ScanState for that prefix sum
 // C = G^2 cells, G = L / w.  Cells are numbered row-major: c = cy * G + cx.
 #pragma once
 
@@ -28,6 +32,11 @@ namespace nm {
 constexpr int kBlock = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
+// Two-level binning: coarse bins are runs of 2^sb consecutive cells, at most
+// kCoarseBins of them; the first pass takes kCoarseP particles per workgroup.
+constexpr int kCoarseBins = 1024;
+constexpr int kCoarseP = 4096;
+constexpr int kFineCells = 4096;  // cells per coarse bin the LDS sort takes (else one-level)
 constexpr uint32_t kMagic = 0x4E4D5753u;  // "NMWS"
 constexpr uint32_t kBuilt = 0x42554C54u;  // "BULT"
 constexpr int kKeyIndexBits = 24;         // particle index field of a search key
@@ -62,7 +71,11 @@ struct DevWs {
   double2* cs;
   uint8_t* dflag;
   int4* chunks;
+  int4* coarse;
+  int32_t* hist;
+  ScanState* scan_h;
   int32_t chunk_cap;
+  int32_t sb, nbins, nblk, nb_scan_h;  // two-level binning (nbins == 0: one-level)
   int32_t n;
   int32_t box;
   int32_t cell_w;
@@ -76,8 +89,8 @@ struct DevWs {
 
 struct Layout {
   int64_t off_scan_c, off_scan_m, off_count, off_start, off_rank, off_sorted, off_cs,
-      off_dflag, off_chunks, total;
-  int32_t log2_box, log2_w, G, nb_scan_c, nb_scan_m, chunk_cap;
+      off_dflag, off_chunks, off_coarse, off_hist, off_scan_h, total;
+  int32_t log2_box, log2_w, G, nb_scan_c, nb_scan_m, chunk_cap, sb, nbins, nblk, nb_scan_h;
   int64_t C;
 };
 
