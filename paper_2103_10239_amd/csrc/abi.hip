@@ -73,7 +73,7 @@ bool make_layout(const nm_grid* g, Layout* out) {
   // two-level binning when a coarse bin of at most kFineCells cells suffices
   L.sb = 0;
   while ((L.C >> L.sb) > kCoarseBins) ++L.sb;
-  if ((int64_t(1) << L.sb) <= kFineCells) {
+  if ((int64_t(1) << L.sb) <= kFineCells && g->n >= kCoarseMinN) {
     L.nbins = static_cast<int32_t>((L.C + (int64_t(1) << L.sb) - 1) >> L.sb);
     L.nblk = (g->n + kCoarseP - 1) / kCoarseP;
     const int64_t hsize = static_cast<int64_t>(L.nbins) * L.nblk + 1;

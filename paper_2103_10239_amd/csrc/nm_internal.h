@@ -37,6 +37,7 @@ constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kCoarseBins = 1024;
 constexpr int kCoarseP = 4096;
 constexpr int kFineCells = 4096;  // cells per coarse bin the LDS sort takes (else one-level)
+constexpr int kCoarseMinN = 1 << 17;  // smaller systems: one-level binning (fewer launches)
 constexpr uint32_t kMagic = 0x4E4D5753u;  // "NMWS"
 constexpr uint32_t kBuilt = 0x42554C54u;  // "BULT"
 constexpr int kKeyIndexBits = 24;         // particle index field of a search key

@@ -323,6 +323,47 @@ def test_full_size_clustered_4m_sampled(k):
     assert _angle_err(sysm.theta[sel].cpu().numpy(), rt).max() <= TOL
 
 
+@pytest.mark.parametrize("kind,w", [("uniform", 512), ("uniform", 2048), ("clustered", 1024),
+                                    ("uniform", 16384), ("uniform", 4096)])
+def test_two_level_binning_sampled(kind, w):
+    # N >= 2^17 takes the two-level binning (coarse bins of up to 4096 cells at
+    # w = 512, of 4 cells at w = 16384); ragged N, one fused step, sampled rows.
+    n, k = (1 << 17) + 1234, 7
+    if kind == "clustered":
+        x, y, th = workloads.clustered(n)
+    else:
+        x, y, th = _gen(kind, n)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    sysm = nm.System.create(x, y, th, k, p, cell_w=w)
+    sysm.step()
+    assert nm.check(sysm.ws) == 0
+    _device_invariants(_dev(x, torch.int32), _dev(y, torch.int32), sysm.nbr, k)
+    rows = np.concatenate([_sample_rows(n, 300, w), [0, n - 1]]).astype(np.int32)
+    rn, _ = oracle.knn(x, y, L, k, rows=rows, with_d2=False)
+    sel = torch.as_tensor(rows).long().cuda()
+    assert np.array_equal(sysm.nbr[sel].cpu().numpy(), rn)
+    rx, ry, rt = oracle.align_step(x, y, th, L, nbr=rn, v0=64, eta=0.2, seed=workloads.NOISE_SEED,
+                                   rows=rows)
+    assert np.array_equal(sysm.x[sel].cpu().numpy(), rx) and np.array_equal(sysm.y[sel].cpu().numpy(), ry)
+    assert _angle_err(sysm.theta[sel].cpu().numpy(), rt).max() <= TOL
+    rc2 = workloads.rc2_for_mean(n, 5.0)
+    offs, idx = nm.metric_list(sysm.ws, rc2)
+    assert nm.check(sysm.ws) == 0
+    ro, ri, _ = oracle.metric_list(x, y, L, rc2, rows=rows, with_d2=False)
+    offs_np, idx_np = offs.cpu().numpy().astype(np.int64), idx.cpu().numpy()
+    assert np.array_equal(np.diff(ro), offs_np[rows + 1] - offs_np[rows])
+    assert np.array_equal(np.concatenate([idx_np[offs_np[r]:offs_np[r + 1]] for r in rows]), ri)
+
+
+def test_two_level_binning_reports_range_error():
+    n = (1 << 17) + 5
+    x, y, th = workloads.uniform(n)
+    x[70000] = L
+    ws = nm.Workspace(n, L, 2048)
+    nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+    assert nm.check(ws) == nm.NM_E_RANGE
+
+
 def test_range_error_is_reported():
     n = 1000
     x, y, th = workloads.uniform(n)
