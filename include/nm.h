@@ -77,6 +77,19 @@ typedef struct nm_grid {
                   /* lists are identical for every choice; only speed differs.    */
 } nm_grid;
 
+/* Variants of the step (nm_params.variant), from the Vicsek-model family the
+ * paper's alignment rule belongs to (Sec. III); 0 is Eq. (2) and Eq. (1) as
+ * written:
+ *   NM_NOISE_SCALAR      angular noise instead of Eq. (2)'s random unit
+ *                        vector: theta' = arg(A) + eta * phi, A the average of
+ *                        the unit vectors (theta itself when A = 0), phi the
+ *                        same Philox noise angle in [-pi, pi); the result is
+ *                        wrapped into [-pi, pi)
+ *   NM_MOVE_NEW_HEADING  Eq. (1) with the new heading n_i(t+1) instead of
+ *                        n_i(t) */
+#define NM_NOISE_SCALAR 1u
+#define NM_MOVE_NEW_HEADING 2u
+
 /* Parameters of Eq. (1) and Eq. (2). */
 typedef struct nm_params {
   int32_t box;          /* L, same rules as nm_grid.box                            */
@@ -85,7 +98,7 @@ typedef struct nm_params {
   int32_t include_self; /* 1: own heading joins the average, 0: it does not       */
   uint64_t seed;        /* Philox key                                              */
   uint32_t sys_id;      /* Philox counter word 3 (system identity)                 */
-  uint32_t reserved;    /* must be 0                                               */
+  uint32_t variant;     /* 0, or NM_NOISE_SCALAR and/or NM_MOVE_NEW_HEADING         */
 } nm_params;
 
 /* Human-readable name of a status code (static string). */
@@ -153,6 +166,14 @@ int nm_align_step(const int32_t* x, const int32_t* y, const float* theta, int32_
                   const int32_t* nbr, const int32_t* offsets, int32_t k, int64_t nnz_cap,
                   const nm_params* p, uint64_t step, int32_t* x_out, int32_t* y_out,
                   float* theta_out, void* ws_err, void* stream);
+
+/* Polar order parameter of the headings (Sec. III: the ordered, flocking
+ * phase is the one whose headings agree): sums[0] = sum_i cos theta_i,
+ * sums[1] = sum_i sin theta_i, in fp64, into the caller's DEVICE double[2];
+ * the order parameter is |(sums[0], sums[1])| / n.  theta: device fp32[n],
+ * n >= 1.  Enqueued on `stream` without synchronising; the summation order
+ * varies between calls (the sums agree to fp64 rounding). */
+int nm_polar_order(const float* theta, int32_t n, double* sums, void* stream);
 
 /* One full step of the topological model (Alg. 1) = nm_bin_step followed by
  * nm_knn_align.  Same results as nm_build_cells + nm_knn + nm_align_step

@@ -71,8 +71,10 @@ def _load():
     lib.orc_align_step.argtypes = [_i32p, _i32p, _f32p, ctypes.c_int32, ctypes.c_int32,
                                    _i32p, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint64,
-                                   _vp, ctypes.c_int32, _i32p, _i32p, _f32p]
+                                   _vp, ctypes.c_int32, _i32p, _i32p, _f32p, ctypes.c_uint32]
     lib.orc_align_step.restype = ctypes.c_int
+    lib.orc_polar_order.argtypes = [_f32p, ctypes.c_int32]
+    lib.orc_polar_order.restype = ctypes.c_double
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -150,8 +152,10 @@ def metric_list(x, y, box: int, rc2: int, rows=None, with_d2: bool = True):
 
 
 def align_step(x, y, theta, box: int, nbr=None, offsets=None, idx=None, *, v0: int, eta: float,
-               seed: int, sys_id: int = 0, include_self: int = 1, step: int = 0, rows=None):
-    """Eq. (2) then Eq. (1) for each listed particle, fp64.
+               seed: int, sys_id: int = 0, include_self: int = 1, step: int = 0, rows=None,
+               variant: int = 0):
+    """Eq. (2) then Eq. (1) for each listed particle, fp64 (variant bit 0:
+    angular noise; bit 1: move with the new heading).
 
     Neighbour lists are either ``nbr`` (int32[rows, k]) or CSR ``offsets`` +
     ``idx``.  Returns (x', y', theta') for the listed rows.
@@ -173,16 +177,22 @@ def align_step(x, y, theta, box: int, nbr=None, offsets=None, idx=None, *, v0: i
     yo = np.zeros(nr, dtype=np.int32)
     to = np.zeros(nr, dtype=np.float32)
     rc = _load().orc_align_step(x, y, theta, n, box, lst, offp, k, v0, eta, seed, sys_id,
-                                include_self, step, rp, nr, xo, yo, to)
+                                include_self, step, rp, nr, xo, yo, to, variant)
     _check(rc, "align_step")
     return xo, yo, to
 
 
+def polar_order(theta) -> float:
+    """Polar order parameter |sum_i (cos, sin) theta_i| / N, fp64 in index order."""
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    return float(_load().orc_polar_order(th, int(th.size)))
+
+
 def step(x, y, theta, box: int, k: int, *, v0: int, eta: float, seed: int, sys_id: int = 0,
-         include_self: int = 1, step_index: int = 0):
+         include_self: int = 1, step_index: int = 0, variant: int = 0):
     """One full step of the fundamental loop (Alg. 1) in the topological model:
     rebuild the k-NN lists from r(t), then Eq. (2) and Eq. (1) from time-t state."""
     nbr, _ = knn(x, y, box, k, with_d2=False)
     xo, yo, to = align_step(x, y, theta, box, nbr=nbr, v0=v0, eta=eta, seed=seed, sys_id=sys_id,
-                            include_self=include_self, step=step_index)
+                            include_self=include_self, step=step_index, variant=variant)
     return nbr, xo, yo, to

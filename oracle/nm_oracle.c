@@ -30,6 +30,13 @@
  *     (include_self), the zero vector keeps the old heading, and the move uses
  *     the heading at time t (Eq. 1), rounded to the integer grid with
  *     round-half-even;
+ *   - two variants of the step, from the Vicsek-model family the alignment
+ *     rule belongs to (flags in `variant`): angular noise (bit 0), where the
+ *     new heading is the direction of the average plus eta times the noise
+ *     angle, wrapped into [-pi, pi) (the particle's own heading stands in for
+ *     the direction of a zero average); and the move with the new heading
+ *     n_i(t+1) (bit 1);
+ *   - the polar order parameter |sum_i n_i| / N of the headings;
  *   - noise word for particle i at step t of system s is word (i mod 4) of
  *     Philox4x32-10(counter = (i / 4, t mod 2^32, t >> 32, s),
  *                   key = (seed mod 2^32, seed >> 32)),
@@ -260,8 +267,9 @@ int orc_align_step(const int32_t* x, const int32_t* y, const float* theta, int32
                    int32_t box, const int32_t* nbr, const int64_t* offsets, int32_t k,
                    int32_t v0, float eta, uint64_t seed, uint32_t sys_id,
                    int32_t include_self, uint64_t step, const int32_t* rows,
-                   int32_t nrows, int32_t* x_out, int32_t* y_out, float* theta_out) {
-  if (n < 1 || box < 1) return ORC_E_INVAL;
+                   int32_t nrows, int32_t* x_out, int32_t* y_out, float* theta_out,
+                   uint32_t variant) {
+  if (n < 1 || box < 1 || (variant & ~3u) != 0) return ORC_E_INVAL;
   if (!offsets && k < 0) return ORC_E_INVAL;
   if (check_coords(x, y, n, box) != ORC_OK) return ORC_E_RANGE;
   int32_t count = rows ? nrows : n;
@@ -297,19 +305,34 @@ int orc_align_step(const int32_t* x, const int32_t* y, const float* theta, int32
       ay = sy / (double)m;
     }
 
-    /* Vectorial noise: eta times a random unit vector xi_i. */
     double phi = orc_noise_angle(seed, sys_id, step, i);
     double e = (double)eta;
-    double vx = ax + e * cos(phi);
-    double vy = ay + e * sin(phi);
-
-    /* Normalisation: only the direction matters; the zero vector keeps theta. */
     float th_new = theta[i];
-    if (!(vx == 0.0 && vy == 0.0)) th_new = (float)atan2(vy, vx);
+    if (variant & 1u) {
+      /* Angular noise: the direction of the average (the old heading when
+       * the average vanishes) turned by eta * phi, then brought back into
+       * [-pi, pi) by whole turns. */
+      double base = (ax == 0.0 && ay == 0.0) ? (double)theta[i] : atan2(ay, ax);
+      double t = base + e * phi;
+      double turn = 2.0 * M_PI;
+      th_new = (float)(t - turn * floor((t + M_PI) / turn));
+    } else {
+      /* Vectorial noise: eta times a random unit vector xi_i. */
+      double vx = ax + e * cos(phi);
+      double vy = ay + e * sin(phi);
+      /* Normalisation: only the direction matters; the zero vector keeps theta. */
+      if (!(vx == 0.0 && vy == 0.0)) th_new = (float)atan2(vy, vx);
+    }
 
-    /* Euler move with the heading at time t, on the integer grid. */
-    int64_t dx = (int64_t)rint((double)v0 * own_c);
-    int64_t dy = (int64_t)rint((double)v0 * own_s);
+    /* Euler move on the integer grid, with the heading at time t (Eq. 1) or,
+     * in the variant, the new one. */
+    double mc = own_c, ms = own_s;
+    if (variant & 2u) {
+      mc = cos((double)th_new);
+      ms = sin((double)th_new);
+    }
+    int64_t dx = (int64_t)rint((double)v0 * mc);
+    int64_t dy = (int64_t)rint((double)v0 * ms);
     int64_t nx = ((int64_t)x[i] + dx) % box;
     int64_t ny = ((int64_t)y[i] + dy) % box;
     if (nx < 0) nx += box;
@@ -320,6 +343,18 @@ int orc_align_step(const int32_t* x, const int32_t* y, const float* theta, int32
     theta_out[r] = th_new;
   }
   return bad ? ORC_E_INVAL : ORC_OK;
+}
+
+/* Polar order parameter: |sum_i (cos theta_i, sin theta_i)| / n, summed in
+ * index order in fp64. */
+double orc_polar_order(const float* theta, int32_t n) {
+  if (n < 1) return -1.0;
+  double c = 0.0, s = 0.0;
+  for (int32_t i = 0; i < n; ++i) {
+    c += cos((double)theta[i]);
+    s += sin((double)theta[i]);
+  }
+  return sqrt(c * c + s * s) / (double)n;
 }
 
 /* Number of OpenMP threads the oracle runs on (for reporting). */

@@ -28,7 +28,7 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 int status_of(hipError_t e) { return e == hipSuccess ? NM_OK : NM_E_DEVICE; }
 
 bool params_ok(const nm_params* p) {
-  if (p == nullptr || p->reserved != 0) return false;
+  if (p == nullptr || (p->variant & ~kVariantMask) != 0) return false;
   if (!is_pow2(p->box) || p->box < 2 || p->box > (1 << 20)) return false;
   if (2ll * (p->v0 < 0 ? -static_cast<int64_t>(p->v0) : p->v0) >= p->box) return false;
   if (!(p->eta >= 0.0f) || !isfinite(p->eta)) return false;
@@ -212,6 +212,11 @@ int nm_metric_list(const nm_grid* g, void* ws, int64_t rc2, int32_t* offsets, in
   }
   if (idx == nullptr) return NM_OK;
   return status_of(launch_metric_fill(w, rc2, offsets, idx, cap, s));
+}
+
+int nm_polar_order(const float* theta, int32_t n, double* sums, void* stream) {
+  if (theta == nullptr || sums == nullptr || n < 1) return NM_E_INVAL;
+  return status_of(launch_polar_order(theta, n, sums, as_stream(stream)));
 }
 
 int nm_align_step(const int32_t* x, const int32_t* y, const float* theta, int32_t n,

@@ -16,6 +16,7 @@ struct StepArgs {
   int32_t v0;
   float eta;
   int32_t include_self;
+  uint32_t variant;
   uint32_t seed_lo, seed_hi, sys_id, step_lo, step_hi;
 };
 
@@ -71,25 +72,71 @@ __global__ __launch_bounds__(kBlock) void k_align(const int32_t* __restrict__ x,
   }
   const uint4 blk = Philox::block(make_uint4(static_cast<uint32_t>(i >> 2), a.step_lo, a.step_hi,
                                              a.sys_id), a.seed_lo, a.seed_hi);
+  const double phi = noise_angle(uint4_word(blk, i & 3));
   double sp, cp;
-  sincos(noise_angle(uint4_word(blk, i & 3)), &sp, &cp);
-  const double e = static_cast<double>(a.eta);
-  const double vx = ax + e * cp;
-  const double vy = ay + e * sp;
-  theta_out[i] = vec_angle(vx, vy, th0);
+  sincos(phi, &sp, &cp);
+  const float thn = heading_update(ax, ay, cp, sp, phi, a.eta, &th0, a.variant);
+  theta_out[i] = thn;
 
   const int xi = x[i], yi = y[i];
   if (static_cast<uint32_t>(xi) >= static_cast<uint32_t>(a.box) ||
       static_cast<uint32_t>(yi) >= static_cast<uint32_t>(a.box))
     set_err(err, NM_E_RANGE);
-  const int ddx = static_cast<int>(rint(static_cast<double>(a.v0) * own_c));
-  const int ddy = static_cast<int>(rint(static_cast<double>(a.v0) * own_s));
+  int ddx, ddy;
+  move_step(a.v0, own_c, own_s, thn, a.variant, ddx, ddy);
   const int mask = a.box - 1;
   x_out[i] = (xi + ddx) & mask;
   y_out[i] = (yi + ddy) & mask;
 }
 
+// Polar order parameter: sums of cos and sin of the headings, fp64.  Each
+// workgroup reduces a strided share in registers and LDS, then adds its two
+// sums to the output with one atomic each (vector memory atomics).
+__global__ __launch_bounds__(64) void k_order_zero(double* sums) {
+  if (threadIdx.x < 2) sums[threadIdx.x] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_polar_order(const float* __restrict__ theta, int32_t n,
+                                                        double* __restrict__ sums) {
+  __shared__ double s_c[kBlock / 64], s_s[kBlock / 64];
+  double c = 0.0, s = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    double sn, cs;
+    sincos(static_cast<double>(theta[i]), &sn, &cs);
+    c += cs;
+    s += sn;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    c += __shfl_xor(c, off, 64);
+    s += __shfl_xor(s, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_c[wave] = c;
+    s_s[wave] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tc = 0.0, ts = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) {
+      tc += s_c[q];
+      ts += s_s[q];
+    }
+    atomicAdd(&sums[0], tc);
+    atomicAdd(&sums[1], ts);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_polar_order(const float* theta, int32_t n, double* sums, hipStream_t s) {
+  hipLaunchKernelGGL(k_order_zero, dim3(1), dim3(64), 0, s, sums);
+  const int grid = max(1, min(1024, (n + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_polar_order, dim3(grid), dim3(kBlock), 0, s, theta, n, sums);
+  return hipGetLastError();
+}
 
 hipError_t launch_align(const int32_t* x, const int32_t* y, const float* theta, int32_t n,
                         const int32_t* nbr, const int32_t* offsets, int32_t k, long long nnz_cap,
@@ -99,6 +146,7 @@ hipError_t launch_align(const int32_t* x, const int32_t* y, const float* theta, 
              p->v0,
              p->eta,
              p->include_self,
+             p->variant,
              static_cast<uint32_t>(p->seed),
              static_cast<uint32_t>(p->seed >> 32),
              p->sys_id,

@@ -72,6 +72,7 @@ BatchSys make_batch_sys(const SysSpec& s, int k) {
   d.v0 = s.v0;
   d.eta = s.eta;
   d.include_self = s.include_self;
+  d.variant = s.variant;
   d.sys_id = s.sys_id;
   d.seed_lo = static_cast<uint32_t>(s.seed);
   d.seed_hi = static_cast<uint32_t>(s.seed >> 32);
@@ -183,6 +184,7 @@ void build_tables(nm_batch* b, const std::vector<int>& which, std::vector<BatchS
     sp.v0 = b->p.v0;
     sp.eta = b->p.eta;
     sp.include_self = b->p.include_self;
+    sp.variant = b->p.variant;
     sp.seed = b->p.seed;
     sp.sys_id = b->sys_id[s];
     sp.step = b->step0 + static_cast<uint64_t>(b->steps_done);
@@ -255,7 +257,7 @@ int nm_batch_plan(int32_t nsys, const int32_t* n, int32_t box, int32_t k, const 
   if (out == nullptr || ws_bytes == nullptr || n == nullptr || p == nullptr) return NM_E_INVAL;
   *out = nullptr;
   if (nsys < 1 || nsys > NM_BATCH_MAX_SYS || k < 1 || k > NM_MAX_K) return NM_E_INVAL;
-  if (p->box != box || p->reserved != 0 || (p->include_self != 0 && p->include_self != 1))
+  if (p->box != box || (p->variant & ~kVariantMask) != 0 || (p->include_self != 0 && p->include_self != 1))
     return NM_E_INVAL;
   if (!(p->eta >= 0.0f) || !isfinite(p->eta) || 2ll * llabs(static_cast<long long>(p->v0)) >= box)
     return NM_E_INVAL;

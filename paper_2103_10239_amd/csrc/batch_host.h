@@ -20,6 +20,7 @@ struct SysSpec {
   int32_t v0;
   float eta;
   int32_t include_self;
+  uint32_t variant;
   uint64_t seed;
   uint32_t sys_id;
   uint64_t step;   // Philox step of the system's next step

@@ -219,14 +219,12 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
   }
   const double m = static_cast<double>(k + (a.include_self ? 1 : 0));
   const double ax = sx / m, ay = sy / m;
-  const double e = static_cast<double>(a.eta);
-  const double vx = ax + e * xi.x;
-  const double vy = ay + e * xi.y;
-  const float th = (vx == 0.0 && vy == 0.0) ? a.theta[q.z] : vec_angle(vx, vy, 0.0f);
+  const float th = heading_update(ax, ay, xi.x, xi.y, noise_angle(static_cast<uint32_t>(q.w)), a.eta,
+                                  a.theta + q.z, a.variant);
 
-  // Eq. (1): move with the heading at time t, rounded to the grid (half to even).
-  const int ddx = static_cast<int>(rint(static_cast<double>(a.v0) * own.x));
-  const int ddy = static_cast<int>(rint(static_cast<double>(a.v0) * own.y));
+  // Eq. (1): move with the heading at time t (or the new one), rounded to the grid.
+  int ddx, ddy;
+  move_step(a.v0, own.x, own.y, th, a.variant, ddx, ddy);
   const int mask = w.box - 1;
   a.x_out[q.z] = (q.x + ddx) & mask;
   a.y_out[q.z] = (q.y + ddy) & mask;
@@ -709,6 +707,7 @@ __device__ __forceinline__ AlignArgs uniform_load_align(const BatchSys* d) {
   a.v0 = __builtin_amdgcn_readfirstlane(d->v0);
   a.eta = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, d->eta)));
   a.include_self = __builtin_amdgcn_readfirstlane(d->include_self);
+  a.variant = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(d->variant)));
   a.theta = uniform_ptr(d->th[p]);
   a.x_out = uniform_ptr(d->x[1 - p]);
   a.y_out = uniform_ptr(d->y[1 - p]);
@@ -867,7 +866,7 @@ hipError_t launch_knn_align(const DevWs& w, int k, int block, const nm_params* p
                             int32_t* nbr, int32_t* x_out, int32_t* y_out, float* theta_out,
                             hipStream_t s) {
   const FastCfg f = fast_cfg(w, k, block);
-  AlignArgs a{p->v0, p->eta, p->include_self, theta, x_out, y_out, theta_out};
+  AlignArgs a{p->v0, p->eta, p->include_self, p->variant, theta, x_out, y_out, theta_out};
   return dispatch_k(k, [&](auto km) {
     return launch_t<decltype(km)::value, true>(w, f, k, nbr, nullptr, a, s);
   });

@@ -174,6 +174,57 @@ __device__ __forceinline__ float vec_angle(double vx, double vy, float keep) {
   return atan2f(static_cast<float>(ldexp(vy, -ex)), static_cast<float>(ldexp(vx, -ex)));
 }
 
+constexpr uint32_t kVariantMask = NM_NOISE_SCALAR | NM_MOVE_NEW_HEADING;
+
+// The two variants, out of line so that the default path keeps its
+// register footprint in the kernels that inline it.
+//   angular noise: arg(A) + eta phi in fp64 (th + eta phi when A = 0),
+//                  wrapped into [-pi, pi) by t - 2pi floor((t + pi) / 2pi);
+//   new-heading move: v0 (cos, sin) of the new heading, rounded half to even.
+inline __device__ __noinline__ float scalar_noise_heading(double ax, double ay, double phi, float eta,
+                                                         float th) {
+  const double base = (ax == 0.0 && ay == 0.0) ? static_cast<double>(th) : atan2(ay, ax);
+  const double t = base + static_cast<double>(eta) * phi;
+  const double two_pi = 6.283185307179586;  // fp64(2 pi)
+  return static_cast<float>(t - two_pi * floor((t + 3.141592653589793) / two_pi));
+}
+
+inline __device__ __noinline__ int2 new_heading_move(int v0, float thn) {
+  double s, c;
+  sincos(static_cast<double>(thn), &s, &c);
+  return make_int2(static_cast<int>(rint(static_cast<double>(v0) * c)),
+                   static_cast<int>(rint(static_cast<double>(v0) * s)));
+}
+
+// New heading of particle with heading *thp (read only when needed), from
+// the average (ax, ay) of the unit vectors of Eq. (2) (zero when there are
+// none) and its noise angle phi with unit vector (xc, xs): the direction of
+// A + eta xi, the zero vector keeping the heading (Eq. (2)), or the angular
+// noise variant.
+__device__ __forceinline__ float heading_update(double ax, double ay, double xc, double xs, double phi,
+                                                float eta, const float* thp, uint32_t variant) {
+  if (variant & NM_NOISE_SCALAR) return scalar_noise_heading(ax, ay, phi, eta, *thp);
+  const double e = static_cast<double>(eta);
+  const double vx = ax + e * xc;
+  const double vy = ay + e * xs;
+  return (vx == 0.0 && vy == 0.0) ? *thp : vec_angle(vx, vy, 0.0f);
+}
+
+// Displacement of Eq. (1), rounded to the grid (half to even): v0 times the
+// unit vector (own_c, own_s) of the heading at time t, or of the new heading
+// thn with NM_MOVE_NEW_HEADING.
+__device__ __forceinline__ void move_step(int v0, double own_c, double own_s, float thn, uint32_t variant,
+                                          int& ddx, int& ddy) {
+  if (variant & NM_MOVE_NEW_HEADING) {
+    const int2 d = new_heading_move(v0, thn);
+    ddx = d.x;
+    ddy = d.y;
+    return;
+  }
+  ddx = static_cast<int>(rint(static_cast<double>(v0) * own_c));
+  ddy = static_cast<int>(rint(static_cast<double>(v0) * own_s));
+}
+
 // ---------------------------------------------------------------------------
 // Register-resident sorted list of the KMAX smallest 64-bit keys.  The first
 // KMAX - k entries hold the sentinel 0 (below every real key, which is >= 1),
@@ -455,6 +506,7 @@ struct AlignArgs {
   int32_t v0;
   float eta;
   int32_t include_self;
+  uint32_t variant;  // NM_NOISE_SCALAR, NM_MOVE_NEW_HEADING
   const float* theta;
   int32_t* x_out;
   int32_t* y_out;
@@ -482,6 +534,7 @@ struct BatchSys {
   int32_t v0;
   float eta;
   int32_t include_self;
+  uint32_t variant;
   uint32_t sys_id, seed_lo, seed_hi;
   uint32_t step_lo, step_hi;  // Philox step of the next step (device-updated)
   int32_t parity;             // buffer holding the current state (device-updated)
@@ -536,6 +589,7 @@ int batch_grid(const void* kernel, int items);
 hipError_t launch_batch_bin(const BatchRef& b, int stage, hipStream_t s);
 hipError_t launch_batch_knn(const BatchRef& b, int k, hipStream_t s);
 hipError_t launch_batch_advance(const BatchRef& b, hipStream_t s);
+hipError_t launch_polar_order(const float* theta, int32_t n, double* sums, hipStream_t s);
 hipError_t launch_align(const int32_t* x, const int32_t* y, const float* theta, int32_t n,
                         const int32_t* nbr, const int32_t* offsets, int32_t k, long long nnz_cap,
                         const nm_params* p, uint64_t step, int32_t* x_out, int32_t* y_out,

@@ -223,6 +223,7 @@ bool start_job(nm_server* s, Job* j) {
   sp.v0 = j->p.v0;
   sp.eta = j->p.eta;
   sp.include_self = j->p.include_self;
+  sp.variant = j->p.variant;
   sp.seed = j->p.seed;
   sp.sys_id = j->p.sys_id;
   sp.step = 0;
@@ -473,7 +474,7 @@ int nm_server_submit(nm_server* s, const nm_job* job, int64_t* id) {
   const nm_params& p = job->p;
   if (job->n < 2 || job->k < 1 || job->k > NM_MAX_K || job->k > job->n - 1 || job->nsteps < 1)
     return NM_E_INVAL;
-  if (job->x == nullptr || job->y == nullptr || job->theta == nullptr || p.reserved != 0) return NM_E_INVAL;
+  if (job->x == nullptr || job->y == nullptr || job->theta == nullptr || (p.variant & ~nm::kVariantMask) != 0) return NM_E_INVAL;
   if (p.include_self != 0 && p.include_self != 1) return NM_E_INVAL;
   if (!(p.eta >= 0.0f) || !isfinite(p.eta) || 2ll * llabs(static_cast<long long>(p.v0)) >= p.box)
     return NM_E_INVAL;

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libnm.so")
 
 NM_OK, NM_E_INVAL, NM_E_RANGE, NM_E_CAPACITY, NM_E_NOMEM, NM_E_DEVICE = 0, -1, -2, -3, -4, -5
 NM_MAX_K = 32
+NM_NOISE_SCALAR, NM_MOVE_NEW_HEADING = 1, 2  # nm_params.variant flags
 
 _c_i32, _c_i64, _c_u32, _c_u64, _vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                        ctypes.c_uint64, ctypes.c_void_p)
@@ -39,7 +40,7 @@ class Grid(ctypes.Structure):
 class Params(ctypes.Structure):
     """nm_params: Eq. (1) and Eq. (2) parameters and the Philox identity."""
     _fields_ = [("box", _c_i32), ("v0", _c_i32), ("eta", ctypes.c_float), ("include_self", _c_i32),
-                ("seed", _c_u64), ("sys_id", _c_u32), ("reserved", _c_u32)]
+                ("seed", _c_u64), ("sys_id", _c_u32), ("variant", _c_u32)]
 
 
 class BatchIO(ctypes.Structure):
@@ -93,6 +94,7 @@ def lib():
     L.nm_bin_step.argtypes = [gp, _vp, _vp, _vp, pp, _c_u64, _vp, ctypes.c_size_t, _vp]
     L.nm_knn_align.argtypes = [gp, _vp, _c_i32, pp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.nm_check.argtypes = [_vp, _vp]
+    L.nm_polar_order.argtypes = [_vp, _c_i32, _vp, _vp]
     L.nm_tune_grid.argtypes = [gp, _c_i32, _vp, _vp, _vp, _c_i32, pp, _c_u64, _vp, ctypes.c_size_t,
                                _vp, _vp, _vp, _vp, _c_i32, ctypes.POINTER(_c_i32),
                                ctypes.POINTER(ctypes.c_float), _vp]
@@ -156,8 +158,21 @@ def suggest_cell_w(n: int, box: int, per_cell: float = 2.0) -> int:
 
 
 def make_params(box: int, v0: int = 64, eta: float = 0.2, include_self: int = 1, seed: int = 0,
-                sys_id: int = 0) -> Params:
-    return Params(box, v0, eta, include_self, seed, sys_id, 0)
+                sys_id: int = 0, variant: int = 0) -> Params:
+    """variant: 0 (Eq. (2) and Eq. (1)), or NM_NOISE_SCALAR and/or NM_MOVE_NEW_HEADING."""
+    return Params(box, v0, eta, include_self, seed, sys_id, variant)
+
+
+def polar_order(theta: torch.Tensor, sums: torch.Tensor | None = None) -> float:
+    """Polar order parameter |sum_i (cos, sin) theta_i| / n of device headings
+    (synchronises to read the two fp64 sums)."""
+    n = int(theta.numel())
+    if sums is None:
+        sums = torch.empty(2, dtype=torch.float64, device=theta.device)
+    _ok(lib().nm_polar_order(_dev(theta, torch.float32, n, "theta"), n,
+                             _dev(sums, torch.float64, 2, "sums"), _stream(theta.device)), "polar_order")
+    c, s = sums.cpu().tolist()
+    return float((c * c + s * s) ** 0.5 / n)
 
 
 class Workspace:

@@ -70,9 +70,13 @@ def test_host_checks_return_before_any_launch():
     assert lib.nm_build_cells(ctypes.byref(g), fake, fake, ctypes.c_void_p(300), 1 << 30, None) == nm.NM_E_INVAL
     # metric radius out of range
     assert lib.nm_metric_list(ctypes.byref(g), fake, -1, fake, None, 0, None, None) == nm.NM_E_INVAL
-    # bad parameters: box not a power of two, |v0| >= L/2, negative eta, reserved != 0
+    # polar order: null pointers, no headings
+    assert lib.nm_polar_order(None, 10, fake, None) == nm.NM_E_INVAL
+    assert lib.nm_polar_order(fake, 0, fake, None) == nm.NM_E_INVAL
+    assert lib.nm_polar_order(fake, 10, None, None) == nm.NM_E_INVAL
+    # bad parameters: box not a power of two, |v0| >= L/2, negative eta, unknown variant bit
     for p in (nm.Params(1000, 64, 0.2, 1, 0, 0, 0), nm.Params(1 << 20, 1 << 19, 0.2, 1, 0, 0, 0),
-              nm.Params(1 << 20, 64, -0.1, 1, 0, 0, 0), nm.Params(1 << 20, 64, 0.2, 1, 0, 0, 1),
+              nm.Params(1 << 20, 64, -0.1, 1, 0, 0, 0), nm.Params(1 << 20, 64, 0.2, 1, 0, 0, 4),
               nm.Params(1 << 20, 64, float("nan"), 1, 0, 0, 0), nm.Params(1 << 20, 64, 0.2, 2, 0, 0, 0)):
         assert lib.nm_align_step(fake, fake, fake, 16, fake, None, 7, 0, ctypes.byref(p), 0,
                                  ctypes.c_void_p(512), ctypes.c_void_p(768), ctypes.c_void_p(1024),

@@ -88,6 +88,25 @@ def test_batch_first_step_matches_oracle(k):
     b.close()
 
 
+def test_batch_variants_first_step_match_oracle():
+    sizes = [8, 300, 1025, 5000]
+    xs, ys, ts = _systems(sizes, clustered_every=2, seed=23)
+    v = nm.NM_NOISE_SCALAR | nm.NM_MOVE_NEW_HEADING
+    p = nm.make_params(L, v0=64, eta=0.5, seed=31, variant=v)
+    b = nm.Batch(sizes, np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), 7, p, step0=2)
+    b.step(1)
+    torch.cuda.synchronize()
+    assert b.check() == 0
+    for s in range(len(sizes)):
+        rn, rx, ry, rt = oracle.step(xs[s], ys[s], ts[s], L, 7, v0=64, eta=0.5, seed=31, sys_id=s,
+                                     step_index=2, variant=v)
+        bx, by, bt, bn = (t.cpu().numpy() for t in b.system(s))
+        assert np.array_equal(bn, rn), f"system {s}"
+        assert np.array_equal(bx, rx) and np.array_equal(by, ry), f"system {s}"
+        assert _angle_err(bt, rt).max() <= TOL, f"system {s}"
+    b.close()
+
+
 def test_batch_graph_replays_match_eager():
     """Replays of the captured step, with eager work and synchronisation in
     between, against a batch stepped without the graph."""

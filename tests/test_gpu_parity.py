@@ -162,6 +162,64 @@ def test_align_step_metric_mode(include_self):
     assert _angle_err(to.cpu().numpy(), rt).max() <= TOL
 
 
+@pytest.mark.parametrize("variant", [nm.NM_NOISE_SCALAR, nm.NM_MOVE_NEW_HEADING,
+                                     nm.NM_NOISE_SCALAR | nm.NM_MOVE_NEW_HEADING])
+@pytest.mark.parametrize("include_self,eta", [(1, 0.2), (0, 1.0), (1, 0.0)])
+def test_align_step_variants_match_oracle(variant, include_self, eta):
+    n, k = 4097, 7
+    x, y, th = workloads.clustered(n)
+    rn, _ = oracle.knn(x, y, L, k)
+    p = nm.make_params(L, v0=64, eta=eta, include_self=include_self, seed=77, sys_id=2, variant=variant)
+    xo, yo, to = nm.align_step(_dev(x, torch.int32), _dev(y, torch.int32), _dev(th, torch.float32), p,
+                               4, nbr=_dev(rn, torch.int32))
+    torch.cuda.synchronize()
+    rx, ry, rt = oracle.align_step(x, y, th, L, nbr=rn, v0=64, eta=eta, seed=77, sys_id=2,
+                                   include_self=include_self, step=4, variant=variant)
+    assert np.array_equal(xo.cpu().numpy(), rx) and np.array_equal(yo.cpu().numpy(), ry)
+    assert _angle_err(to.cpu().numpy(), rt).max() <= TOL
+    # metric mode, with isolated particles (empty rows)
+    rc2 = workloads.rc2_for_mean(n, 2.0)
+    ro, ri, _ = oracle.metric_list(x, y, L, rc2)
+    xo, yo, to = nm.align_step(_dev(x, torch.int32), _dev(y, torch.int32), _dev(th, torch.float32), p, 4,
+                               offsets=_dev(ro, torch.int32), idx=_dev(ri, torch.int32))
+    torch.cuda.synchronize()
+    rx, ry, rt = oracle.align_step(x, y, th, L, offsets=ro, idx=ri, v0=64, eta=eta, seed=77, sys_id=2,
+                                   include_self=include_self, step=4, variant=variant)
+    assert np.array_equal(xo.cpu().numpy(), rx) and np.array_equal(yo.cpu().numpy(), ry)
+    assert _angle_err(to.cpu().numpy(), rt).max() <= TOL
+
+
+@pytest.mark.parametrize("variant", [nm.NM_NOISE_SCALAR, nm.NM_MOVE_NEW_HEADING,
+                                     nm.NM_NOISE_SCALAR | nm.NM_MOVE_NEW_HEADING])
+@pytest.mark.parametrize("kind,n,w", [("uniform", 4097, 2048), ("clustered", (1 << 17) + 3, 1024)])
+def test_fused_step_variants_match_oracle(variant, kind, n, w):
+    k = 7
+    x, y, th = _gen(kind, n) if kind == "uniform" else workloads.clustered(n)
+    p = nm.make_params(L, v0=64, eta=0.4, seed=workloads.NOISE_SEED, variant=variant)
+    sysm = nm.System.create(x, y, th, k, p, cell_w=w)
+    sysm.step()
+    assert nm.check(sysm.ws) == 0
+    rows = None if n < 10000 else np.concatenate([_sample_rows(n, 400, 3), [0, n - 1]]).astype(np.int32)
+    rn, _ = oracle.knn(x, y, L, k, rows=rows, with_d2=False)
+    rx, ry, rt = oracle.align_step(x, y, th, L, nbr=rn, v0=64, eta=0.4, seed=workloads.NOISE_SEED,
+                                   rows=rows, variant=variant)
+    sel = torch.arange(n, device="cuda") if rows is None else torch.as_tensor(rows).long().cuda()
+    assert np.array_equal(sysm.nbr[sel].cpu().numpy(), rn)
+    assert np.array_equal(sysm.x[sel].cpu().numpy(), rx) and np.array_equal(sysm.y[sel].cpu().numpy(), ry)
+    assert _angle_err(sysm.theta[sel].cpu().numpy(), rt).max() <= TOL
+
+
+@pytest.mark.parametrize("n", [1, 1000, 100003, 1 << 20])
+def test_polar_order_matches_oracle(n):
+    rng = np.random.default_rng(n)
+    for th in (rng.uniform(-np.pi, np.pi, n).astype(np.float32),
+               (0.3 + 0.05 * rng.standard_normal(n)).astype(np.float32)):
+        got = nm.polar_order(_dev(th, torch.float32))
+        ref = oracle.polar_order(th)
+        assert abs(got - ref) <= 1e-12 * max(1.0, ref) + 1e-13
+    assert abs(nm.polar_order(_dev(np.full(n, -1.1, np.float32), torch.float32)) - 1.0) < 1e-12
+
+
 @pytest.mark.parametrize("kind,n,k,w", [("uniform", 1024, 7, 2048), ("clustered", 8191, 12, 2048),
                                         ("uniform", 20013, 20, 1024), ("uniform", 2, 1, L // 2),
                                         ("squeezed", 3000, 7, 2048)])

@@ -95,6 +95,21 @@ def test_served_first_step_matches_oracle():
     srv.close()
 
 
+def test_served_variant_first_step_matches_oracle():
+    srv = nm.Server(budget_bytes=1 << 30)
+    v = nm.NM_NOISE_SCALAR | nm.NM_MOVE_NEW_HEADING
+    x, y, th = _inputs(2500, True, 8)
+    p = nm.make_params(L, v0=64, eta=0.6, seed=workloads.NOISE_SEED, sys_id=8, variant=v)
+    res = srv.wait(srv.submit(x, y, th, 7, 1, p, want_nbr=True))
+    srv.close()
+    rn, rx, ry, rt = oracle.step(x, y, th, L, 7, v0=64, eta=0.6, seed=workloads.NOISE_SEED, sys_id=8,
+                                 step_index=0, variant=v)
+    assert res["status"] == 0
+    assert np.array_equal(res["nbr"], rn)
+    assert np.array_equal(res["x"], rx) and np.array_equal(res["y"], ry)
+    assert _angle_err(res["theta"], rt).max() <= TOL
+
+
 def test_served_alone_equals_in_mix():
     n, k, steps, seed = 30000, 7, 40, 99
     x, y, th = _inputs(n, True, seed)

@@ -422,3 +422,92 @@ def test_align_half_angle_identity(include_self, k):
                                  include_self=include_self)
     phi = np.array([oracle.noise_angle(21, 0, 8, i) for i in range(n)])
     assert np.abs(_wrap_angle(to - phi / 2)).max() < 1e-6
+
+
+# --------------------------------------------------------------------------
+# Step variants (the Vicsek-model family of Sec. III's alignment rule) and
+# the polar order parameter of the ordered phase.
+# --------------------------------------------------------------------------
+def _wrap(a):
+    return np.remainder(np.asarray(a, np.float64) + np.pi, 2 * np.pi) - np.pi
+
+
+def _aligned_state(n, th0, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.integers(0, L, n).astype(np.int32)
+    y = rng.integers(0, L, n).astype(np.int32)
+    return x, y, np.full(n, th0, np.float32)
+
+
+def test_angular_noise_without_noise_is_the_average_direction():
+    # eta = 0: both noise forms reduce to the direction of the neighbours' average
+    x, y, th = workloads.uniform(2000, seed_pos=3)
+    nbr, _ = oracle.knn(x, y, L, 7, with_d2=False)
+    for include_self in (0, 1):
+        _, _, tv = oracle.align_step(x, y, th, L, nbr=nbr, v0=64, eta=0.0, seed=1,
+                                     include_self=include_self)
+        _, _, ts = oracle.align_step(x, y, th, L, nbr=nbr, v0=64, eta=0.0, seed=1,
+                                     include_self=include_self, variant=1)
+        assert np.abs(_wrap(ts.astype(np.float64) - tv)).max() < 1e-6
+        assert ts.min() >= -np.pi and ts.max() < np.pi + 1e-6  # wrapped into [-pi, pi)
+
+
+@pytest.mark.parametrize("eta", [1.0, 0.25])
+def test_angular_noise_is_uniform_in_eta_pi(eta):
+    # Aligned headings: the average is the common heading, so the increment is
+    # the angular noise alone, uniform on [-eta pi, eta pi) and, particle by
+    # particle, eta times that particle's noise angle (pinned by the Philox
+    # known answers above).
+    from scipy.stats import kstest
+    n, th0 = 20000, 0.7
+    x, y, th = _aligned_state(n, th0, 5)
+    nbr, _ = oracle.knn(x, y, L, 5, with_d2=False)
+    _, _, to = oracle.align_step(x, y, th, L, nbr=nbr, v0=64, eta=eta, seed=9, step=3, variant=1)
+    inc = _wrap(to.astype(np.float64) - th0)
+    assert np.abs(inc).max() <= eta * np.pi + 1e-6
+    assert kstest(inc / (eta * np.pi), "uniform", args=(-1.0, 2.0)).pvalue > 1e-3
+    phi = np.array([oracle.noise_angle(9, 0, 3, i) for i in range(0, n, 97)])
+    assert np.abs(_wrap(inc[::97] - eta * phi)).max() < 1e-5
+    # the vectorial form's increments are not uniform in angle (they are the
+    # direction of a unit vector plus eta times a random one)
+    _, _, tv = oracle.align_step(x, y, th, L, nbr=nbr, v0=64, eta=eta, seed=9, step=3)
+    if eta == 0.25:
+        assert np.abs(_wrap(tv.astype(np.float64) - th0)).max() <= math.asin(0.25) + 1e-6
+
+
+def test_move_with_new_heading_follows_it():
+    # Eq. (1) with n_i(t+1): the grid displacement points along the new heading
+    # (within the rounding of v0 (cos, sin) to integers), not the old one.
+    n, v0 = 3000, 64
+    x, y, th = workloads.uniform(n, seed_pos=11)
+    nbr, _ = oracle.knn(x, y, L, 7, with_d2=False)
+    for variant in (2, 3):
+        xo, yo, to = oracle.align_step(x, y, th, L, nbr=nbr, v0=v0, eta=2.0, seed=4, variant=variant)
+        dx = ((xo.astype(np.int64) - x + L // 2) % L) - L // 2
+        dy = ((yo.astype(np.int64) - y + L // 2) % L) - L // 2
+        r = np.hypot(dx, dy)
+        assert np.abs(r - v0).max() <= 1 / math.sqrt(2) + 1e-9
+        ang = np.abs(_wrap(np.arctan2(dy, dx) - to.astype(np.float64)))
+        assert ang.max() <= math.asin((1 / math.sqrt(2)) / (v0 - 1)) + 1e-9
+        old = np.abs(_wrap(np.arctan2(dy, dx) - th.astype(np.float64)))
+        assert (old > 0.1).mean() > 0.5  # large noise: the old heading is mostly not followed
+    # without noise and with aligned headings the two moves coincide
+    x, y, th = _aligned_state(500, -2.2, 13)
+    nbr, _ = oracle.knn(x, y, L, 4, with_d2=False)
+    a = oracle.align_step(x, y, th, L, nbr=nbr, v0=v0, eta=0.0, seed=4)
+    b = oracle.align_step(x, y, th, L, nbr=nbr, v0=v0, eta=0.0, seed=4, variant=2)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_polar_order_closed_forms():
+    assert abs(oracle.polar_order(np.full(1000, 1.234, np.float32)) - 1.0) < 1e-12
+    ring = (2 * np.pi * np.arange(1000) / 1000 - np.pi).astype(np.float32)
+    assert oracle.polar_order(ring) < 1e-6
+    assert abs(oracle.polar_order(np.array([0.0, np.pi / 2], np.float32)) - math.sqrt(0.5)) < 1e-7
+    # two opposite headings cancel; a third decides
+    assert abs(oracle.polar_order(np.array([0.5, 0.5 - np.pi, 0.5], np.float32)) - 1 / 3) < 1e-7
+    rng = np.random.default_rng(2)
+    th = rng.uniform(-np.pi, np.pi, 5000).astype(np.float32)
+    rot = _wrap(th.astype(np.float64) + 1.0).astype(np.float32)
+    assert abs(oracle.polar_order(th) - oracle.polar_order(rot)) < 1e-6
+    assert oracle.polar_order(th) < 5 / math.sqrt(5000)  # disordered: O(1/sqrt N)
