@@ -71,7 +71,9 @@ def parse():
     ap.add_argument("--metric-steps", type=int, default=100)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--served-seconds", type=float, default=15.0)
+    ap.add_argument("--variant-steps", type=int, default=100)
     ap.add_argument("--no-metric", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -270,6 +272,57 @@ def bench_metric(args, torch, nm, workloads):
     return {"rc2": rc2, "steps": steps, "ms_per_step": ms_step, "metric_list_ms": m_ms,
             "particle_steps_per_s": n / (ms_step * 1e-3), "final_mean_degree": nnz / n,
             "metric_list_roofline_frac": (8 + 4 + 4 * nnz / n) * n / (m_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def bench_variants(args, torch, nm, workloads):
+    """The step variants from the same uniform start on a fixed grid (w = 2048,
+    block 4): each timed over args.variant_steps full steps (binning + fused
+    k-NN/align), every step's polar order parameter timed beside."""
+    n, k, box = args.n, args.k, workloads.BOX
+    dev = torch.device("cuda:0")
+    x, y, th = workloads.uniform(n)
+    out = {"steps": args.variant_steps, "grid": [2048, 4]}
+    sums = torch.empty(2, dtype=torch.float64, device=dev)
+    order_ms = []
+    for name, var in (("eq2_old_heading", 0), ("angular_noise", nm.NM_NOISE_SCALAR),
+                      ("new_heading_move", nm.NM_MOVE_NEW_HEADING),
+                      ("angular_noise_new_heading", nm.NM_NOISE_SCALAR | nm.NM_MOVE_NEW_HEADING)):
+        p = nm.make_params(box, v0=64, eta=0.2, include_self=1, seed=workloads.NOISE_SEED, variant=var)
+        X, Y, T = (torch.as_tensor(a).to(dev) for a in (x, y, th))
+        s = {"x": X, "y": Y, "t": T, "xb": torch.empty_like(X), "yb": torch.empty_like(Y),
+             "tb": torch.empty_like(T)}
+        ws = nm.Workspace(n, box, 2048, dev, block=4)
+        nbr = torch.empty((n, k), dtype=torch.int32, device=dev)
+        steps = args.variant_steps
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for warm in (True, False):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(3 if warm else steps):
+                nm.bin_step(ws, s["x"], s["y"], s["t"], p, i)
+                nm.knn_align(ws, k, p, s["t"], nbr, s["xb"], s["yb"], s["tb"])
+                s["x"], s["xb"] = s["xb"], s["x"]
+                s["y"], s["yb"] = s["yb"], s["y"]
+                s["t"], s["tb"] = s["tb"], s["t"]
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        if nm.check(ws) != 0:
+            raise RuntimeError(f"device error in variant {name}")
+        e0.record()
+        for _ in range(20):
+            nm.nm.lib().nm_polar_order(s["t"].data_ptr(), n, sums.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        e1.record()
+        torch.cuda.synchronize()
+        order_ms.append(e0.elapsed_time(e1) / 20)
+        ms = (t1 - t0) * 1e3 / steps
+        out[name] = {"variant": var, "ms_per_step": ms, "particle_steps_per_s": n / (ms * 1e-3),
+                     "final_polar_order": nm.polar_order(s["t"], sums)}
+        log(f"[bench] variant {name}: {ms:.4f} ms/step, polar order after {steps} steps "
+            f"{out[name]['final_polar_order']:.4f}")
+    o = sum(order_ms) / len(order_ms)
+    out["polar_order_kernel_ms"] = o
+    out["polar_order_roofline_frac"] = 4 * n / (o * 1e-3) / 1e9 / HBM_PEAK_GBS
+    return out
 
 
 def bench_batched(args, torch, nm, workloads):
@@ -544,6 +597,8 @@ def main():
     }
     if not args.no_metric:
         out["metric_list"] = bench_metric(args, torch, nm, workloads)
+    if not args.no_variants:
+        out["variants"] = bench_variants(args, torch, nm, workloads)
     if not args.no_batched:
         out["batched"] = bench_batched(args, torch, nm, workloads)
     if not args.no_served:

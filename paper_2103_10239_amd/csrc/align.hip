@@ -133,7 +133,9 @@ __global__ __launch_bounds__(kBlock) void k_polar_order(const float* __restrict_
 
 hipError_t launch_polar_order(const float* theta, int32_t n, double* sums, hipStream_t s) {
   hipLaunchKernelGGL(k_order_zero, dim3(1), dim3(64), 0, s, sums);
-  const int grid = max(1, min(1024, (n + kBlock - 1) / kBlock));
+  // one workgroup per CU at most: the two same-address atomics per workgroup
+  // are serialised where the memory is, so fewer, longer workgroups are faster
+  const int grid = max(1, min(256, (n + kBlock - 1) / kBlock));
   hipLaunchKernelGGL(k_polar_order, dim3(grid), dim3(kBlock), 0, s, theta, n, sums);
   return hipGetLastError();
 }
