@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--served-seconds", type=float, default=15.0)
     ap.add_argument("--variant-steps", type=int, default=100)
+    ap.add_argument("--clustered-steps", type=int, default=100)
+    ap.add_argument("--no-clustered", action="store_true")
     ap.add_argument("--no-metric", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -322,6 +324,46 @@ def bench_variants(args, torch, nm, workloads):
     o = sum(order_ms) / len(order_ms)
     out["polar_order_kernel_ms"] = o
     out["polar_order_roofline_frac"] = 4 * n / (o * 1e-3) / 1e9 / HBM_PEAK_GBS
+    return out
+
+
+def bench_clustered(args, torch, nm, workloads):
+    """N = 2^22 from 256 Gaussian clusters (sigma 0.01 L), k in {6, 12, 20}:
+    args.clustered_steps full steps each (binning + fused k-NN/align), grid
+    picked by nm_tune_grid on the initial state."""
+    n, box = 1 << 22, workloads.BOX
+    dev = torch.device("cuda:0")
+    x, y, th = workloads.clustered(n)
+    out = {"n": n, "steps": args.clustered_steps}
+    for k in (6, 12, 20):
+        p = nm.make_params(box, v0=64, eta=0.2, include_self=1, seed=workloads.NOISE_SEED)
+        X, Y, T = (torch.as_tensor(a).to(dev) for a in (x, y, th))
+        cws = sorted({nm.suggest_cell_w(n, box, pc) for pc in (0.125, 0.5, 2.0)})
+        ws, tuned = nm.tune_grid(n, box, X, Y, T, k, p, cell_ws=cws, blocks=(0, 4), reps=3, device=dev)
+        log(f"[bench] clustered k={k} tuned=" + str({f"{w}/{b}": round(v, 4) for (w, b), v in tuned.items()}))
+        s = {"x": X, "y": Y, "t": T, "xb": torch.empty_like(X), "yb": torch.empty_like(Y),
+             "tb": torch.empty_like(T)}
+        nbr = torch.empty((n, k), dtype=torch.int32, device=dev)
+        steps = args.clustered_steps
+        for warm in (True, False):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(2 if warm else steps):
+                nm.bin_step(ws, s["x"], s["y"], s["t"], p, i)
+                nm.knn_align(ws, k, p, s["t"], nbr, s["xb"], s["yb"], s["tb"])
+                s["x"], s["xb"] = s["xb"], s["x"]
+                s["y"], s["yb"] = s["yb"], s["y"]
+                s["t"], s["tb"] = s["tb"], s["t"]
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        if nm.check(ws) != 0:
+            raise RuntimeError(f"device error in the clustered run, k={k}")
+        ms = (t1 - t0) * 1e3 / steps
+        out[f"k{k}"] = {"ms_per_step": ms, "particle_steps_per_s": n / (ms * 1e-3),
+                        "cell_w": ws.grid.cell_w, "block": ws.grid.block,
+                        "roofline_frac": (24 + 4 * k) * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"[bench] clustered N=2^22 k={k}: {ms:.4f} ms/step (w={ws.grid.cell_w}, block={ws.grid.block})")
+        del ws
     return out
 
 
@@ -599,6 +641,8 @@ def main():
         out["metric_list"] = bench_metric(args, torch, nm, workloads)
     if not args.no_variants:
         out["variants"] = bench_variants(args, torch, nm, workloads)
+    if not args.no_clustered:
+        out["clustered_4m"] = bench_clustered(args, torch, nm, workloads)
     if not args.no_batched:
         out["batched"] = bench_batched(args, torch, nm, workloads)
     if not args.no_served:
