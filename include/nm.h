@@ -167,6 +167,23 @@ int nm_align_step(const int32_t* x, const int32_t* y, const float* theta, int32_
                   const nm_params* p, uint64_t step, int32_t* x_out, int32_t* y_out,
                   float* theta_out, void* ws_err, void* stream);
 
+/* Field-of-view topological lists (the topological rule of Sec. III
+ * restricted to a cone around each particle's heading): for every particle
+ * the k nearest, by (d^2, index), among the particles it sees.  The heading
+ * vector is h = (rint(4096 cos theta), rint(4096 sin theta)) in fp64 from
+ * the fp32 heading, and the cone's half angle alpha is given by
+ * cos alpha = cos_q / 4096 (-4096 <= cos_q <= 4096; -4096 sees everything,
+ * 0 the half plane ahead).  With d the minimum-image displacement to j, j is
+ * seen when d = 0 or 4096 (d . h) >= cos_q |d| |h|, decided exactly.
+ *   ws     built by nm_build_cells or nm_bin_step for these positions
+ *   theta  device fp32[n], headings in the caller's particle order
+ *   nbr    device int32[n * k], row-major in the caller's order
+ *   k      1 <= k <= min(NM_MAX_K, n - 1)
+ * A particle that sees fewer than k others makes nm_check() report
+ * NM_E_RANGE (its row is then unspecified). */
+int nm_knn_fov(const nm_grid* g, const void* ws, int32_t k, const float* theta, int32_t cos_q,
+               int32_t* nbr, void* stream);
+
 /* Polar order parameter of the headings (Sec. III: the ordered, flocking
  * phase is the one whose headings agree): sums[0] = sum_i cos theta_i,
  * sums[1] = sum_i sin theta_i, in fp64, into the caller's DEVICE double[2];

@@ -73,6 +73,11 @@ def _load():
                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint64,
                                    _vp, ctypes.c_int32, _i32p, _i32p, _f32p, ctypes.c_uint32]
     lib.orc_align_step.restype = ctypes.c_int
+    lib.orc_knn_fov.argtypes = [_i32p, _i32p, _f32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_int32, _vp, ctypes.c_int32, _i32p]
+    lib.orc_knn_fov.restype = ctypes.c_int
+    lib.orc_fov_visible.argtypes = [ctypes.c_int64] * 4 + [ctypes.c_int32]
+    lib.orc_fov_visible.restype = ctypes.c_int
     lib.orc_polar_order.argtypes = [_f32p, ctypes.c_int32]
     lib.orc_polar_order.restype = ctypes.c_double
     lib.orc_num_threads.argtypes = []
@@ -180,6 +185,32 @@ def align_step(x, y, theta, box: int, nbr=None, offsets=None, idx=None, *, v0: i
                                 include_self, step, rp, nr, xo, yo, to, variant)
     _check(rc, "align_step")
     return xo, yo, to
+
+
+def knn_fov(x, y, theta, box: int, k: int, cos_q: int, rows=None):
+    """Field-of-view k-NN: the k nearest (by (d^2, j)) among the particles inside
+    the cone cos(alpha) = cos_q / 4096 around each heading.  Returns (nbr int32
+    [rows, k], ok); rows with fewer than k visible particles are padded with -1
+    and ok is False."""
+    x, y = _i32(x), _i32(y)
+    theta = np.ascontiguousarray(theta, dtype=np.float32)
+    n = int(x.size)
+    rp, nr, _keep = _rows_arg(rows, n)
+    nbr = np.zeros((nr, k), dtype=np.int32)
+    rc = _load().orc_knn_fov(x, y, theta, n, box, k, cos_q, rp, nr, nbr)
+    if rc == -2 and check_coords_ok(x, y, box):
+        return nbr, False
+    _check(rc, "knn_fov")
+    return nbr, True
+
+
+def check_coords_ok(x, y, box: int) -> bool:
+    return bool(((x >= 0) & (x < box) & (y >= 0) & (y < box)).all())
+
+
+def fov_visible(dx: int, dy: int, hx: int, hy: int, cos_q: int) -> bool:
+    """The cone test of knn_fov for one displacement and heading vector."""
+    return bool(_load().orc_fov_visible(dx, dy, hx, hy, cos_q))
 
 
 def polar_order(theta) -> float:

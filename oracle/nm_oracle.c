@@ -37,6 +37,8 @@
  *     the direction of a zero average); and the move with the new heading
  *     n_i(t+1) (bit 1);
  *   - the polar order parameter |sum_i n_i| / N of the headings;
+ *   - a field-of-view topological rule: the k nearest among the particles
+ *     inside a cone around the heading (see orc_knn_fov for its exact test);
  *   - noise word for particle i at step t of system s is word (i mod 4) of
  *     Philox4x32-10(counter = (i / 4, t mod 2^32, t >> 32, s),
  *                   key = (seed mod 2^32, seed >> 32)),
@@ -192,6 +194,75 @@ int orc_knn(const int32_t* x, const int32_t* y, int32_t n, int32_t box, int32_t 
     free(best);
   }
   return failed ? ORC_E_NOMEM : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Field-of-view topological rule: the k nearest among the particles inside */
+/* a cone around the particle's heading (the topological rule of Sec. III,  */
+/* restricted to what the particle faces).  The heading vector is          */
+/* h = (rint(4096 cos theta), rint(4096 sin theta)) in fp64 from the fp32   */
+/* heading; the cone's half angle alpha is given by cos alpha = c / 4096.   */
+/* With d the minimum-image displacement to j, j is visible when d = 0 or   */
+/* 4096 (d . h) >= c |d| |h|, decided exactly on squares in 128-bit         */
+/* integers.  Fewer than k visible particles is an error (ORC_E_RANGE).     */
+/* ------------------------------------------------------------------------ */
+int orc_fov_visible(int64_t dx, int64_t dy, int64_t hx, int64_t hy, int32_t c) {
+  if (dx == 0 && dy == 0) return 1;
+  int64_t p = 4096 * (dx * hx + dy * hy);                /* |p| < 2^45 */
+  unsigned __int128 p2 = (unsigned __int128)(p < 0 ? -p : p) * (unsigned __int128)(p < 0 ? -p : p);
+  unsigned __int128 q2 = (unsigned __int128)(uint64_t)(dx * dx + dy * dy) *
+                         (unsigned __int128)(uint64_t)(hx * hx + hy * hy) *
+                         (unsigned __int128)(uint64_t)((int64_t)c * c);
+  if (c >= 0) return p >= 0 && p2 >= q2;
+  return p >= 0 || p2 <= q2;
+}
+
+int orc_knn_fov(const int32_t* x, const int32_t* y, const float* theta, int32_t n, int32_t box,
+                int32_t k, int32_t c, const int32_t* rows, int32_t nrows, int32_t* nbr) {
+  if (n < 2 || box < 1 || k < 1 || k > n - 1 || c < -4096 || c > 4096) return ORC_E_INVAL;
+  if (check_coords(x, y, n, box) != ORC_OK) return ORC_E_RANGE;
+  int32_t count = rows ? nrows : n;
+  if (rows)
+    for (int32_t r = 0; r < nrows; ++r)
+      if (rows[r] < 0 || rows[r] >= n) return ORC_E_INVAL;
+  int failed = 0, short_rows = 0;
+#pragma omp parallel
+  {
+    cand_t* best = (cand_t*)malloc(sizeof(cand_t) * (size_t)k);
+    if (!best) {
+#pragma omp atomic write
+      failed = 1;
+    }
+#pragma omp for schedule(dynamic, 16)
+    for (int32_t r = 0; r < count; ++r) {
+      if (!best) continue;
+      int32_t i = rows ? rows[r] : r;
+      int64_t hx = (int64_t)rint(4096.0 * cos((double)theta[i]));
+      int64_t hy = (int64_t)rint(4096.0 * sin((double)theta[i]));
+      int32_t have = 0;
+      for (int32_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        int64_t dx = min_image((int64_t)x[j] - x[i], box), dy = min_image((int64_t)y[j] - y[i], box);
+        if (!orc_fov_visible(dx, dy, hx, hy, c)) continue;
+        cand_t cd = {dx * dx + dy * dy, j};
+        if (have == k && !cand_less(cd, best[k - 1])) continue;
+        int32_t pos = (have < k) ? have++ : k - 1;
+        while (pos > 0 && cand_less(cd, best[pos - 1])) {
+          best[pos] = best[pos - 1];
+          --pos;
+        }
+        best[pos] = cd;
+      }
+      if (have < k) {
+#pragma omp atomic write
+        short_rows = 1;
+      }
+      for (int32_t t = 0; t < k; ++t) nbr[(int64_t)r * k + t] = t < have ? best[t].j : -1;
+    }
+    free(best);
+  }
+  if (failed) return ORC_E_NOMEM;
+  return short_rows ? ORC_E_RANGE : ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */

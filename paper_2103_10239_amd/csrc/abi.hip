@@ -191,6 +191,15 @@ int nm_knn(const nm_grid* g, const void* ws, int32_t k, int32_t* nbr, int64_t* d
                               reinterpret_cast<long long*>(d2), as_stream(stream)));
 }
 
+int nm_knn_fov(const nm_grid* g, const void* ws, int32_t k, const float* theta, int32_t cos_q,
+               int32_t* nbr, void* stream) {
+  Layout lay;
+  if (!make_layout(g, &lay) || ws == nullptr || nbr == nullptr || theta == nullptr) return NM_E_INVAL;
+  if (k < 1 || k > NM_MAX_K || k > g->n - 1 || cos_q < -4096 || cos_q > 4096) return NM_E_INVAL;
+  return status_of(launch_knn_fov(dev_ws(g, lay, const_cast<void*>(ws)), theta, k, cos_q, nbr,
+                                  as_stream(stream)));
+}
+
 int nm_metric_list(const nm_grid* g, void* ws, int64_t rc2, int32_t* offsets, int32_t* idx,
                    int64_t cap, int64_t* nnz_host, void* stream) {
   Layout lay;

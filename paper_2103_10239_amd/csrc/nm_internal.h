@@ -589,6 +589,7 @@ int batch_grid(const void* kernel, int items);
 hipError_t launch_batch_bin(const BatchRef& b, int stage, hipStream_t s);
 hipError_t launch_batch_knn(const BatchRef& b, int k, hipStream_t s);
 hipError_t launch_batch_advance(const BatchRef& b, hipStream_t s);
+hipError_t launch_knn_fov(const DevWs& w, const float* theta, int k, int c, int32_t* nbr, hipStream_t s);
 hipError_t launch_polar_order(const float* theta, int32_t n, double* sums, hipStream_t s);
 hipError_t launch_align(const int32_t* x, const int32_t* y, const float* theta, int32_t n,
                         const int32_t* nbr, const int32_t* offsets, int32_t k, long long nnz_cap,

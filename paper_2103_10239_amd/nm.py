@@ -95,6 +95,7 @@ def lib():
     L.nm_knn_align.argtypes = [gp, _vp, _c_i32, pp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.nm_check.argtypes = [_vp, _vp]
     L.nm_polar_order.argtypes = [_vp, _c_i32, _vp, _vp]
+    L.nm_knn_fov.argtypes = [gp, _vp, _c_i32, _vp, _c_i32, _vp, _vp]
     L.nm_tune_grid.argtypes = [gp, _c_i32, _vp, _vp, _vp, _c_i32, pp, _c_u64, _vp, ctypes.c_size_t,
                                _vp, _vp, _vp, _vp, _c_i32, ctypes.POINTER(_c_i32),
                                ctypes.POINTER(ctypes.c_float), _vp]
@@ -161,6 +162,18 @@ def make_params(box: int, v0: int = 64, eta: float = 0.2, include_self: int = 1,
                 sys_id: int = 0, variant: int = 0) -> Params:
     """variant: 0 (Eq. (2) and Eq. (1)), or NM_NOISE_SCALAR and/or NM_MOVE_NEW_HEADING."""
     return Params(box, v0, eta, include_self, seed, sys_id, variant)
+
+
+def knn_fov(ws: Workspace, k: int, theta: torch.Tensor, cos_q: int, nbr: torch.Tensor | None = None):
+    """Field-of-view k-NN lists [n, k] (cone cos(alpha) = cos_q / 4096 around each
+    heading) from the cells built in ws.  A particle that sees fewer than k
+    others is reported by check() as NM_E_RANGE."""
+    n = ws.n
+    if nbr is None:
+        nbr = torch.empty((n, k), dtype=torch.int32, device=ws.device)
+    _ok(lib().nm_knn_fov(ctypes.byref(ws.grid), ws.ptr, k, _dev(theta, torch.float32, n, "theta"), cos_q,
+                         _dev(nbr, torch.int32, n * k, "nbr"), _stream(ws.device)), "knn_fov")
+    return nbr
 
 
 def polar_order(theta: torch.Tensor, sums: torch.Tensor | None = None) -> float:

@@ -619,3 +619,50 @@ def test_knn_fast_path_query_last_in_home_row():
         rn, rd = oracle.knn(x, y, L, 1)
         assert np.array_equal(nbr, rn) and np.array_equal(d2, rd)
         assert nbr[0, 0] == 1
+
+
+@pytest.mark.parametrize("kind,n,w", [("uniform", 4097, 2048), ("clustered", 8191, 1024), ("squeezed", 3000, 2048)])
+@pytest.mark.parametrize("cos_q", [-4096, -2048, 0, 2048, 3500])
+def test_knn_fov_matches_oracle(kind, n, w, cos_q):
+    x, y, th = _gen(kind, n)
+    ws = nm.Workspace(n, L, w)
+    nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+    T = _dev(th, torch.float32)
+    for k in (1, 7):
+        ref, ok = oracle.knn_fov(x, y, th, L, k, cos_q)
+        got = nm.knn_fov(ws, k, T, cos_q)
+        st = nm.check(ws)
+        if ok:
+            assert st == 0
+            assert np.array_equal(got.cpu().numpy(), ref)
+        else:  # a particle sees fewer than k others
+            assert st == nm.NM_E_RANGE
+            rows = (ref >= 0).all(axis=1)
+            assert np.array_equal(got.cpu().numpy()[rows], ref[rows])
+
+
+def test_knn_fov_full_size_sampled():
+    n, k = 1 << 20, 7
+    x, y, th = workloads.uniform(n)
+    ws = nm.Workspace(n, L, 2048)
+    nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+    got = nm.knn_fov(ws, k, _dev(th, torch.float32), 0)
+    assert nm.check(ws) == 0
+    rows = _sample_rows(n, 500, 17)
+    ref, ok = oracle.knn_fov(x, y, th, L, k, 0, rows=rows)
+    assert ok
+    assert np.array_equal(got[torch.as_tensor(rows).long().cuda()].cpu().numpy(), ref)
+
+
+def test_knn_fov_after_fused_binning():
+    # nm_bin_step builds the same cells (with the noise beside them)
+    n, k = 20013, 7
+    x, y, th = workloads.clustered(n)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=3)
+    ws = nm.Workspace(n, L, 2048)
+    X, Y, T = _dev(x, torch.int32), _dev(y, torch.int32), _dev(th, torch.float32)
+    nm.bin_step(ws, X, Y, T, p, 0)
+    got = nm.knn_fov(ws, k, T, 1000)
+    ref, ok = oracle.knn_fov(x, y, th, L, k, 1000)
+    assert ok and nm.check(ws) == 0
+    assert np.array_equal(got.cpu().numpy(), ref)

@@ -511,3 +511,97 @@ def test_polar_order_closed_forms():
     rot = _wrap(th.astype(np.float64) + 1.0).astype(np.float32)
     assert abs(oracle.polar_order(th) - oracle.polar_order(rot)) < 1e-6
     assert oracle.polar_order(th) < 5 / math.sqrt(5000)  # disordered: O(1/sqrt N)
+
+
+# --------------------------------------------------------------------------
+# Field-of-view topological rule: the k nearest inside a cone around the
+# heading (the topological rule of Sec. III restricted to what is seen).
+# --------------------------------------------------------------------------
+def _heading_vec(th):
+    th = np.asarray(th, np.float32).astype(np.float64)
+    return np.rint(4096.0 * np.cos(th)).astype(np.int64), np.rint(4096.0 * np.sin(th)).astype(np.int64)
+
+
+def _disp(x, y, i, j):
+    dx = ((np.int64(x[j]) - np.int64(x[i]) + L // 2) % L) - L // 2
+    dy = ((np.int64(y[j]) - np.int64(y[i]) + L // 2) % L) - L // 2
+    return dx, dy
+
+
+@pytest.mark.parametrize("kind", ["uniform", "clustered", "squeezed"])
+def test_fov_full_cone_is_the_topological_rule(kind):
+    n = 700
+    if kind == "clustered":
+        x, y, th = workloads.clustered(n, n_clusters=8, seed=3)
+    else:
+        x, y, th = workloads.uniform(n, seed_pos=4)
+        if kind == "squeezed":  # duplicates and distance ties
+            x, y = (x % 5) * 1000, (y % 3) * 1000
+    for k in (1, 7):
+        got, ok = oracle.knn_fov(x, y, th, L, k, -4096)
+        ref, _ = oracle.knn(x, y, L, k, with_d2=False)
+        assert ok and np.array_equal(got, ref)
+
+
+def test_fov_worked_example():
+    # particle 0 at the origin heading along +x; others ahead at 100 and 300,
+    # behind at 50, and off to the side at (60, 80) (53.13 degrees from +x)
+    x = np.array([0, 100, L - 50, 300, 60], np.int32)
+    y = np.array([0, 0, 0, 0, 80], np.int32)
+    th = np.zeros(5, np.float32)
+    row = np.array([0], np.int32)
+    # (60, 80) and (100, 0) are both at d^2 = 10000: the smaller index comes first
+    assert oracle.knn_fov(x, y, th, L, 2, 0, rows=row)[0].tolist() == [[1, 4]]       # half plane
+    assert oracle.knn_fov(x, y, th, L, 2, 2048, rows=row)[0].tolist() == [[1, 4]]    # 60 degrees
+    # cos(53.13 deg) = 0.6 = 2457.6 / 4096: the cone boundary passes between c = 2457 and 2458
+    assert oracle.knn_fov(x, y, th, L, 2, 2457, rows=row)[0].tolist() == [[1, 4]]
+    assert oracle.knn_fov(x, y, th, L, 2, 2458, rows=row)[0].tolist() == [[1, 3]]
+    assert oracle.knn_fov(x, y, th, L, 2, -4096, rows=row)[0].tolist() == [[2, 1]]   # everything
+    nb, ok = oracle.knn_fov(x, y, th, L, 3, 3000, rows=row)  # 42.9 degrees: only 1 and 3 are seen
+    assert not ok and nb.tolist() == [[1, 3, -1]]
+
+
+def test_fov_half_plane_invariants():
+    n, k = 1500, 6
+    x, y, th = workloads.uniform(n, seed_pos=8)
+    nbr, ok = oracle.knn_fov(x, y, th, L, k, 0)
+    assert ok
+    hx, hy = _heading_vec(th)
+    for i in range(0, n, 7):
+        dx, dy = _disp(x, y, i, np.arange(n))
+        seen = (dx * hx[i] + dy * hy[i] >= 0)
+        seen[i] = False
+        key = (dx * dx + dy * dy) * n + np.arange(n)
+        assert seen[nbr[i]].all()
+        ks = key[nbr[i]]
+        assert (np.diff(ks) > 0).all()
+        others = np.setdiff1d(np.flatnonzero(seen), nbr[i])
+        assert (key[others] > ks[-1]).all()
+
+
+def test_fov_cone_test_matches_the_angle():
+    rng = np.random.default_rng(7)
+    for _ in range(4000):
+        dx, dy = (int(v) for v in rng.integers(-(1 << 19), 1 << 19, 2))
+        th = np.float32(rng.uniform(-np.pi, np.pi))
+        hx, hy = (int(v[0]) for v in _heading_vec([th]))
+        c = int(rng.integers(-4096, 4097))
+        ang = math.atan2(dx * hy - dy * hx, dx * hx + dy * hy)  # signed angle from h to d
+        alpha = math.acos(c / 4096.0)
+        if abs(abs(ang) - alpha) < 1e-9 or (dx == 0 and dy == 0):
+            continue
+        assert oracle.fov_visible(dx, dy, hx, hy, c) == (abs(ang) <= alpha)
+    assert oracle.fov_visible(0, 0, 4096, 0, 4096)  # coincident particles are always seen
+
+
+def test_fov_narrower_cone_sees_farther():
+    n, k = 1200, 5
+    x, y, th = workloads.uniform(n, seed_pos=9)
+    kth = []
+    for c in (-4096, -2048, 0, 2048):
+        nb, ok = oracle.knn_fov(x, y, th, L, k, c)
+        assert ok
+        dx, dy = _disp(x, y, np.arange(n), nb[:, -1])
+        kth.append(dx * dx + dy * dy)
+    for a, b in zip(kth, kth[1:]):
+        assert (b >= a).all()
