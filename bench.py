@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--variant-steps", type=int, default=100)
     ap.add_argument("--clustered-steps", type=int, default=100)
     ap.add_argument("--no-clustered", action="store_true")
+    ap.add_argument("--no-fov", action="store_true")
     ap.add_argument("--no-metric", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -367,6 +368,41 @@ def bench_clustered(args, torch, nm, workloads):
     return out
 
 
+def bench_fov(args, torch, nm, workloads):
+    """Field-of-view k-NN lists at N = 2^20 uniform, k = 7, on the cells of a
+    w = 2048 grid: kernel time per cone (HIP events), beside the plain k-NN
+    list kernel on the same cells."""
+    n, k, box = args.n, args.k, workloads.BOX
+    dev = torch.device("cuda:0")
+    x, y, th = workloads.uniform(n)
+    X, Y, T = (torch.as_tensor(a).to(dev) for a in (x, y, th))
+    ws = nm.Workspace(n, box, 2048, dev)
+    nm.build_cells(ws, X, Y)
+    nbr = torch.empty((n, k), dtype=torch.int32, device=dev)
+    out = {"n": n, "k": k, "cell_w": 2048}
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out["plain_knn_ms"] = timed(lambda: nm.knn(ws, k, nbr))
+    for name, c in (("all_-4096", -4096), ("half_plane_0", 0), ("60deg_2048", 2048), ("30deg_3547", 3547)):
+        ms = timed(lambda: nm.knn_fov(ws, k, T, c, nbr))
+        out[name] = {"cos_q": c, "ms": ms, "queries_per_s": n / (ms * 1e-3),
+                     "roofline_frac": (8 + 4 + 4 * k) * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"[bench] field-of-view k-NN cos_q={c}: {ms:.4f} ms")
+    if nm.check(ws) != 0:
+        raise RuntimeError("device error in the field-of-view lists")
+    return out
+
+
 def bench_batched(args, torch, nm, workloads):
     import numpy as np
 
@@ -643,6 +679,8 @@ def main():
         out["variants"] = bench_variants(args, torch, nm, workloads)
     if not args.no_clustered:
         out["clustered_4m"] = bench_clustered(args, torch, nm, workloads)
+    if not args.no_fov:
+        out["field_of_view"] = bench_fov(args, torch, nm, workloads)
     if not args.no_batched:
         out["batched"] = bench_batched(args, torch, nm, workloads)
     if not args.no_served:
