@@ -103,6 +103,43 @@ __device__ __forceinline__ void sort_exact(const DevWs& w, int qx, int qy, int k
   }
 }
 
+// Exact squared distance from a staged query (packed position pq, or x and
+// y) to staged particle i: the 16-bit differences are exact inside a block.
+template <bool kWide>
+__device__ __forceinline__ long long staged_d2(const int* lpos, int i, int pq, int pqy) {
+  if (kWide) {
+    const int2 c = reinterpret_cast<const int2*>(lpos)[i];
+    const long long dx = c.x - pq, dy = c.y - pqy;
+    return dx * dx + dy * dy;
+  }
+  return rel_d2(lpos[i], pq);
+}
+
+// sort_exact for staged neighbours (LDS indices), from the staged positions
+// and particle indices.
+template <int KMAX, bool kWide>
+__device__ __forceinline__ void sort_exact_lds(const int* lpos, const int* lidx, int pq, int pqy, int k,
+                                               int (&lds)[KMAX]) {
+  unsigned long long kk[KMAX];
+#pragma unroll
+  for (int t = 0; t < KMAX; ++t)
+    kk[t] = t >= KMAX - k ? pack_key(staged_d2<kWide>(lpos, lds[t], pq, pqy), lidx[lds[t]]) : 0ull;
+  // the unused prefix holds 0, below every real key, so it stays in front
+#pragma unroll
+  for (int i = 1; i < KMAX; ++i) {
+#pragma unroll
+    for (int j = i; j > 0; --j) {
+      const bool swap = kk[j] < kk[j - 1];
+      const unsigned long long a = kk[j - 1], c = kk[j];
+      const int sa = lds[j - 1], sc = lds[j];
+      kk[j - 1] = swap ? c : a;
+      kk[j] = swap ? a : c;
+      lds[j - 1] = swap ? sc : sa;
+      lds[j] = swap ? sa : sc;
+    }
+  }
+}
+
 // Block side for a query: its edge should sit `reach` mean k-th-neighbour
 // radii away, r_k^2 = k / (pi rho), with the density rho estimated from the
 // occupancy of the (up to) 3 x 3 cells around the home cell.
@@ -248,8 +285,6 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
 // search.
 // ---------------------------------------------------------------------------
 constexpr int kDeferCap = 128;    // uncertified queries listed in LDS per strip
-constexpr int kSortCap = 1024;    // queries of a strip ordered by work (more: strip order)
-constexpr int kBuckets = 64;      // candidate-count buckets of that order
 constexpr double kReachX = 1.25;  // strip half width, in mean k-th-neighbour radii
 
 
@@ -292,12 +327,13 @@ __device__ __forceinline__ StripBlock strip_block(int rx, int oy, int cy, int Bq
 // Certified search of one staged query over LDS.  self: the query's LDS
 // index; (pq, pqy): its relative position (narrow: packed pair in pq);
 // (rx, oy): its x offset from the halo corner and y offset in its cell; cy:
-// its halo row.  True with `slot` filled when the k nearest are certified.
+// its halo row.  True with `lds` filled (LDS indices of the k nearest, in
+// order) when they are certified.
 template <int KMAX, bool kWide>
 __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, const int* rbase,
-                                             const int* lpos, const int* lslot, int W, int self,
-                                             int pq, int pqy, int rx, int oy, int cy, int qx,
-                                             int qy, int k, int Bq, int (&slot)[KMAX]) {
+                                             const int* lpos, const int* lidx, int W, int self,
+                                             int pq, int pqy, int rx, int oy, int cy, int k, int Bq,
+                                             int (&lds)[KMAX]) {
   constexpr int KT = KMAX + 1;
   const int2* lpos2 = reinterpret_cast<const int2*>(lpos);
   if (Bq > tc.bmax) return false;
@@ -352,8 +388,8 @@ __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, 
       if (t >= KT - (k + 1)) tied = tied || (key32_d(key[t]) == key32_d(key[t + 1]));
 #pragma unroll
     for (int t = 0; t < KMAX; ++t)
-      if (t >= KMAX - k) slot[t] = lslot[key[t] & 0x1FFFu];
-    if (tied) sort_exact<KMAX>(w, qx, qy, k, slot);
+      if (t >= KMAX - k) lds[t] = static_cast<int>(key[t] & 0x1FFFu);
+    if (tied) sort_exact_lds<KMAX, kWide>(lpos, lidx, pq, pqy, k, lds);
     return true;
   }
   return false;
@@ -484,7 +520,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   // packed 16-bit pairs, or int32 pairs (wide); padded so that a round of
   // kUnroll reads past a block's last candidate stays inside the buffer
   __shared__ int2 lpos_store[kStripPts / 2 + kUnroll];
-  __shared__ int lslot[kStripPts];
+  __shared__ int lidx[kStripPts];          // particle index of each staged particle
   __shared__ int s_rbase[kStripRows + 1];  // LDS offset of each halo row
   __shared__ int s_ga0[kStripRows];        // first slot of the row's first piece
   __shared__ int s_n0[kStripRows];         // particles in the row's first piece
@@ -494,13 +530,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   __shared__ int s_wsum[kBlock / 64];
   __shared__ int s_defer;
   __shared__ int s_dq[kDeferCap];  // slots of the strip's uncertified queries
-  // Work-sorted query order: per query (bucket of its candidate count, block
-  // height), then the permutation (query, block height), heaviest first.
-  __shared__ uint16_t s_key[kSortCap];
-  __shared__ uint32_t s_perm[kSortCap];
   __shared__ uint8_t s_rowid[kStripPts];   // halo row of each staged particle
-  __shared__ int s_hist[kBuckets];
-  __shared__ int s_nsorted;
   int* lpos = reinterpret_cast<int*>(lpos_store);
   if (!ws_ready(w)) {
     if (tile == 0 && threadIdx.x == 0) set_err(w.hdr, NM_E_INVAL);
@@ -518,9 +548,9 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
 
   int npts, nq;
   const StripGeo geo{tb.x0, tb.y0, tb.ty, tw, hx, hy, wide};
-  const StripLds lds{lpos_store, lslot, s_rbase, s_ga0, s_n0, s_ga1, s_qoff, s_tself, s_wsum, s_rowid};
+  const StripLds lds{lpos_store, lidx, s_rbase, s_ga0, s_n0, s_ga1, s_qoff, s_tself, s_wsum, s_rowid};
   if (threadIdx.x == 0) s_defer = 0;
-  const bool staged = strip_stage<false>(w, geo, lds, total, npts, nq);
+  const bool staged = strip_stage<true>(w, geo, lds, total, npts, nq);
   if (nq == 0) return;
 
   auto defer = [&](int slot_s) {
@@ -537,112 +567,85 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
       if (r + step < tb.ty && s_qoff[r + step] <= qi) r += step;
     return r;
   };
-  // x offset from the halo corner and y offset inside its cell of the staged
-  // point with LDS index i (narrow y is kept modulo 2^16, a multiple of w).
-  auto rel_pos = [&](int i, int& rx, int& oy) {
+  // One staged query (LDS index self, halo row cy): the certified search over
+  // LDS, then its outputs with the neighbours' indices from LDS and their
+  // unit vectors gathered by slot; otherwise it is deferred to the exact search.
+  auto staged_query = [&](int self, int cy) {
+    int rx, oy, pq, pqy;
     if (wide) {
-      const int2 p2 = lpos_store[i];
+      const int2 p2 = lpos_store[self];
+      pq = p2.x;
+      pqy = p2.y;
       rx = p2.x;
       oy = p2.y & ((1 << lw) - 1);
     } else {
-      const int p = lpos[i];
-      rx = p & 0xFFFF;
-      oy = (p >> 16) & ((1 << lw) - 1);
+      pq = lpos[self];
+      pqy = 0;
+      rx = pq & 0xFFFF;
+      oy = (pq >> 16) & ((1 << lw) - 1);
     }
-  };
-  auto search = [&](int self, int cy, int Bq, int& s_out, int (&slot)[KMAX]) {
-    int rx, oy;
-    rel_pos(self, rx, oy);
-    s_out = lslot[self];
-    const int qx = rx + ox0, qy = ((cy << lw) | oy) + oy0;  // strip-image coordinates
-    if (Bq < 0) Bq = strip_block_rows(f, s_rbase, W, cy, k);
-    if (wide) {
-      const int2 p2 = lpos_store[self];
-      return strip_search<KMAX, true>(w, tc, s_rbase, lpos, lslot, W, self, p2.x, p2.y, rx, oy, cy,
-                                      qx, qy, k, Bq, slot);
+    const int Bq = strip_block_rows(f, s_rbase, W, cy, k);
+    int nb[KMAX];
+    const bool ok = wide ? strip_search<KMAX, true>(w, tc, s_rbase, lpos, lidx, W, self, pq, pqy, rx, oy,
+                                                    cy, k, Bq, nb)
+                         : strip_search<KMAX, false>(w, tc, s_rbase, lpos, lidx, W, self, pq, pqy, rx, oy,
+                                                     cy, k, Bq, nb);
+    const int s = strip_slot(lds, self);
+    if (!ok) {
+      defer(s);
+      return;
     }
-    return strip_search<KMAX, false>(w, tc, s_rbase, lpos, lslot, W, self, lpos[self], 0, rx, oy,
-                                     cy, qx, qy, k, Bq, slot);
+    const int qi = lidx[self];
+    int32_t* row = nbr + static_cast<int64_t>(qi) * k;
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int t = 0; t < KMAX; ++t) {
+      if (t >= KMAX - k) {
+        const int i = nb[t];
+        row[t - (KMAX - k)] = lidx[i];
+        if (!kAlign && d2out)
+          d2out[static_cast<int64_t>(qi) * k + t - (KMAX - k)] =
+              wide ? staged_d2<true>(lpos, i, pq, pqy) : staged_d2<false>(lpos, i, pq, pqy);
+        if (kAlign) {
+          const double2 u = w.cs[2 * strip_slot(lds, i)];
+          sx += u.x;
+          sy += u.y;
+        }
+      }
+    }
+    if (kAlign) {
+      // Eq. (2) and Eq. (1) as in finish_query, the position from the staged copy
+      const double2 own = w.cs[2 * s];
+      const double2 xi = w.cs[2 * s + 1];
+      if (a.include_self) {
+        sx += own.x;
+        sy += own.y;
+      }
+      const double m = static_cast<double>(k + (a.include_self ? 1 : 0));
+      const double phi = (a.variant & NM_NOISE_SCALAR) ? noise_angle(static_cast<uint32_t>(w.sorted[s].w)) : 0.0;
+      const float th = heading_update(sx / m, sy / m, xi.x, xi.y, phi, a.eta, a.theta + qi, a.variant);
+      int ddx, ddy;
+      move_step(a.v0, own.x, own.y, th, a.variant, ddx, ddy);
+      const int qx = rx + ox0, qy = ((cy << lw) | oy) + oy0;  // strip-image coordinates
+      const int mask = w.box - 1;
+      a.x_out[qi] = (qx + ddx) & mask;
+      a.y_out[qi] = (qy + ddy) & mask;
+      a.theta_out[qi] = th;
+    }
   };
 
-  if (staged && nq <= kSortCap) {
-    // Pre-pass: block height and candidate count of every query, from LDS
-    // only; a counting sort by candidate count then gives each wavefront
-    // queries of similar work (a wavefront runs as long as its longest query).
-    if (threadIdx.x < kBuckets) s_hist[threadIdx.x] = 0;
-    __syncthreads();
-    for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
-      const int r = row_of(qi);
-      const int self = s_tself[r] + (qi - s_qoff[r]);
-      int rx, oy;
-      rel_pos(self, rx, oy);
-      const int cy = r + hy;
-      const int Bq = strip_block_rows(f, s_rbase, W, cy, k);
-      int key = 0xFFFF;
-      if (Bq <= tc.bmax) {
-        const StripBlock b = strip_block(rx, oy, cy, Bq, W, lw);
-        const int nc = s_rbase[b.r0 + Bq] - s_rbase[b.r0];
-        const int bk = nc < 128 ? (nc >> 2) : 32 + min((nc - 128) >> 5, kBuckets - 33);
-        atomicAdd(&s_hist[bk], 1);
-        key = (bk << 5) | Bq;
-      } else {
-        defer(lslot[self]);
-      }
-      s_key[qi] = static_cast<uint16_t>(key);
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {  // exclusive offsets, heaviest bucket first
-      const int bk = kBuckets - 1 - lane;
-      const int c = s_hist[bk];
-      int incl = c;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += t;
-      }
-      s_hist[bk] = incl - c;
-      if (lane == 63) s_nsorted = incl;
-    }
-    __syncthreads();
-    for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
-      const int key = s_key[qi];
-      if (key == 0xFFFF) continue;
-      const int pos = atomicAdd(&s_hist[key >> 5], 1);
-      const int r = row_of(qi);
-      const int self = s_tself[r] + (qi - s_qoff[r]);
-      // (LDS index, halo row, block height)
-      s_perm[pos] = (static_cast<uint32_t>(self) << 13) | (static_cast<uint32_t>(r + hy) << 5) |
-                    static_cast<uint32_t>(key & 31);
-    }
-    __syncthreads();
-    const int ns = s_nsorted;
-    for (int j = threadIdx.x; j < ns; j += kBlock) {
-      const uint32_t e = s_perm[j];
-      int s, slot[KMAX];
-      if (search(static_cast<int>(e >> 13), static_cast<int>((e >> 5) & 255u), static_cast<int>(e & 31u), s, slot))
-        finish_query<KMAX, kAlign>(w, s, w.sorted[s], slot, k, nbr, d2out, a);
+  for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
+    const int r = row_of(qi);
+    if (staged) {
+      staged_query(s_tself[r] + (qi - s_qoff[r]), r + hy);
+    } else {
+      int slot[KMAX];
+      const int s = w.start[static_cast<int64_t>(tb.y0 + r) * G + tb.x0] + (qi - s_qoff[r]);
+      const int4 q = w.sorted[s];
+      if (knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot))
+        finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
       else
         defer(s);
-    }
-  } else {
-    for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
-      int slot[KMAX];
-      if (staged) {
-        int s;
-        const int r = row_of(qi);
-        if (search(s_tself[r] + (qi - s_qoff[r]), r + hy, -1, s, slot))
-          finish_query<KMAX, kAlign>(w, s, w.sorted[s], slot, k, nbr, d2out, a);
-        else
-          defer(s);
-      } else {
-        const int r = row_of(qi);
-        const int s = w.start[static_cast<int64_t>(tb.y0 + r) * G + tb.x0] + (qi - s_qoff[r]);
-        const int4 q = w.sorted[s];
-        if (knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot))
-          finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
-        else
-          defer(s);
-      }
     }
   }
   __syncthreads();

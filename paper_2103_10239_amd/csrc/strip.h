@@ -76,6 +76,14 @@ struct StripLds {
   uint8_t* rowid;    // [kStripPts] halo row of each staged particle
 };
 
+// Cell-ordered slot of staged particle i (the inverse of the staging copy).
+__device__ __forceinline__ int strip_slot(const StripLds& s, int i) {
+  const int r = s.rowid[i];
+  const int inrow = i - s.rbase[r];
+  const int n0 = s.n0[r];
+  return inrow >= n0 ? s.ga1[r] + (inrow - n0) : s.ga0[r] + inrow;
+}
+
 // Row tables and (when the halo fits: hx > 0 and npts <= cap) the staged
 // particles of strip g.  Every thread of the workgroup must call it; it ends
 // with a barrier.  Returns whether the particles were staged; npts and nq
