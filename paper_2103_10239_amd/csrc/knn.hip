@@ -531,6 +531,8 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   __shared__ int s_defer;
   __shared__ int s_dq[kDeferCap];  // slots of the strip's uncertified queries
   __shared__ uint8_t s_rowid[kStripPts];   // halo row of each staged particle
+  __shared__ int s_sub[kStripRows + 1];    // sub-strip rows of a strip whose halo overflows LDS
+  __shared__ int s_nsub;
   int* lpos = reinterpret_cast<int*>(lpos_store);
   if (!ws_ready(w)) {
     if (tile == 0 && threadIdx.x == 0) set_err(w.hdr, NM_E_INVAL);
@@ -543,14 +545,20 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   const int W = tw + 2 * hx;
   const int uL = tb.x0 - hx;
   const int lane = threadIdx.x & 63;
-  const int ox0 = uL << lw, oy0 = (tb.y0 - hy) << lw;  // halo corner (strip image)
+  const int ox0 = uL << lw;  // halo corner x (strip image)
+  // the (sub-)strip being run: first row, rows, halo corner y (strip image)
+  int y0_cur = tb.y0, ty_cur = tb.ty, oy0 = (tb.y0 - hy) << lw;
   const bool wide = tc.wide != 0;
 
   int npts, nq;
   const StripGeo geo{tb.x0, tb.y0, tb.ty, tw, hx, hy, wide};
-  const StripLds lds{lpos_store, lidx, s_rbase, s_ga0, s_n0, s_ga1, s_qoff, s_tself, s_wsum, s_rowid};
+  // built at each use: an aggregate of LDS addresses shared by the lambdas
+  // below would become a constant global, which the target cannot express
+  auto strip_lds = [&]() {
+    return StripLds{lpos_store, lidx, s_rbase, s_ga0, s_n0, s_ga1, s_qoff, s_tself, s_wsum, s_rowid};
+  };
   if (threadIdx.x == 0) s_defer = 0;
-  const bool staged = strip_stage<true>(w, geo, lds, total, npts, nq);
+  const bool staged = strip_stage<true>(w, geo, strip_lds(), total, npts, nq);
   if (nq == 0) return;
 
   auto defer = [&](int slot_s) {
@@ -564,7 +572,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
     int r = 0;
 #pragma unroll
     for (int step = kRowStep; step > 0; step >>= 1)
-      if (r + step < tb.ty && s_qoff[r + step] <= qi) r += step;
+      if (r + step < ty_cur && s_qoff[r + step] <= qi) r += step;
     return r;
   };
   // One staged query (LDS index self, halo row cy): the certified search over
@@ -590,7 +598,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
                                                     cy, k, Bq, nb)
                          : strip_search<KMAX, false>(w, tc, s_rbase, lpos, lidx, W, self, pq, pqy, rx, oy,
                                                      cy, k, Bq, nb);
-    const int s = strip_slot(lds, self);
+    const int s = strip_slot(strip_lds(), self);
     if (!ok) {
       defer(s);
       return;
@@ -607,7 +615,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
           d2out[static_cast<int64_t>(qi) * k + t - (KMAX - k)] =
               wide ? staged_d2<true>(lpos, i, pq, pqy) : staged_d2<false>(lpos, i, pq, pqy);
         if (kAlign) {
-          const double2 u = w.cs[2 * strip_slot(lds, i)];
+          const double2 u = w.cs[2 * strip_slot(strip_lds(), i)];
           sx += u.x;
           sy += u.y;
         }
@@ -634,19 +642,62 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
     }
   };
 
-  for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
-    const int r = row_of(qi);
-    if (staged) {
-      staged_query(s_tself[r] + (qi - s_qoff[r]), r + hy);
-    } else {
-      int slot[KMAX];
-      const int s = w.start[static_cast<int64_t>(tb.y0 + r) * G + tb.x0] + (qi - s_qoff[r]);
-      const int4 q = w.sorted[s];
-      if (knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot))
-        finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
-      else
-        defer(s);
+  // The queries of the (sub-)strip just staged, or searched in global memory
+  // (the fast block search) when its halo could not be staged.
+  auto run = [&](bool st, int nq_cur) {
+    for (int qi = threadIdx.x; qi < nq_cur; qi += kBlock) {
+      const int r = row_of(qi);
+      if (st) {
+        staged_query(s_tself[r] + (qi - s_qoff[r]), r + hy);
+      } else {
+        int slot[KMAX];
+        const int s = w.start[static_cast<int64_t>(y0_cur + r) * G + tb.x0] + (qi - s_qoff[r]);
+        const int4 q = w.sorted[s];
+        if (knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot))
+          finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
+        else
+          defer(s);
+      }
     }
+  };
+  // A halo with more particles than LDS holds is run as sub-strips of whole
+  // rows, each as tall as fits; a row whose own halo does not fit (bit 30)
+  // is searched in global memory.  One call site of run keeps one copy of
+  // the query code.
+  const bool split = !staged && hx > 0;
+  if (split) {
+    const int cap = wide ? kStripPts / 2 : kStripPts;
+    if (threadIdx.x == 0) {
+      int ns = 0;
+      for (int r0 = 0; r0 < tb.ty;) {
+        const bool fits = s_rbase[r0 + 2 * hy + 1] - s_rbase[r0] <= cap;
+        int r1 = r0 + 1;
+        if (fits)
+          while (r1 < tb.ty && s_rbase[r1 + 2 * hy + 1] - s_rbase[r0] <= cap) ++r1;
+        s_sub[ns++] = r0 | (fits ? 0 : 1 << 30);
+        r0 = r1;
+      }
+      s_sub[ns] = tb.ty;
+      s_nsub = ns;
+    }
+    __syncthreads();
+  }
+  const int nsub = split ? s_nsub : 1;
+  for (int si = 0; si < nsub; ++si) {
+    bool st = staged;
+    int nq_cur = nq;
+    if (split) {
+      const int e = s_sub[si], r0 = e & 0xFFFF, r1 = s_sub[si + 1] & 0xFFFF;
+      const bool fits = (e >> 30) == 0;
+      __syncthreads();  // the previous sub-strip's queries are done with LDS
+      y0_cur = tb.y0 + r0;
+      ty_cur = r1 - r0;
+      oy0 = (y0_cur - hy) << lw;
+      const StripGeo g2{tb.x0, y0_cur, ty_cur, tw, fits ? hx : 0, hy, wide};
+      int np2;
+      st = strip_stage<true>(w, g2, strip_lds(), total, np2, nq_cur);
+    }
+    run(st, nq_cur);
   }
   __syncthreads();
   const int nd = s_defer;
@@ -674,8 +725,9 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   }
   if (nd > kDeferCap) {
     for (int r = 0; r < tb.ty; ++r) {
-      const int a0 = w.start[static_cast<int64_t>(tb.y0 + r) * G + tb.x0];
-      const int a1 = a0 + (s_qoff[r + 1] - s_qoff[r]);
+      const int64_t row = static_cast<int64_t>(tb.y0 + r) * G;
+      const int a0 = w.start[row + tb.x0];
+      const int a1 = max(min(w.start[row + tb.x0 + tw], total), a0);
       for (int sq = a0 + threadIdx.x; sq < a1; sq += kBlock) {
         if (w.dflag[sq]) {
           w.dflag[sq] = 0;

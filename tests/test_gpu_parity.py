@@ -621,6 +621,39 @@ def test_knn_fast_path_query_last_in_home_row():
         assert nbr[0, 0] == 1
 
 
+# Tight clusters in an otherwise sparse box: strips sized for the mean density
+# hold halos larger than the staging buffer.  Such a strip runs as sub-strips
+# of whole rows staged one after another; a row whose own halo is too large is
+# searched in global memory.  Each case reaches both kinds (counted with a host
+# model of the strip tables): (box, n, clusters, width, k, cell width).
+SPLIT_CASES = [
+    (1 << 16, 40000, 16, 0.005, 7, 256),    # narrow strips: 17 overflow, 42 sub-strips, 6 rows global
+    (1 << 16, 40000, 8, 0.003, 12, 128),    # narrow: 21 overflow, 396 sub-strips, 353 global
+    (1 << 20, 20013, 16, 0.005, 12, 2048),  # wide strips: 11 overflow, 89 sub-strips, 64 global
+    (1 << 20, 40000, 64, 0.01, 7, 2048),    # wide: 11 overflow, every row stageable
+]
+
+
+@pytest.mark.parametrize("box,n,ncl,sf,k,w", SPLIT_CASES)
+def test_knn_strips_larger_than_lds_match_oracle(box, n, ncl, sf, k, w):
+    x, y, th = workloads.clustered(n, box=box, n_clusters=ncl, sigma_frac=sf)
+    ws = nm.Workspace(n, box, w)
+    nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+    nbr, d2 = nm.knn(ws, k, with_d2=True)
+    assert nm.check(ws) == 0
+    rn, rd = oracle.knn(x, y, box, k)
+    assert np.array_equal(nbr.cpu().numpy(), rn) and np.array_equal(d2.cpu().numpy(), rd)
+    # the fused step over the same strips
+    p = nm.make_params(box, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    sysm = nm.System.create(x, y, th, k, p, cell_w=w)
+    sysm.step()
+    assert nm.check(sysm.ws) == 0
+    sn, sx, sy, st = oracle.step(x, y, th, box, k, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    assert np.array_equal(sysm.nbr.cpu().numpy(), sn)
+    assert np.array_equal(sysm.x.cpu().numpy(), sx) and np.array_equal(sysm.y.cpu().numpy(), sy)
+    assert _angle_err(sysm.theta.cpu().numpy(), st).max() <= TOL
+
+
 @pytest.mark.parametrize("kind,n,w", [("uniform", 4097, 2048), ("clustered", 8191, 1024), ("squeezed", 3000, 2048)])
 @pytest.mark.parametrize("cos_q", [-4096, -2048, 0, 2048, 3500])
 def test_knn_fov_matches_oracle(kind, n, w, cos_q):
