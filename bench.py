@@ -328,10 +328,17 @@ def bench_variants(args, torch, nm, workloads):
     return out
 
 
+def grid_label(w, b):
+    """cell width / block side, with 's' for the sub-strip kernel"""
+    return f"{w}/{b & 0xFF}{'s' if b > 0 and b & 0x100 else ''}" if b >= 0 else f"{w}/{b}"
+
+
 def bench_clustered(args, torch, nm, workloads):
     """N = 2^22 from 256 Gaussian clusters (sigma 0.01 L), k in {6, 12, 20}:
-    args.clustered_steps full steps each (binning + fused k-NN/align), grid
-    picked by nm_tune_grid on the initial state."""
+    args.clustered_steps full steps each (binning + fused k-NN/align).  The
+    grid (cell width, block side, strip kernel) is picked by nm_tune_grid on
+    the initial state, then weighed once more against its other strip kernel
+    after 10 untimed steps (the clusters contract as the flock aligns)."""
     n, box = 1 << 22, workloads.BOX
     dev = torch.device("cuda:0")
     x, y, th = workloads.clustered(n)
@@ -340,21 +347,31 @@ def bench_clustered(args, torch, nm, workloads):
         p = nm.make_params(box, v0=64, eta=0.2, include_self=1, seed=workloads.NOISE_SEED)
         X, Y, T = (torch.as_tensor(a).to(dev) for a in (x, y, th))
         cws = sorted({nm.suggest_cell_w(n, box, pc) for pc in (0.125, 0.5, 2.0)})
-        ws, tuned = nm.tune_grid(n, box, X, Y, T, k, p, cell_ws=cws, blocks=(0, 4), reps=3, device=dev)
-        log(f"[bench] clustered k={k} tuned=" + str({f"{w}/{b}": round(v, 4) for (w, b), v in tuned.items()}))
+        S = nm.NM_BLOCK_SUBSTRIPS
+        ws, tuned = nm.tune_grid(n, box, X, Y, T, k, p, cell_ws=cws, blocks=(0, 4, S, S | 4), reps=3,
+                                 device=dev)
+        log(f"[bench] clustered k={k} tuned=" + str({grid_label(w, b): round(v, 4) for (w, b), v in tuned.items()}))
         s = {"x": X, "y": Y, "t": T, "xb": torch.empty_like(X), "yb": torch.empty_like(Y),
              "tb": torch.empty_like(T)}
         nbr = torch.empty((n, k), dtype=torch.int32, device=dev)
         steps = args.clustered_steps
+        i = 0
         for warm in (True, False):
+            if not warm:
+                w, b = ws.grid.cell_w, ws.grid.block
+                _, re = nm.tune_grid(n, box, s["x"], s["y"], s["t"], k, p, step_index=i,
+                                     pairs=[(w, b), (w, b ^ S)], reps=2, device=dev, ws=ws)
+                log(f"[bench] clustered k={k} re-tuned after {i} steps: "
+                    + str({grid_label(w2, b2): round(v, 4) for (w2, b2), v in re.items()}))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for i in range(2 if warm else steps):
+            for _ in range(10 if warm else steps):
                 nm.bin_step(ws, s["x"], s["y"], s["t"], p, i)
                 nm.knn_align(ws, k, p, s["t"], nbr, s["xb"], s["yb"], s["tb"])
                 s["x"], s["xb"] = s["xb"], s["x"]
                 s["y"], s["yb"] = s["yb"], s["y"]
                 s["t"], s["tb"] = s["tb"], s["t"]
+                i += 1
             torch.cuda.synchronize()
             t1 = time.perf_counter()
         if nm.check(ws) != 0:
@@ -363,7 +380,8 @@ def bench_clustered(args, torch, nm, workloads):
         out[f"k{k}"] = {"ms_per_step": ms, "particle_steps_per_s": n / (ms * 1e-3),
                         "cell_w": ws.grid.cell_w, "block": ws.grid.block,
                         "roofline_frac": (24 + 4 * k) * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        log(f"[bench] clustered N=2^22 k={k}: {ms:.4f} ms/step (w={ws.grid.cell_w}, block={ws.grid.block})")
+        log(f"[bench] clustered N=2^22 k={k}: {ms:.4f} ms/step "
+            f"(grid {grid_label(ws.grid.cell_w, ws.grid.block)})")
         del ws
     return out
 

@@ -73,9 +73,16 @@ typedef struct nm_grid {
   int32_t box;    /* L, power of two in [2, 2^20]                                  */
   int32_t cell_w; /* w, power of two in [1, L]; (L/w)^2 <= 2^28 cells              */
   int32_t block;  /* k-NN fast-path block side in cells: 0 = chosen from n, L, w   */
-                  /* and k; 3..8 = that side; -1 = exact ring search only.  The   */
-                  /* lists are identical for every choice; only speed differs.    */
+                  /* and k; 3..15 = that side; -1 = exact ring search only.  With */
+                  /* NM_BLOCK_SUBSTRIPS or-ed into 0 or a side, a strip of cells  */
+                  /* whose halo overflows the on-chip staging buffer runs as      */
+                  /* sub-strips staged in turn instead of searching global memory */
+                  /* (faster on strongly clustered states, slower elsewhere: a    */
+                  /* separate kernel).  The lists are identical for every choice; */
+                  /* only speed differs.                                          */
 } nm_grid;
+
+#define NM_BLOCK_SUBSTRIPS 0x100
 
 /* Variants of the step (nm_params.variant), from the Vicsek-model family the
  * paper's alignment rule belongs to (Sec. III); 0 is Eq. (2) and Eq. (1) as

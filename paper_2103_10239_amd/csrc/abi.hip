@@ -38,7 +38,9 @@ bool params_ok(const nm_params* p) {
 }  // namespace
 
 bool make_layout(const nm_grid* g, Layout* out) {
-  if (g == nullptr || g->block < -1 || g->block > kMaxB || (g->block > 0 && g->block < 3)) return false;
+  if (g == nullptr) return false;
+  const int side = g->block < 0 ? g->block : (g->block & ~NM_BLOCK_SUBSTRIPS);
+  if (side < -1 || side > kMaxB || (side > 0 && side < 3)) return false;
   if (g->n < 2 || g->n > kMaxParticles) return false;
   if (!is_pow2(g->box) || g->box < 2 || g->box > (1 << 20)) return false;
   if (!is_pow2(g->cell_w) || g->cell_w > g->box) return false;

@@ -512,7 +512,16 @@ __device__ __forceinline__ StripBox strip_box(const DevWs& w, const TileCfg& tc,
 }
 
 
-template <int KMAX, bool kAlign>
+// What a strip does when its halo holds more particles than LDS.  The two
+// are compiled as separate kernels: the sub-strip loop costs the common
+// (fitting) strips some 10% when it shares their kernel, so the choice is a
+// grid parameter that the autotuner weighs like the cell width.
+enum StripMode {
+  kOverflowGlobal = 0,  // search its queries in global memory (fast block search)
+  kOverflowSplit = 1,   // run it as sub-strips of whole rows, each staged in turn
+};
+
+template <int KMAX, bool kAlign, int kMode>
 __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, const TileCfg& tc,
                                               int k, int32_t* __restrict__ nbr,
                                               long long* __restrict__ d2out, const AlignArgs& a,
@@ -531,7 +540,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   __shared__ int s_defer;
   __shared__ int s_dq[kDeferCap];  // slots of the strip's uncertified queries
   __shared__ uint8_t s_rowid[kStripPts];   // halo row of each staged particle
-  __shared__ int s_sub[kStripRows + 1];    // sub-strip rows of a strip whose halo overflows LDS
+  __shared__ int s_sub[kStripRows + 1];    // sub-strip rows (kOverflowSplit)
   __shared__ int s_nsub;
   int* lpos = reinterpret_cast<int*>(lpos_store);
   if (!ws_ready(w)) {
@@ -550,16 +559,13 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   int y0_cur = tb.y0, ty_cur = tb.ty, oy0 = (tb.y0 - hy) << lw;
   const bool wide = tc.wide != 0;
 
-  int npts, nq;
-  const StripGeo geo{tb.x0, tb.y0, tb.ty, tw, hx, hy, wide};
+  StripGeo geo{tb.x0, tb.y0, tb.ty, tw, hx, hy, wide};
   // built at each use: an aggregate of LDS addresses shared by the lambdas
   // below would become a constant global, which the target cannot express
   auto strip_lds = [&]() {
     return StripLds{lpos_store, lidx, s_rbase, s_ga0, s_n0, s_ga1, s_qoff, s_tself, s_wsum, s_rowid};
   };
   if (threadIdx.x == 0) s_defer = 0;
-  const bool staged = strip_stage<true>(w, geo, strip_lds(), total, npts, nq);
-  if (nq == 0) return;
 
   auto defer = [&](int slot_s) {
     const int pos = atomicAdd(&s_defer, 1);
@@ -644,60 +650,79 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
 
   // The queries of the (sub-)strip just staged, or searched in global memory
   // (the fast block search) when its halo could not be staged.
-  auto run = [&](bool st, int nq_cur) {
-    for (int qi = threadIdx.x; qi < nq_cur; qi += kBlock) {
-      const int r = row_of(qi);
-      if (st) {
-        staged_query(s_tself[r] + (qi - s_qoff[r]), r + hy);
-      } else {
-        int slot[KMAX];
-        const int s = w.start[static_cast<int64_t>(y0_cur + r) * G + tb.x0] + (qi - s_qoff[r]);
-        const int4 q = w.sorted[s];
-        if (knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot))
-          finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
-        else
-          defer(s);
-      }
-    }
+  auto global_query = [&](int qi, int r) {
+    int slot[KMAX];
+    const int s = w.start[static_cast<int64_t>(y0_cur + r) * G + tb.x0] + (qi - s_qoff[r]);
+    const int4 q = w.sorted[s];
+    if (knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot))
+      finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
+    else
+      defer(s);
   };
-  // A halo with more particles than LDS holds is run as sub-strips of whole
-  // rows, each as tall as fits; a row whose own halo does not fit (bit 30)
-  // is searched in global memory.  One call site of run keeps one copy of
-  // the query code.
-  const bool split = !staged && hx > 0;
-  if (split) {
-    const int cap = wide ? kStripPts / 2 : kStripPts;
-    if (threadIdx.x == 0) {
-      int ns = 0;
-      for (int r0 = 0; r0 < tb.ty;) {
-        const bool fits = s_rbase[r0 + 2 * hy + 1] - s_rbase[r0] <= cap;
-        int r1 = r0 + 1;
-        if (fits)
-          while (r1 < tb.ty && s_rbase[r1 + 2 * hy + 1] - s_rbase[r0] <= cap) ++r1;
-        s_sub[ns++] = r0 | (fits ? 0 : 1 << 30);
-        r0 = r1;
-      }
-      s_sub[ns] = tb.ty;
-      s_nsub = ns;
+  if constexpr (kMode == kOverflowGlobal) {
+    int npts, nq;
+    const bool staged = strip_stage<true>(w, geo, strip_lds(), total, npts, nq);
+    if (nq == 0) return;
+    for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
+      const int r = row_of(qi);
+      if (staged)
+        staged_query(s_tself[r] + (qi - s_qoff[r]), r + hy);
+      else
+        global_query(qi, r);
     }
-    __syncthreads();
-  }
-  const int nsub = split ? s_nsub : 1;
-  for (int si = 0; si < nsub; ++si) {
-    bool st = staged;
-    int nq_cur = nq;
-    if (split) {
-      const int e = s_sub[si], r0 = e & 0xFFFF, r1 = s_sub[si + 1] & 0xFFFF;
-      const bool fits = (e >> 30) == 0;
-      __syncthreads();  // the previous sub-strip's queries are done with LDS
+  } else {
+    // The strip is staged whole when its halo fits LDS.  Otherwise it runs
+    // as sub-strips of whole rows, each as tall as fits, staged one after
+    // another; a row whose own halo does not fit (bit 30) is searched in
+    // global memory.  One staging site keeps a single copy of that code.
+    int next = -1, nsub = 0;  // the sub-strip to stage next (-1: none planned)
+    for (;;) {
+      int np_cur, nq_cur;
+      const bool st = strip_stage<true>(w, geo, strip_lds(), total, np_cur, nq_cur);
+      nq_cur = __builtin_amdgcn_readfirstlane(nq_cur);  // block-uniform: keep it scalar
+      bool plan = false;
+      if (next < 0) {
+        if (nq_cur == 0) return;
+        plan = !st && hx > 0;
+      }
+      if (plan) {
+        const int cap = wide ? kStripPts / 2 : kStripPts;
+        if (threadIdx.x == 0) {
+          int ns = 0;
+          for (int r0 = 0; r0 < tb.ty;) {
+            const bool fits = s_rbase[r0 + 2 * hy + 1] - s_rbase[r0] <= cap;
+            int r1 = r0 + 1;
+            if (fits)
+              while (r1 < tb.ty && s_rbase[r1 + 2 * hy + 1] - s_rbase[r0] <= cap) ++r1;
+            s_sub[ns++] = r0 | (fits ? 0 : 1 << 30);
+            r0 = r1;
+          }
+          s_sub[ns] = tb.ty;
+          s_nsub = ns;
+        }
+        __syncthreads();
+        nsub = __builtin_amdgcn_readfirstlane(s_nsub);
+        next = 0;
+      } else {
+        if (st) {
+          for (int qi = threadIdx.x; qi < nq_cur; qi += kBlock) {
+            const int r = row_of(qi);
+            staged_query(s_tself[r] + (qi - s_qoff[r]), r + hy);
+          }
+        } else {
+          for (int qi = threadIdx.x; qi < nq_cur; qi += kBlock) global_query(qi, row_of(qi));
+        }
+        if (next < 0 || next >= nsub) break;
+        __syncthreads();  // this sub-strip's queries are done with LDS
+      }
+      const int e = __builtin_amdgcn_readfirstlane(s_sub[next]);
+      const int r0 = e & 0xFFFF, r1 = __builtin_amdgcn_readfirstlane(s_sub[next + 1]) & 0xFFFF;
       y0_cur = tb.y0 + r0;
       ty_cur = r1 - r0;
       oy0 = (y0_cur - hy) << lw;
-      const StripGeo g2{tb.x0, y0_cur, ty_cur, tw, fits ? hx : 0, hy, wide};
-      int np2;
-      st = strip_stage<true>(w, g2, strip_lds(), total, np2, nq_cur);
+      geo = StripGeo{tb.x0, y0_cur, ty_cur, tw, (e >> 30) == 0 ? hx : 0, hy, wide};
+      ++next;
     }
-    run(st, nq_cur);
   }
   __syncthreads();
   const int nd = s_defer;
@@ -738,11 +763,11 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   }
 }
 
-template <int KMAX, bool kAlign>
+template <int KMAX, bool kAlign, int kMode>
 __global__ __launch_bounds__(kBlock) void k_knn(DevWs w, FastCfg f, TileCfg tc, int k,
                                                 int32_t* __restrict__ nbr,
                                                 long long* __restrict__ d2out, AlignArgs a) {
-  knn_tile_body<KMAX, kAlign>(w, f, tc, k, nbr, d2out, a, xcd_tile(blockIdx.x, gridDim.x));
+  knn_tile_body<KMAX, kAlign, kMode>(w, f, tc, k, nbr, d2out, a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Batched k-NN + alignment.  Items of the tile stage are (system, tile); the
@@ -786,7 +811,7 @@ __global__ __launch_bounds__(kBlock) void k_bb_knn(BatchRef b, int k) {
     const TileCfg tc = uniform_load(&g->tc);
     const AlignArgs a = uniform_load_align(g);
     const int li = it - __builtin_amdgcn_readfirstlane(g->base[kStKnn]);
-    knn_tile_body<KMAX, true>(w, f, tc, k, uniform_ptr(g->nbr), nullptr, a, li);
+    knn_tile_body<KMAX, true, kOverflowGlobal>(w, f, tc, k, uniform_ptr(g->nbr), nullptr, a, li);
     __syncthreads();
   }
 }
@@ -852,7 +877,12 @@ hipError_t launch_t(const DevWs& w, const FastCfg& f, int k, int32_t* nbr, long 
                     const AlignArgs& a, hipStream_t s) {
   const TileCfg tc = tile_cfg_impl(w, f, k);
   const int ntiles = tc.ntx * tc.nty;
-  hipLaunchKernelGGL((k_knn<KMAX, kAlign>), dim3(ntiles), dim3(kBlock), 0, s, w, f, tc, k, nbr, d2, a);
+  if (f.split && tc.hx > 0)
+    hipLaunchKernelGGL((k_knn<KMAX, kAlign, kOverflowSplit>), dim3(ntiles), dim3(kBlock), 0, s, w, f,
+                       tc, k, nbr, d2, a);
+  else
+    hipLaunchKernelGGL((k_knn<KMAX, kAlign, kOverflowGlobal>), dim3(ntiles), dim3(kBlock), 0, s, w, f,
+                       tc, k, nbr, d2, a);
   return hipGetLastError();
 }
 
@@ -890,11 +920,14 @@ hipError_t launch_batch_knn(const BatchRef& b, int k, hipStream_t s) {
 // Fast-path limits for a grid: block sides up to the largest B whose
 // offsets keep 32-bit squared distances exact ((B / 2 + 1) w < 2^15) and whose
 // block cannot meet itself around the box (B + 2 <= G).  `block` > 0 fixes the
-// side, 0 picks it per query, < 0 disables the fast path.
+// side, 0 picks it per query, < 0 disables the fast path; NM_BLOCK_SUBSTRIPS
+// in it selects the sub-strip kernel.
 FastCfg fast_cfg(const DevWs& w, int k, int block) {
   (void)k;
-  FastCfg f{0, 0, 1.25f, 0};
+  FastCfg f{0, 0, 1.25f, 0, 0};
   if (block < 0) return f;
+  f.split = (block & NM_BLOCK_SUBSTRIPS) ? 1 : 0;
+  block &= ~NM_BLOCK_SUBSTRIPS;
   int bw = kMaxB;  // any span (64-bit distances): the block must not meet itself
   while (bw >= 3 && bw + 2 > w.G) --bw;
   if (bw < 3) return f;

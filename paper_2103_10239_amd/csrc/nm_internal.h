@@ -350,6 +350,7 @@ struct FastCfg {
   int bfix;    // fixed block side, or 0 to pick it per query from density
   float reach; // distance to the block edge, in mean k-th-neighbour radii
   int bmax_w;  // largest block side of the 64-bit-distance ("wide") tiles
+  int split;   // strips whose halo overflows LDS run as staged sub-strips
 };
 
 __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {

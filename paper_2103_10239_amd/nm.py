@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libnm.so")
 NM_OK, NM_E_INVAL, NM_E_RANGE, NM_E_CAPACITY, NM_E_NOMEM, NM_E_DEVICE = 0, -1, -2, -3, -4, -5
 NM_MAX_K = 32
 NM_NOISE_SCALAR, NM_MOVE_NEW_HEADING = 1, 2  # nm_params.variant flags
+NM_BLOCK_SUBSTRIPS = 0x100  # nm_grid.block flag: overflowing strips run as staged sub-strips
 
 _c_i32, _c_i64, _c_u32, _c_u64, _vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                        ctypes.c_uint64, ctypes.c_void_p)
@@ -33,7 +34,8 @@ class NMError(RuntimeError):
 
 class Grid(ctypes.Structure):
     """nm_grid: n particles, box side L, cell width w (powers of two), and the
-    k-NN fast-path block side (0 automatic, -1 exact ring search only)."""
+    k-NN fast-path block side (0 automatic, -1 exact ring search only), with
+    NM_BLOCK_SUBSTRIPS or-ed in to pick the sub-strip kernel."""
     _fields_ = [("n", _c_i32), ("box", _c_i32), ("cell_w", _c_i32), ("block", _c_i32)]
 
 
@@ -364,10 +366,11 @@ class System:
     step_index: int = 0
 
     @classmethod
-    def create(cls, x, y, theta, k: int, params: Params, cell_w: int | None = None, device="cuda"):
+    def create(cls, x, y, theta, k: int, params: Params, cell_w: int | None = None, device="cuda",
+               block: int = 0):
         n = int(len(x))
         dev = torch.device(device)
-        ws = Workspace(n, params.box, cell_w, dev)
+        ws = Workspace(n, params.box, cell_w, dev, block=block)
         t = lambda a, dt: torch.as_tensor(a, dtype=dt).to(dev).contiguous()
         sysm = cls(ws, k, params, t(x, torch.int32), t(y, torch.int32), t(theta, torch.float32),
                    torch.empty((n, k), dtype=torch.int32, device=dev))

@@ -44,6 +44,15 @@ def test_invalid_grids_rejected(n, box, w):
     assert nm.lib().nm_workspace_bytes(ctypes.byref(g)) == nm.NM_E_INVAL
 
 
+@pytest.mark.parametrize("block,ok", [(0, True), (-1, True), (4, True), (15, True), (16, False), (2, False),
+                                      (-2, False), (nm.NM_BLOCK_SUBSTRIPS, True),
+                                      (nm.NM_BLOCK_SUBSTRIPS | 6, True), (nm.NM_BLOCK_SUBSTRIPS | 2, False),
+                                      (nm.NM_BLOCK_SUBSTRIPS | 16, False), (0x200, False)])
+def test_block_field_and_substrip_flag(block, ok):
+    g = nm.Grid(1 << 20, 1 << 20, 1024, block)
+    assert (nm.lib().nm_workspace_bytes(ctypes.byref(g)) > 0) == ok
+
+
 def test_workspace_size_grows_with_cells_and_particles():
     b = lambda n, w: nm.lib().nm_workspace_bytes(ctypes.byref(nm.Grid(n, 1 << 20, w, 0)))
     assert b(1 << 20, 1024) > b(1 << 20, 2048) > 0

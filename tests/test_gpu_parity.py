@@ -362,12 +362,15 @@ def test_full_size_uniform_1m_sampled():
     assert abs(offs_np[-1] / n - 7.0) < 0.05  # mean metric degree of the chosen r_c
 
 
+@pytest.mark.parametrize("block", [0, nm.NM_BLOCK_SUBSTRIPS])
 @pytest.mark.parametrize("k", [6, 12, 20])
-def test_full_size_clustered_4m_sampled(k):
+def test_full_size_clustered_4m_sampled(k, block):
+    # (at w = 1024 about one strip in 17 (k = 6) and one in four (k = 12) has
+    # a halo larger than LDS)
     n = 1 << 22
     x, y, th = workloads.clustered(n)
     p = nm.make_params(L, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
-    sysm = nm.System.create(x, y, th, k, p, cell_w=nm.suggest_cell_w(n, L, 1.0))
+    sysm = nm.System.create(x, y, th, k, p, cell_w=nm.suggest_cell_w(n, L, 1.0), block=block)
     sysm.step()
     assert nm.check(sysm.ws) == 0
     _device_invariants(_dev(x, torch.int32), _dev(y, torch.int32), sysm.nbr, k)
@@ -625,7 +628,9 @@ def test_knn_fast_path_query_last_in_home_row():
 # hold halos larger than the staging buffer.  Such a strip runs as sub-strips
 # of whole rows staged one after another; a row whose own halo is too large is
 # searched in global memory.  Each case reaches both kinds (counted with a host
-# model of the strip tables): (box, n, clusters, width, k, cell width).
+# model of the strip tables): (box, n, clusters, width, k, cell width).  Both
+# kernels run each case: block 0 (such strips search global memory) and
+# NM_BLOCK_SUBSTRIPS (sub-strips).
 SPLIT_CASES = [
     (1 << 16, 40000, 16, 0.005, 7, 256),    # narrow strips: 17 overflow, 42 sub-strips, 6 rows global
     (1 << 16, 40000, 8, 0.003, 12, 128),    # narrow: 21 overflow, 396 sub-strips, 353 global
@@ -634,10 +639,11 @@ SPLIT_CASES = [
 ]
 
 
+@pytest.mark.parametrize("block", [0, nm.NM_BLOCK_SUBSTRIPS, nm.NM_BLOCK_SUBSTRIPS | 4])
 @pytest.mark.parametrize("box,n,ncl,sf,k,w", SPLIT_CASES)
-def test_knn_strips_larger_than_lds_match_oracle(box, n, ncl, sf, k, w):
+def test_knn_strips_larger_than_lds_match_oracle(box, n, ncl, sf, k, w, block):
     x, y, th = workloads.clustered(n, box=box, n_clusters=ncl, sigma_frac=sf)
-    ws = nm.Workspace(n, box, w)
+    ws = nm.Workspace(n, box, w, block=block)
     nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
     nbr, d2 = nm.knn(ws, k, with_d2=True)
     assert nm.check(ws) == 0
@@ -645,7 +651,7 @@ def test_knn_strips_larger_than_lds_match_oracle(box, n, ncl, sf, k, w):
     assert np.array_equal(nbr.cpu().numpy(), rn) and np.array_equal(d2.cpu().numpy(), rd)
     # the fused step over the same strips
     p = nm.make_params(box, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
-    sysm = nm.System.create(x, y, th, k, p, cell_w=w)
+    sysm = nm.System.create(x, y, th, k, p, cell_w=w, block=block)
     sysm.step()
     assert nm.check(sysm.ws) == 0
     sn, sx, sy, st = oracle.step(x, y, th, box, k, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
