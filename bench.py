@@ -388,14 +388,17 @@ def bench_clustered(args, torch, nm, workloads):
 
 def bench_fov(args, torch, nm, workloads):
     """Field-of-view k-NN lists at N = 2^20 uniform, k = 7, on the cells of a
-    w = 2048 grid: kernel time per cone (HIP events), beside the plain k-NN
-    list kernel on the same cells."""
+    w = 2048 grid: kernel time per cone (HIP events) of the strip kernel and
+    of the one-lane ring search (block -1), beside the plain k-NN list kernel
+    on the same cells."""
     n, k, box = args.n, args.k, workloads.BOX
     dev = torch.device("cuda:0")
     x, y, th = workloads.uniform(n)
     X, Y, T = (torch.as_tensor(a).to(dev) for a in (x, y, th))
     ws = nm.Workspace(n, box, 2048, dev)
     nm.build_cells(ws, X, Y)
+    ws_ring = nm.Workspace(n, box, 2048, dev, block=-1)
+    nm.build_cells(ws_ring, X, Y)
     nbr = torch.empty((n, k), dtype=torch.int32, device=dev)
     out = {"n": n, "k": k, "cell_w": 2048}
 
@@ -413,10 +416,11 @@ def bench_fov(args, torch, nm, workloads):
     out["plain_knn_ms"] = timed(lambda: nm.knn(ws, k, nbr))
     for name, c in (("all_-4096", -4096), ("half_plane_0", 0), ("60deg_2048", 2048), ("30deg_3547", 3547)):
         ms = timed(lambda: nm.knn_fov(ws, k, T, c, nbr))
-        out[name] = {"cos_q": c, "ms": ms, "queries_per_s": n / (ms * 1e-3),
+        ring = timed(lambda: nm.knn_fov(ws_ring, k, T, c, nbr))
+        out[name] = {"cos_q": c, "ms": ms, "queries_per_s": n / (ms * 1e-3), "ring_search_ms": ring,
                      "roofline_frac": (8 + 4 + 4 * k) * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        log(f"[bench] field-of-view k-NN cos_q={c}: {ms:.4f} ms")
-    if nm.check(ws) != 0:
+        log(f"[bench] field-of-view k-NN cos_q={c}: {ms:.4f} ms (ring search {ring:.4f} ms)")
+    if nm.check(ws) != 0 or nm.check(ws_ring) != 0:
         raise RuntimeError("device error in the field-of-view lists")
     return out
 

@@ -198,8 +198,8 @@ int nm_knn_fov(const nm_grid* g, const void* ws, int32_t k, const float* theta, 
   Layout lay;
   if (!make_layout(g, &lay) || ws == nullptr || nbr == nullptr || theta == nullptr) return NM_E_INVAL;
   if (k < 1 || k > NM_MAX_K || k > g->n - 1 || cos_q < -4096 || cos_q > 4096) return NM_E_INVAL;
-  return status_of(launch_knn_fov(dev_ws(g, lay, const_cast<void*>(ws)), theta, k, cos_q, nbr,
-                                  as_stream(stream)));
+  return status_of(launch_knn_fov(dev_ws(g, lay, const_cast<void*>(ws)), g->block, theta, k, cos_q,
+                                  nbr, as_stream(stream)));
 }
 
 int nm_metric_list(const nm_grid* g, void* ws, int64_t rc2, int32_t* offsets, int32_t* idx,

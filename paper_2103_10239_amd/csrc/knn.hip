@@ -22,6 +22,7 @@
 // fp64 unit vectors stored beside the cell-ordered copy (the neighbours'
 // entries sit in the cells just scanned, so they are cache hits) and writes
 // the list, the new position and the new heading at the particle's index.
+#include "fov.h"
 #include "strip.h"
 
 namespace nm {
@@ -324,16 +325,31 @@ __device__ __forceinline__ StripBlock strip_block(int rx, int oy, int cy, int Bq
   return b;
 }
 
+// Candidate filters of the strip search: every staged particle, or those
+// inside the query's field of view.
+struct NoFilter {
+  static constexpr bool kActive = false;
+};
+
+struct FovFilter {
+  static constexpr bool kActive = true;
+  FovHeading h;
+  __device__ bool visible_short(int dx, int dy, int d2) const { return fov_visible_short(dx, dy, d2, h); }
+  __device__ bool visible(long long dx, long long dy) const { return fov_visible(dx, dy, h); }
+};
+
 // Certified search of one staged query over LDS.  self: the query's LDS
 // index; (pq, pqy): its relative position (narrow: packed pair in pq);
 // (rx, oy): its x offset from the halo corner and y offset in its cell; cy:
-// its halo row.  True with `lds` filled (LDS indices of the k nearest, in
-// order) when they are certified.
-template <int KMAX, bool kWide>
+// its halo row.  True with `lds` filled (LDS indices of the k nearest that
+// pass `filt`, in order) when they are certified.  Anything outside the
+// block is farther than its edge whatever the filter, so the certificate
+// holds for the filtered lists too.
+template <int KMAX, bool kWide, class Filter>
 __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, const int* rbase,
                                              const int* lpos, const int* lidx, int W, int self,
                                              int pq, int pqy, int rx, int oy, int cy, int k, int Bq,
-                                             int (&lds)[KMAX]) {
+                                             const Filter& filt, int (&lds)[KMAX]) {
   constexpr int KT = KMAX + 1;
   const int2* lpos2 = reinterpret_cast<const int2*>(lpos);
   if (Bq > tc.bmax) return false;
@@ -356,6 +372,8 @@ __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, 
           const unsigned long long d2 = static_cast<unsigned long long>(dx * dx + dy * dy);
           kk[u] = (static_cast<uint32_t>(min(d2, static_cast<unsigned long long>(b.bound)) >> sh) << 13) |
                   static_cast<uint32_t>(i + u);
+          if constexpr (Filter::kActive)
+            if (!filt.visible(dx, dy)) kk[u] = kKey32Inf;
         }
       } else {
         int pc[kUnroll];
@@ -366,6 +384,10 @@ __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, 
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t d2 = static_cast<uint32_t>(rel_d2(pc[u], pq));
           kk[u] = ((min(d2, clampd) >> sh) << 13) | static_cast<uint32_t>(i + u);
+          if constexpr (Filter::kActive) {
+            const short2v dd = __builtin_bit_cast(short2v, pc[u]) - __builtin_bit_cast(short2v, pq);
+            if (!filt.visible_short(dd[0], dd[1], static_cast<int>(d2))) kk[u] = kKey32Inf;
+          }
         }
       }
 #pragma unroll
@@ -413,9 +435,10 @@ __device__ __forceinline__ void ring_cell(int r, int q, int& dx, int& dy) {
 // across the lanes and evaluate 64 per round; candidates that beat the
 // current k-th are merged one by one (their keys broadcast to every lane,
 // which all hold the same list).  Same stop rule as the lane search.
-template <int KMAX>
+// Candidates that fail `filt` are skipped.
+template <int KMAX, class Filter = NoFilter>
 __device__ __forceinline__ bool knn_wave(const DevWs& w, int s, const int4& q, int k, int total,
-                                         int (&slot)[KMAX]) {
+                                         int (&slot)[KMAX], const Filter& filt = Filter{}) {
   const int lane = threadIdx.x & 63;
   const int sh = 32 - w.log2_box;
   const int cw = 1 << w.log2_w;
@@ -464,7 +487,9 @@ __device__ __forceinline__ bool knn_wave(const DevWs& w, int s, const int4& q, i
           if (t != s) {
             const int4 e = w.sorted[t];
             const int ex = wrap_axis(e.x - q.x, sh), ey = wrap_axis(e.y - q.y, sh);
-            kk = pack_key(static_cast<long long>(ex) * ex + static_cast<long long>(ey) * ey, e.z);
+            bool keep = true;
+            if constexpr (Filter::kActive) keep = filt.visible(ex, ey);
+            if (keep) kk = pack_key(static_cast<long long>(ex) * ex + static_cast<long long>(ey) * ey, e.z);
           }
         }
         unsigned long long better = __ballot(kk < top.worst());
@@ -519,6 +544,8 @@ __device__ __forceinline__ StripBox strip_box(const DevWs& w, const TileCfg& tc,
 enum StripMode {
   kOverflowGlobal = 0,  // search its queries in global memory (fast block search)
   kOverflowSplit = 1,   // run it as sub-strips of whole rows, each staged in turn
+  kFieldOfView = 2,     // field-of-view lists (a.theta, a.cone); such a strip's
+                        // queries and the uncertified ones take the exact search
 };
 
 template <int KMAX, bool kAlign, int kMode>
@@ -600,10 +627,19 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
     }
     const int Bq = strip_block_rows(f, s_rbase, W, cy, k);
     int nb[KMAX];
-    const bool ok = wide ? strip_search<KMAX, true>(w, tc, s_rbase, lpos, lidx, W, self, pq, pqy, rx, oy,
-                                                    cy, k, Bq, nb)
-                         : strip_search<KMAX, false>(w, tc, s_rbase, lpos, lidx, W, self, pq, pqy, rx, oy,
-                                                     cy, k, Bq, nb);
+    bool ok;
+    if constexpr (kMode == kFieldOfView) {
+      const FovFilter filt{fov_heading(a.theta[lidx[self]], a.cone)};
+      ok = wide ? strip_search<KMAX, true>(w, tc, s_rbase, lpos, lidx, W, self, pq, pqy, rx, oy, cy, k, Bq,
+                                           filt, nb)
+                : strip_search<KMAX, false>(w, tc, s_rbase, lpos, lidx, W, self, pq, pqy, rx, oy, cy, k, Bq,
+                                            filt, nb);
+    } else {
+      ok = wide ? strip_search<KMAX, true>(w, tc, s_rbase, lpos, lidx, W, self, pq, pqy, rx, oy, cy, k, Bq,
+                                           NoFilter{}, nb)
+                : strip_search<KMAX, false>(w, tc, s_rbase, lpos, lidx, W, self, pq, pqy, rx, oy, cy, k, Bq,
+                                            NoFilter{}, nb);
+    }
     const int s = strip_slot(strip_lds(), self);
     if (!ok) {
       defer(s);
@@ -654,12 +690,16 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
     int slot[KMAX];
     const int s = w.start[static_cast<int64_t>(y0_cur + r) * G + tb.x0] + (qi - s_qoff[r]);
     const int4 q = w.sorted[s];
+    if constexpr (kMode == kFieldOfView) {
+      fov_exact<KMAX>(w, s, q, fov_heading(a.theta[q.z], a.cone), k, total, nbr);
+      return;
+    }
     if (knn_fast<KMAX>(w, f, s, q.x, q.y, k, total, slot))
       finish_query<KMAX, kAlign>(w, s, q, slot, k, nbr, d2out, a);
     else
       defer(s);
   };
-  if constexpr (kMode == kOverflowGlobal) {
+  if constexpr (kMode != kOverflowSplit) {
     int npts, nq;
     const bool staged = strip_stage<true>(w, geo, strip_lds(), total, npts, nq);
     if (nq == 0) return;
@@ -732,19 +772,29 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   // each lane searches its own; with a few, a wavefront searches one at a
   // time, so that a single long search is not one lane's serial chain.
   const int nl = min(nd, kDeferCap);
-  if (nl > 16) {
+  if (kMode == kFieldOfView && nl > 16) {
+    for (int j = threadIdx.x; j < nl; j += kBlock) {
+      const int sq = s_dq[j];
+      const int4 q = w.sorted[sq];
+      fov_exact<KMAX>(w, sq, q, fov_heading(a.theta[q.z], a.cone), k, total, nbr);
+    }
+  } else if (kMode != kFieldOfView && nl > 16) {
     for (int j = threadIdx.x; j < nl; j += kBlock) exact_lane<KMAX, kAlign>(w, s_dq[j], k, total, nbr, d2out, a);
   } else {
     for (int j = threadIdx.x >> 6; j < nl; j += kBlock / 64) {
       const int sq = s_dq[j];
       const int4 q = w.sorted[sq];
       int slot[KMAX];
-      const bool ok = knn_wave<KMAX>(w, sq, q, k, total, slot);
+      bool ok;
+      if constexpr (kMode == kFieldOfView)
+        ok = knn_wave<KMAX>(w, sq, q, k, total, slot, FovFilter{fov_heading(a.theta[q.z], a.cone)});
+      else
+        ok = knn_wave<KMAX>(w, sq, q, k, total, slot);
       if (lane == 0) {
         if (ok)
           finish_query<KMAX, kAlign>(w, sq, q, slot, k, nbr, d2out, a);
         else
-          set_err(w.hdr, NM_E_RANGE);  // fewer than k other particles were binned
+          set_err(w.hdr, NM_E_RANGE);  // fewer than k other (visible) particles were binned
       }
     }
   }
@@ -756,7 +806,12 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
       for (int sq = a0 + threadIdx.x; sq < a1; sq += kBlock) {
         if (w.dflag[sq]) {
           w.dflag[sq] = 0;
-          exact_lane<KMAX, kAlign>(w, sq, k, total, nbr, d2out, a);
+          if constexpr (kMode == kFieldOfView) {
+            const int4 q = w.sorted[sq];
+            fov_exact<KMAX>(w, sq, q, fov_heading(a.theta[q.z], a.cone), k, total, nbr);
+          } else {
+            exact_lane<KMAX, kAlign>(w, sq, k, total, nbr, d2out, a);
+          }
         }
       }
     }
@@ -768,6 +823,22 @@ __global__ __launch_bounds__(kBlock) void k_knn(DevWs w, FastCfg f, TileCfg tc, 
                                                 int32_t* __restrict__ nbr,
                                                 long long* __restrict__ d2out, AlignArgs a) {
   knn_tile_body<KMAX, kAlign, kMode>(w, f, tc, k, nbr, d2out, a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Field-of-view lists over the same strips (a.theta: headings, a.cone: the
+// cone's cos(half angle) * 4096).
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void k_knn_fov_strip(DevWs w, FastCfg f, TileCfg tc, int k,
+                                                          int32_t* __restrict__ nbr, AlignArgs a) {
+  knn_tile_body<KMAX, false, kFieldOfView>(w, f, tc, k, nbr, nullptr, a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+template <int KMAX>
+hipError_t launch_fov_strip_t(const DevWs& w, const FastCfg& f, const TileCfg& tc, int k, int32_t* nbr,
+                              const AlignArgs& a, hipStream_t s) {
+  const int ntiles = tc.ntx * tc.nty;
+  hipLaunchKernelGGL(k_knn_fov_strip<KMAX>, dim3(ntiles), dim3(kBlock), 0, s, w, f, tc, k, nbr, a);
+  return hipGetLastError();
 }
 
 // Batched k-NN + alignment.  Items of the tile stage are (system, tile); the
@@ -942,6 +1013,28 @@ FastCfg fast_cfg(const DevWs& w, int k, int block) {
   f.bmax = bmax;
   f.bmax_w = bw;
   return f;
+}
+
+// A cone of half angle alpha sees the fraction alpha / pi of the directions,
+// so its k nearest visible lie about as far as the k / (alpha / pi) nearest
+// of all: the strips and blocks are sized for that many.
+hipError_t launch_knn_fov_strips(const DevWs& w, int block, const float* theta, int k, int c,
+                                 int32_t* nbr, hipStream_t s) {
+  FastCfg f = fast_cfg(w, k, block);
+  const double alpha = acos(fmax(-1.0, fmin(1.0, c / 4096.0)));
+  const double frac = fmax(alpha / 3.141592653589793, 1.0 / 64.0);
+  const int ks = static_cast<int>(ceil(k / frac));
+  const TileCfg tc = tile_cfg_impl(w, f, ks);
+  f.reach = static_cast<float>(f.reach * sqrt(static_cast<double>(ks) / k));
+  AlignArgs a{};
+  a.theta = theta;
+  a.cone = c;
+  if (k <= 4) return launch_fov_strip_t<4>(w, f, tc, k, nbr, a, s);
+  if (k <= 8) return launch_fov_strip_t<8>(w, f, tc, k, nbr, a, s);
+  if (k <= 12) return launch_fov_strip_t<12>(w, f, tc, k, nbr, a, s);
+  if (k <= 16) return launch_fov_strip_t<16>(w, f, tc, k, nbr, a, s);
+  if (k <= 24) return launch_fov_strip_t<24>(w, f, tc, k, nbr, a, s);
+  return launch_fov_strip_t<32>(w, f, tc, k, nbr, a, s);
 }
 
 hipError_t launch_knn(const DevWs& w, int k, int block, int32_t* nbr, long long* d2, hipStream_t s) {

@@ -512,6 +512,7 @@ struct AlignArgs {
   int32_t* x_out;
   int32_t* y_out;
   float* theta_out;
+  int32_t cone;  // field-of-view lists: cos(half angle) * 4096
 };
 
 // ---------------------------------------------------------------------------
@@ -590,7 +591,10 @@ int batch_grid(const void* kernel, int items);
 hipError_t launch_batch_bin(const BatchRef& b, int stage, hipStream_t s);
 hipError_t launch_batch_knn(const BatchRef& b, int k, hipStream_t s);
 hipError_t launch_batch_advance(const BatchRef& b, hipStream_t s);
-hipError_t launch_knn_fov(const DevWs& w, const float* theta, int k, int c, int32_t* nbr, hipStream_t s);
+hipError_t launch_knn_fov(const DevWs& w, int block, const float* theta, int k, int c, int32_t* nbr,
+                          hipStream_t s);
+hipError_t launch_knn_fov_strips(const DevWs& w, int block, const float* theta, int k, int c,
+                                 int32_t* nbr, hipStream_t s);
 hipError_t launch_polar_order(const float* theta, int32_t n, double* sums, hipStream_t s);
 hipError_t launch_align(const int32_t* x, const int32_t* y, const float* theta, int32_t n,
                         const int32_t* nbr, const int32_t* offsets, int32_t k, long long nnz_cap,

@@ -465,7 +465,7 @@ def _gpu_knn_block(x, y, k, w, block):
     return nbr.cpu().numpy(), d2.cpu().numpy()
 
 
-@pytest.mark.parametrize("block", [-1, 0, 3, 4, 5, 6, 8])
+@pytest.mark.parametrize("block", [-1, 0, 3, 4, 5, 6, 8, nm.NM_BLOCK_SUBSTRIPS, nm.NM_BLOCK_SUBSTRIPS | 5])
 @pytest.mark.parametrize("kind,n,k,w", [("uniform", 20013, 7, 4096), ("uniform", 20013, 1, 8192),
                                         ("uniform", 20013, 20, 4096), ("clustered", 20013, 12, 2048),
                                         ("squeezed", 3000, 7, 1024), ("clustered", 8191, 32, 4096)])
@@ -660,11 +660,14 @@ def test_knn_strips_larger_than_lds_match_oracle(box, n, ncl, sf, k, w, block):
     assert _angle_err(sysm.theta.cpu().numpy(), st).max() <= TOL
 
 
+# block 0 and 4: the strip kernel with the cone as a candidate filter; -1:
+# one lane per query running the exact ring search.
+@pytest.mark.parametrize("block", [0, 4, -1])
 @pytest.mark.parametrize("kind,n,w", [("uniform", 4097, 2048), ("clustered", 8191, 1024), ("squeezed", 3000, 2048)])
 @pytest.mark.parametrize("cos_q", [-4096, -2048, 0, 2048, 3500])
-def test_knn_fov_matches_oracle(kind, n, w, cos_q):
+def test_knn_fov_matches_oracle(kind, n, w, cos_q, block):
     x, y, th = _gen(kind, n)
-    ws = nm.Workspace(n, L, w)
+    ws = nm.Workspace(n, L, w, block=block)
     nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
     T = _dev(th, torch.float32)
     for k in (1, 7):
@@ -680,15 +683,42 @@ def test_knn_fov_matches_oracle(kind, n, w, cos_q):
             assert np.array_equal(got.cpu().numpy()[rows], ref[rows])
 
 
-def test_knn_fov_full_size_sampled():
+# Strips of int32 offset pairs (sparse box) and strips whose halo overflows
+# LDS (their queries take the exact search), against the full oracle lists.
+@pytest.mark.parametrize("case", ["wide", "overflow"])
+@pytest.mark.parametrize("cos_q", [-2048, 0, 2048])
+def test_knn_fov_strip_layouts_match_oracle(case, cos_q):
+    if case == "wide":
+        box, w = L, 16384
+        x, y, th = workloads.uniform(16384)
+    else:
+        box, w = 1 << 16, 256
+        x, y, th = workloads.clustered(40000, box=box, n_clusters=16, sigma_frac=0.005)
+    n = len(x)
+    ws = nm.Workspace(n, box, w)
+    nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
+    got = nm.knn_fov(ws, 7, _dev(th, torch.float32), cos_q)
+    st = nm.check(ws)
+    ref, ok = oracle.knn_fov(x, y, th, box, 7, cos_q)
+    if ok:
+        assert st == 0
+        assert np.array_equal(got.cpu().numpy(), ref)
+    else:
+        assert st == nm.NM_E_RANGE
+        rows = (ref >= 0).all(axis=1)
+        assert np.array_equal(got.cpu().numpy()[rows], ref[rows])
+
+
+@pytest.mark.parametrize("cos_q", [0, 3500])
+def test_knn_fov_full_size_sampled(cos_q):
     n, k = 1 << 20, 7
     x, y, th = workloads.uniform(n)
     ws = nm.Workspace(n, L, 2048)
     nm.build_cells(ws, _dev(x, torch.int32), _dev(y, torch.int32))
-    got = nm.knn_fov(ws, k, _dev(th, torch.float32), 0)
+    got = nm.knn_fov(ws, k, _dev(th, torch.float32), cos_q)
     assert nm.check(ws) == 0
     rows = _sample_rows(n, 500, 17)
-    ref, ok = oracle.knn_fov(x, y, th, L, k, 0, rows=rows)
+    ref, ok = oracle.knn_fov(x, y, th, L, k, cos_q, rows=rows)
     assert ok
     assert np.array_equal(got[torch.as_tensor(rows).long().cuda()].cpu().numpy(), ref)
 
