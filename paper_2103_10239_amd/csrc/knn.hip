@@ -892,7 +892,7 @@ __global__ __launch_bounds__(kBlock) void k_bb_knn(BatchRef b, int k) {
 // half width.  The strip height aims at about 256 queries; the halo must fit
 // the staging buffer and the row table, W <= G (a block never meets itself
 // around the box), and narrow strips keep every block under 2^15 units.
-TileCfg tile_cfg_impl(const DevWs& w, const FastCfg& f, int k) {
+TileCfg tile_cfg_impl(const DevWs& w, const FastCfg& f, int k, bool narrow_strips) {
   TileCfg t{1, 1, 0, 0, w.G, w.G, 0, 0};
   const double rho = static_cast<double>(w.n) / static_cast<double>(w.C);  // particles per cell
   const double rr = rho > 1e-12 ? rho : 1e-12;
@@ -916,10 +916,14 @@ TileCfg tile_cfg_impl(const DevWs& w, const FastCfg& f, int k) {
   // neighbour distance, not only its mean.
   int hx = min(max(1, static_cast<int>(ceil(kReachX * rk))), 15);
   if (f.bfix > 0) hx = min(max(hx, f.bfix / 2), 15);
-  // Strip width: two columns once the halo is wide, and at least the
-  // narrowest power of two whose strips reach ~256 queries within the row
-  // limit.
-  int tw = hx >= 3 ? 2 : 1;  // (wider strips stage each particle fewer times)
+  // Strip width: wider as the halo widens (hx 2: two columns, hx >= 3: four),
+  // and at least the narrowest power of two whose strips reach ~256 queries
+  // within the row limit.  Wider strips stage each particle fewer times and
+  // leave fewer queries near a strip's side.  `narrow_strips` (two columns
+  // only from hx 3) serves the sub-strip kernel, whose wide strips overflow
+  // LDS more often, and the field-of-view lists, whose blocks span every
+  // column of the strip.
+  int tw = narrow_strips ? (hx >= 3 ? 2 : 1) : (hx >= 3 ? 4 : (hx >= 2 ? 2 : 1));
   while (tw < 16 && 2 * tw <= w.G && 256.0 / (tw * rr) > 1.1 * (kStripRows - 2 * hy)) tw *= 2;
   while (hx > 1 && tw + 2 * hx > w.G) --hx;
   while (hy > 1 && 2 * hy + 1 > w.G) --hy;
@@ -946,7 +950,7 @@ TileCfg tile_cfg_impl(const DevWs& w, const FastCfg& f, int k) {
 template <int KMAX, bool kAlign>
 hipError_t launch_t(const DevWs& w, const FastCfg& f, int k, int32_t* nbr, long long* d2,
                     const AlignArgs& a, hipStream_t s) {
-  const TileCfg tc = tile_cfg_impl(w, f, k);
+  const TileCfg tc = tile_cfg_impl(w, f, k, f.split != 0);
   const int ntiles = tc.ntx * tc.nty;
   if (f.split && tc.hx > 0)
     hipLaunchKernelGGL((k_knn<KMAX, kAlign, kOverflowSplit>), dim3(ntiles), dim3(kBlock), 0, s, w, f,
@@ -975,7 +979,7 @@ hipError_t dispatch_k(int k, F&& f) {
 
 }  // namespace
 
-TileCfg tile_cfg(const DevWs& w, const FastCfg& f, int k) { return tile_cfg_impl(w, f, k); }
+TileCfg tile_cfg(const DevWs& w, const FastCfg& f, int k) { return tile_cfg_impl(w, f, k, false); }
 
 hipError_t launch_batch_knn(const BatchRef& b, int k, hipStream_t s) {
   const int nt = b.begin[kStKnn + 1] - b.begin[kStKnn];
@@ -1024,7 +1028,7 @@ hipError_t launch_knn_fov_strips(const DevWs& w, int block, const float* theta, 
   const double alpha = acos(fmax(-1.0, fmin(1.0, c / 4096.0)));
   const double frac = fmax(alpha / 3.141592653589793, 1.0 / 64.0);
   const int ks = static_cast<int>(ceil(k / frac));
-  const TileCfg tc = tile_cfg_impl(w, f, ks);
+  const TileCfg tc = tile_cfg_impl(w, f, ks, true);
   f.reach = static_cast<float>(f.reach * sqrt(static_cast<double>(ks) / k));
   AlignArgs a{};
   a.theta = theta;
