@@ -187,7 +187,9 @@ int nm_align_step(const int32_t* x, const int32_t* y, const float* theta, int32_
  *   nbr    device int32[n * k], row-major in the caller's order
  *   k      1 <= k <= min(NM_MAX_K, n - 1)
  * A particle that sees fewer than k others makes nm_check() report
- * NM_E_RANGE (its row is then unspecified). */
+ * NM_E_RANGE (its row is then unspecified).  g->block >= 0 runs the strip
+ * kernel of nm_knn with the cone as a candidate filter; -1 one lane per
+ * particle with the exact ring search.  The lists are the same. */
 int nm_knn_fov(const nm_grid* g, const void* ws, int32_t k, const float* theta, int32_t cos_q,
                int32_t* nbr, void* stream);
 
