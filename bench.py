@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--cell-w", type=int, default=0, help="cell width (0: tuned)")
     ap.add_argument("--block", type=int, default=0, help="fast-path block side with --cell-w")
     ap.add_argument("--retune-every", type=int, default=200, help="re-pick the grid every this many steps")
+    ap.add_argument("--retune-reps", type=int, default=1, help="timed steps per candidate when re-picking")
     ap.add_argument("--metric-steps", type=int, default=100)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--served-seconds", type=float, default=15.0)
@@ -190,7 +191,7 @@ def bench_single(args, torch, nm, workloads):
                 if w_lo <= w2 <= w_hi:
                     cand.add((w2, 0))
             nm.tune_grid(n, box, s["x"], s["y"], s["t"], k, p, step_index=s["step"],
-                         pairs=sorted(cand), reps=2, device=dev, ws=ws)
+                         pairs=sorted(cand), reps=args.retune_reps, device=dev, ws=ws)
             grids.add((ws.grid.cell_w, ws.grid.block))
         nm.bin_step(ws, s["x"], s["y"], s["t"], p, s["step"])
         if ev is not None:
