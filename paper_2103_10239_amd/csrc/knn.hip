@@ -1,8 +1,11 @@
 // knn.hip -- topological neighbour lists (Sec. III: each particle interacts
-// with its k nearest neighbours) and the fused step kernel.
+// with its k nearest neighbours), the fused step kernel and the field-of-view
+// lists.
 //
-// One lane per query, queries taken in cell order so that a wavefront's
-// queries are spatial neighbours and read the same cached cells.
+// The kernels work on strips of cells staged in LDS (see "Strips" below);
+// queries that a strip cannot serve from LDS run the global-memory paths
+// here, one lane per query, queries taken in cell order so that a
+// wavefront's queries are spatial neighbours and read the same cached cells.
 //
 // Fast path: the lane scans a B x B block of cells around the query (a few
 // contiguous slot ranges) and pushes every candidate through a branch-free
@@ -270,18 +273,19 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
 }
 
 // ---------------------------------------------------------------------------
-// Strips.  A workgroup owns a strip of tw x th cells (tw = 1 or 2 columns,
+// Strips.  A workgroup owns a strip of tw x th cells (tw = 1 to 16 columns,
 // about 256 queries) and stages the halo of W = tw + 2 hx columns by
 // R = th + 2 hy rows into LDS: the LDS offset of each halo row, and every
 // particle's position in the strip's periodic image relative to the halo
-// corner, with its cell-ordered slot.  A query's block is all W columns of
+// corner, with its particle index.  A query's block is all W columns of
 // Bq consecutive halo rows around its own, so its candidates are one
 // contiguous LDS range, read several at a time.  Positions are a packed pair
 // of 16-bit offsets whose differences are taken in 16-bit wrap-around
 // arithmetic (exact: every block spans under 2^15 units), so that a squared
 // distance is one packed subtract and one 16-bit dot product; where a block
 // spans more (sparse systems) they are int32 pairs with 64-bit distances.
-// A strip whose halo holds more particles than fit searches global memory.
+// A strip whose halo holds more particles than fit searches global memory,
+// or, in the sub-strip kernel, runs as sub-strips staged in turn.
 // Uncertified queries are finished at the end of the strip by the exact
 // search.
 // ---------------------------------------------------------------------------
