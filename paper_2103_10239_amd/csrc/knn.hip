@@ -291,6 +291,7 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
 // ---------------------------------------------------------------------------
 constexpr int kDeferCap = 128;    // uncertified queries listed in LDS per strip
 constexpr double kReachX = 1.25;  // strip half width, in mean k-th-neighbour radii
+constexpr double kReachY = 1.2;   // halo height over the expected block height
 
 
 // Block height for a staged query: fixed, or such that the block edge sits
@@ -913,9 +914,12 @@ TileCfg tile_cfg_impl(const DevWs& w, const FastCfg& f, int k, bool narrow_strip
     return t;
   };
   if (bmax_all < 1) return plain();
-  const int bq = f.bfix > 0 ? f.bfix : static_cast<int>(ceil(2.0 * f.reach * rk)) + 1;
-  // (block heights travel in 5 bits of the work-sorted order: hy <= 15)
-  int hy = min((bq + 2) / 2, 15);  // rows for the block plus one widening step
+  // Halo rows: for a block kReachY times the expected height (queries in
+  // sparse rows choose taller blocks; 1 with `narrow_strips`), plus one
+  // widening step.
+  const double ry = narrow_strips ? 1.0 : kReachY;
+  const int bq = f.bfix > 0 ? f.bfix : static_cast<int>(ceil(2.0 * ry * f.reach * rk)) + 1;
+  int hy = min((bq + 2) / 2, 15);  // (hy <= 15: block heights fit 5 bits)
   // The block width is fixed per strip, so it covers the tail of the k-th
   // neighbour distance, not only its mean.
   int hx = min(max(1, static_cast<int>(ceil(kReachX * rk))), 15);
@@ -924,9 +928,9 @@ TileCfg tile_cfg_impl(const DevWs& w, const FastCfg& f, int k, bool narrow_strip
   // and at least the narrowest power of two whose strips reach ~256 queries
   // within the row limit.  Wider strips stage each particle fewer times and
   // leave fewer queries near a strip's side.  `narrow_strips` (two columns
-  // only from hx 3) serves the sub-strip kernel, whose wide strips overflow
-  // LDS more often, and the field-of-view lists, whose blocks span every
-  // column of the strip.
+  // only from hx 3, and halo rows for the expected block height) serves the
+  // sub-strip kernel, whose larger halos overflow LDS more often, and the
+  // field-of-view lists, whose blocks span every column of the strip.
   int tw = narrow_strips ? (hx >= 3 ? 2 : 1) : (hx >= 3 ? 4 : (hx >= 2 ? 2 : 1));
   while (tw < 16 && 2 * tw <= w.G && 256.0 / (tw * rr) > 1.1 * (kStripRows - 2 * hy)) tw *= 2;
   while (hx > 1 && tw + 2 * hx > w.G) --hx;
