@@ -192,11 +192,12 @@ def test_align_step_variants_match_oracle(variant, include_self, eta):
 @pytest.mark.parametrize("variant", [nm.NM_NOISE_SCALAR, nm.NM_MOVE_NEW_HEADING,
                                      nm.NM_NOISE_SCALAR | nm.NM_MOVE_NEW_HEADING])
 @pytest.mark.parametrize("kind,n,w", [("uniform", 4097, 2048), ("clustered", (1 << 17) + 3, 1024)])
-def test_fused_step_variants_match_oracle(variant, kind, n, w):
+@pytest.mark.parametrize("block", [0, nm.NM_BLOCK_SUBSTRIPS])
+def test_fused_step_variants_match_oracle(variant, kind, n, w, block):
     k = 7
     x, y, th = _gen(kind, n) if kind == "uniform" else workloads.clustered(n)
     p = nm.make_params(L, v0=64, eta=0.4, seed=workloads.NOISE_SEED, variant=variant)
-    sysm = nm.System.create(x, y, th, k, p, cell_w=w)
+    sysm = nm.System.create(x, y, th, k, p, cell_w=w, block=block)
     sysm.step()
     assert nm.check(sysm.ws) == 0
     rows = None if n < 10000 else np.concatenate([_sample_rows(n, 400, 3), [0, n - 1]]).astype(np.int32)
