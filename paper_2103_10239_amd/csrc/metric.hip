@@ -93,7 +93,8 @@ MetricCfg metric_cfg(const DevWs& w, long long rc2) {
     return m;
   };
   if (h < 1 || 4 * h + 1 > kStripRows || 2 * h + 1 > w.G) return plain();
-  int tw = 1;
+  // two columns once the halo is two wide (each particle staged fewer times)
+  int tw = h >= 2 ? 2 : 1;
   while (tw < 16 && 2 * tw <= w.G && 256.0 / (tw * rr) > 1.1 * (kStripRows - 2 * h)) tw *= 2;
   if (tw + 2 * h > w.G) return plain();
   const int W = tw + 2 * h;
