@@ -15,6 +15,13 @@ computes, with the passage of arXiv:2103.10239 it follows:
   most r_0, as CSR rows ordered the same way.
 - ``align_step``: Eq. (2) (alignment with vectorial noise, normalised) and
   Eq. (1) (Euler move with the heading at time t), in fp64.
+- ``voronoi``: the Delaunay rule of Sec. III / Sec. IV -- i and j are
+  neighbours when their Voronoi cells share an edge, decided pair by pair by
+  an exact test on their bisector against every other particle; rows in
+  counter-clockwise order.
+- ``voronoi_forces``: the Voronoi model of Sec. V -- cell areas and
+  perimeters, the energy of Eq. (3), vertex forces (Eqs. 5-8) and particle
+  forces (Eqs. 9-19), fp64.
 - ``philox4x32_10`` / ``noise_word`` / ``noise_angle``: the counter-based
   generator (Salmon et al., SC'11) that supplies the random unit vector of
   Eq. (2).
@@ -40,7 +47,9 @@ _vp = ctypes.c_void_p
 
 
 class OracleError(RuntimeError):
-    pass
+    def __init__(self, msg: str, status: int = 0):
+        super().__init__(msg)
+        self.status = status
 
 
 def _load():
@@ -80,6 +89,16 @@ def _load():
     lib.orc_fov_visible.restype = ctypes.c_int
     lib.orc_polar_order.argtypes = [_f32p, ctypes.c_int32]
     lib.orc_polar_order.restype = ctypes.c_double
+    lib.orc_voronoi.argtypes = [_i32p, _i32p, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32,
+                                ctypes.c_int32, _i32p, _i32p]
+    lib.orc_voronoi.restype = ctypes.c_int
+    lib.orc_voronoi_local.argtypes = [_i32p, _i32p, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_int32, _i32p, _i32p]
+    lib.orc_voronoi_local.restype = ctypes.c_int
+    _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+    lib.orc_voronoi_forces.argtypes = [_f64p, _f64p, ctypes.c_int32, ctypes.c_double, _i64p, _i32p] + \
+        [ctypes.c_double] * 4 + [_vp] * 9
+    lib.orc_voronoi_forces.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -88,7 +107,7 @@ def _load():
 
 def _check(rc: int, what: str) -> None:
     if rc != OK:
-        raise OracleError(f"{what}: oracle status {rc}")
+        raise OracleError(f"{what}: oracle status {rc}", rc)
 
 
 def _i32(a) -> np.ndarray:
@@ -227,3 +246,57 @@ def step(x, y, theta, box: int, k: int, *, v0: int, eta: float, seed: int, sys_i
     xo, yo, to = align_step(x, y, theta, box, nbr=nbr, v0=v0, eta=eta, seed=seed, sys_id=sys_id,
                             include_self=include_self, step=step_index, variant=variant)
     return nbr, xo, yo, to
+
+
+def voronoi(x, y, box: int, rows=None, dmax: int = 64, rho0: int | None = None):
+    """Voronoi (Delaunay) neighbour rows, counter-clockwise from the +x axis.
+
+    Returns (offsets int64[rows + 1], idx int32[nnz]).  rows=None: every
+    particle, by the bisector test against all others.  With rows and rho0:
+    the same rows from the particles within a radius that starts at rho0 and
+    doubles until every cell vertex lies within half of it (for sampled rows
+    of large systems).  Raises OracleError (status E_RANGE) for coincident
+    particles or a cell vertex L/8 or more from its particle."""
+    x, y = _i32(x), _i32(y)
+    n = int(x.size)
+    rp, nr, _keep = _rows_arg(rows, n)
+    ring = np.zeros(nr * dmax, dtype=np.int32)
+    deg = np.zeros(nr, dtype=np.int32)
+    if rho0 is not None:
+        if rows is None:
+            raise ValueError("rho0 needs rows")
+        rc = _load().orc_voronoi_local(x, y, n, box, rp, nr, int(rho0), dmax, ring, deg)
+    else:
+        rc = _load().orc_voronoi(x, y, n, box, rp, nr, dmax, ring, deg)
+    _check(rc, "voronoi")
+    offsets = np.zeros(nr + 1, dtype=np.int64)
+    np.cumsum(deg, out=offsets[1:])
+    ring = ring.reshape(nr, dmax)
+    idx = np.concatenate([ring[r, :deg[r]] for r in range(nr)]) if nr else np.zeros(0, np.int32)
+    return offsets, idx.astype(np.int32)
+
+
+def voronoi_forces(x, y, box, offsets, idx, ka: float, kp: float, a0: float, p0: float,
+                   vertices: bool = False) -> dict:
+    """Voronoi model (Sec. V) on the rings (offsets, idx) of every particle, at
+    real positions x, y in a periodic box: area, perimeter, force (fx, fy) per
+    particle, the energy of Eq. (3), and with vertices=True per ring slot the
+    vertex h (relative to its particle) and the vertex force -dE/dh."""
+    xd = np.ascontiguousarray(x, dtype=np.float64)
+    yd = np.ascontiguousarray(y, dtype=np.float64)
+    n = int(xd.size)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    ix = _i32(idx)
+    nnz = int(off[-1])
+    out = {k: np.zeros(n) for k in ("area", "perim", "fx", "fy")}
+    e = np.zeros(1)
+    vk = ("hx", "hy", "vfx", "vfy")
+    if vertices:
+        out.update({k: np.zeros(nnz) for k in vk})
+    ptr = lambda a: a.ctypes.data_as(_vp)
+    rc = _load().orc_voronoi_forces(xd, yd, n, float(box), off, ix, ka, kp, a0, p0, ptr(out["area"]),
+                                    ptr(out["perim"]), ptr(out["fx"]), ptr(out["fy"]), ptr(e),
+                                    *[ptr(out[k]) if vertices else None for k in vk])
+    _check(rc, "voronoi_forces")
+    out["energy"] = float(e[0])
+    return out
