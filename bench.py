@@ -128,6 +128,17 @@ def pct(v, q):
     return v[i]
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(x, y, th, k, box, target_s):
     """Oracle (brute force, all host threads) on sampled query rows of the same system."""
     import numpy as np
@@ -150,6 +161,7 @@ def cpu_baseline(x, y, th, k, box, target_s):
     rows = rng.choice(n, size=m, replace=False).astype(np.int32)
     t = run(rows)
     return {"value": m / t, "unit": "particle-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{m} sampled particles of the N={n} uniform system: brute-force k-NN rows "
                       f"(O(N) per row) and the Eq. 1-2 step for them, {t:.1f} s",
             "seconds": t}
@@ -232,9 +244,11 @@ def bench_single(args, torch, nm, workloads):
 
 
 def bench_metric(args, torch, nm, workloads):
-    """Metric-mode steps from the initial state: binning, k-NN + align, and the
-    metric list (count, scan, fill) every step."""
-    n, k, box = args.n, args.k, workloads.BOX
+    """Metric-mode steps from the initial state (Sec. III, "all pairs within
+    r_0"): per step the cell binning, the metric list (count, scan, fill) and
+    Eq. (2) / Eq. (1) over the CSR rows.  The list's roofline fraction uses
+    each timed step's own mean degree."""
+    n, box = args.n, workloads.BOX
     dev = torch.device("cuda:0")
     rc2 = workloads.rc2_for_mean(n, 7.0)
     x, y, th = workloads.uniform(n)
@@ -242,40 +256,48 @@ def bench_metric(args, torch, nm, workloads):
     X, Y, T = (torch.as_tensor(a).to(dev) for a in (x, y, th))
     Xb, Yb, Tb = torch.empty_like(X), torch.empty_like(Y), torch.empty_like(T)
     ws = nm.Workspace(n, box, nm.suggest_cell_w(n, box, 4.0), dev)
-    nbr = torch.empty((n, k), dtype=torch.int32, device=dev)
     offsets = torch.empty(n + 1, dtype=torch.int32, device=dev)
     # Aligned groups cluster from the disordered start and the mean metric
     # degree grows (about 7 at step 0); a fixed capacity of 64 per particle
     # covers the timed steps, and an overflow would fail the run.
     idx = torch.empty(64 * n, dtype=torch.int32, device=dev)
     steps = args.metric_steps
+    nnz_dev = torch.zeros(steps, dtype=torch.int32, device=dev)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     s = {"x": X, "y": Y, "t": T, "xb": Xb, "yb": Yb, "tb": Tb}
+    i = 0
     for warm in (True, False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(3 if warm else steps):
-            nm.bin_step(ws, s["x"], s["y"], s["t"], p, i)
-            nm.knn_align(ws, k, p, s["t"], nbr, s["xb"], s["yb"], s["tb"])
+        for j in range(3 if warm else steps):
+            nm.build_cells(ws, s["x"], s["y"])
             if not warm:
-                ev[i][0].record()
+                ev[j][0].record()
             nm.metric_list(ws, rc2, offsets, idx)
             if not warm:
-                ev[i][1].record()
+                ev[j][1].record()
+                nnz_dev[j:j + 1].copy_(offsets[n:n + 1])
+            nm.align_step(s["x"], s["y"], s["t"], p, i, offsets=offsets, idx=idx,
+                          out=(s["xb"], s["yb"], s["tb"]), ws=ws)
             s["x"], s["xb"] = s["xb"], s["x"]
             s["y"], s["yb"] = s["yb"], s["y"]
             s["t"], s["tb"] = s["tb"], s["t"]
+            i += 1
         torch.cuda.synchronize()
         t1 = time.perf_counter()
     if nm.check(ws) != 0:
         raise RuntimeError("device error in metric-mode steps")
-    nnz = int(offsets[n].item())
-    m_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    nnz = nnz_dev.cpu().numpy().astype(float)
+    m_ms = [a.elapsed_time(b) for a, b in ev]
     ms_step = (t1 - t0) * 1e3 / steps
-    log(f"[bench] metric mode: {ms_step:.4f} ms/step, metric list {m_ms:.4f} ms, final nnz {nnz}")
-    return {"rc2": rc2, "steps": steps, "ms_per_step": ms_step, "metric_list_ms": m_ms,
-            "particle_steps_per_s": n / (ms_step * 1e-3), "final_mean_degree": nnz / n,
-            "metric_list_roofline_frac": (8 + 4 + 4 * nnz / n) * n / (m_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    fracs = [(8 + 4 + 4 * z / n) * n / (m * 1e-3) / 1e9 / HBM_PEAK_GBS for z, m in zip(nnz, m_ms)]
+    log(f"[bench] metric mode: {ms_step:.4f} ms/step, metric list {sum(m_ms) / steps:.4f} ms, "
+        f"mean degree {nnz[0] / n:.2f} -> {nnz[-1] / n:.2f}")
+    return {"rc2": rc2, "steps": steps, "ms_per_step": ms_step, "metric_list_ms": sum(m_ms) / steps,
+            "particle_steps_per_s": n / (ms_step * 1e-3), "mean_degree_first": nnz[0] / n,
+            "mean_degree_last": nnz[-1] / n, "mean_degree_avg": float(nnz.mean()) / n,
+            "metric_list_roofline_frac": sum(fracs) / len(fracs),
+            "step": "cell binning, metric list, Eq. 2 / Eq. 1 over the CSR rows"}
 
 
 def bench_variants(args, torch, nm, workloads):
@@ -686,7 +708,9 @@ def main():
         "neighbor_queries_per_s": value,
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_knn<{k},align>",
+            "scope": "kernel: the fused k-NN + Eq. 2 / Eq. 1 kernel alone (step_roofline_frac covers the "
+                     "whole step with the binning)",
+            "kernel": f"nm::k_knn<{k}, true, 0>",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -144,6 +144,22 @@ int nm_build_cells(const nm_grid* g, const int32_t* x, const int32_t* y, void* w
 int nm_knn(const nm_grid* g, const void* ws, int32_t k, int32_t* nbr, int64_t* d2,
            void* stream);
 
+/* Host-only description of the strip kernel that nm_knn, nm_knn_align and
+ * nm_step run for grid g and list length k (no device work; for tests and
+ * tuning reports).  out: HOST int32[10] =
+ *   [0] kernel: 0 = no staging (one row of queries per strip, searched in
+ *       global memory), 1 = staged strips (default kernel), 2 = staged
+ *       strips with the sub-strip kernel (NM_BLOCK_SUBSTRIPS)
+ *   [1] strip width tw, [2] strip height th (cells)
+ *   [3] halo columns hx, [4] halo rows hy (cells on each side)
+ *   [5] fixed block side (0: chosen per query)
+ *   [6] 1 if staged offsets are int32 pairs with 64-bit distances, 0 if
+ *       packed 16-bit offsets
+ *   [7] tallest block the halo supports (rows)
+ *   [8] strips across, [9] strips down
+ * The layout depends on n, box, cell_w, block and k only. */
+int nm_knn_layout(const nm_grid* g, int32_t k, int32_t* out);
+
 /* Metric neighbour list (Sec. III, "all pairs within r_0") as CSR rows in
  * the caller's particle order, each row ascending by (d^2, j).
  *   rc2      r_0^2 in grid units^2, 0 <= rc2 < 2^40

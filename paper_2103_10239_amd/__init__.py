@@ -9,6 +9,6 @@ Eq. (1), as hand-written HIP kernels behind the C ABI of include/nm.h.
 from . import nm, workloads  # noqa: F401
 from .nm import (NM_E_CAPACITY, NM_E_DEVICE, NM_E_INVAL, NM_E_NOMEM, NM_E_RANGE, NM_MAX_K,  # noqa: F401
                  NM_BLOCK_SUBSTRIPS, NM_MOVE_NEW_HEADING, NM_NOISE_SCALAR, NM_OK, Batch, Grid, NMError, Params, Server, System,
-                 Workspace, align_step, bin_step, build_cells, check, knn, knn_align, knn_fov, make_params,
+                 Workspace, align_step, bin_step, build_cells, check, knn, knn_align, knn_fov, knn_layout, make_params,
                  metric_list,
                  polar_order, server_job_bytes, step, suggest_cell_w, tune_grid)

@@ -193,6 +193,22 @@ int nm_knn(const nm_grid* g, const void* ws, int32_t k, int32_t* nbr, int64_t* d
                               reinterpret_cast<long long*>(d2), as_stream(stream)));
 }
 
+int nm_knn_layout(const nm_grid* g, int32_t k, int32_t* out) {
+  Layout lay;
+  if (!make_layout(g, &lay) || out == nullptr) return NM_E_INVAL;
+  if (k < 1 || k > NM_MAX_K || k > g->n - 1) return NM_E_INVAL;
+  DevWs w{};  // geometry only: the layout reads no device memory
+  w.n = g->n;
+  w.box = g->box;
+  w.cell_w = g->cell_w;
+  w.log2_box = lay.log2_box;
+  w.log2_w = lay.log2_w;
+  w.G = lay.G;
+  w.C = lay.C;
+  knn_layout(w, k, g->block, out);
+  return NM_OK;
+}
+
 int nm_knn_fov(const nm_grid* g, const void* ws, int32_t k, const float* theta, int32_t cos_q,
                int32_t* nbr, void* stream) {
   Layout lay;

@@ -1049,6 +1049,23 @@ hipError_t launch_knn_fov_strips(const DevWs& w, int block, const float* theta, 
   return launch_fov_strip_t<32>(w, f, tc, k, nbr, a, s);
 }
 
+void knn_layout(const DevWs& w, int k, int block, int32_t out[10]) {
+  const FastCfg f = fast_cfg(w, k, block);
+  const TileCfg tc = tile_cfg_impl(w, f, k, f.split != 0);
+  // kernel: 0 = one row of queries per strip, searched in global memory;
+  // 1 = staged strips (default kernel); 2 = staged strips, sub-strip kernel
+  out[0] = tc.hx == 0 ? 0 : (f.split ? 2 : 1);
+  out[1] = tc.tw;
+  out[2] = tc.th;
+  out[3] = tc.hx;
+  out[4] = tc.hy;
+  out[5] = f.bfix;
+  out[6] = tc.wide;
+  out[7] = tc.bmax;
+  out[8] = tc.ntx;
+  out[9] = tc.nty;
+}
+
 hipError_t launch_knn(const DevWs& w, int k, int block, int32_t* nbr, long long* d2, hipStream_t s) {
   const FastCfg f = fast_cfg(w, k, block);
   AlignArgs a{};

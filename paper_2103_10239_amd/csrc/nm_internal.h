@@ -585,6 +585,8 @@ hipError_t launch_metric_fill(const DevWs& w, long long rc2, const int32_t* offs
 hipError_t launch_scan_rows(int32_t* data, int64_t m, ScanState* st, int nb, WsHeader* hdr,
                             hipStream_t s);
 TileCfg tile_cfg(const DevWs& w, const FastCfg& f, int k);
+// Host-only description of the k-NN kernel a grid runs (nm_knn_layout).
+void knn_layout(const DevWs& w, int k, int block, int32_t out[10]);
 // Persistent grid for a batched stage: at most `items` workgroups, at most
 // what stays resident on the device.
 int batch_grid(const void* kernel, int items);

@@ -98,6 +98,7 @@ def lib():
     L.nm_check.argtypes = [_vp, _vp]
     L.nm_polar_order.argtypes = [_vp, _c_i32, _vp, _vp]
     L.nm_knn_fov.argtypes = [gp, _vp, _c_i32, _vp, _c_i32, _vp, _vp]
+    L.nm_knn_layout.argtypes = [gp, _c_i32, ctypes.POINTER(_c_i32)]
     L.nm_tune_grid.argtypes = [gp, _c_i32, _vp, _vp, _vp, _c_i32, pp, _c_u64, _vp, ctypes.c_size_t,
                                _vp, _vp, _vp, _vp, _c_i32, ctypes.POINTER(_c_i32),
                                ctypes.POINTER(ctypes.c_float), _vp]
@@ -120,7 +121,7 @@ def lib():
     for f in ("nm_server_create", "nm_server_submit", "nm_server_poll", "nm_server_wait",
               "nm_server_stats"):
         getattr(L, f).restype = ctypes.c_int
-    for f in ("nm_workspace_init", "nm_build_cells", "nm_knn", "nm_metric_list", "nm_align_step",
+    for f in ("nm_workspace_init", "nm_build_cells", "nm_knn", "nm_knn_layout", "nm_metric_list", "nm_align_step",
               "nm_step", "nm_bin_step", "nm_knn_align", "nm_check", "nm_tune_grid", "nm_batch_plan", "nm_batch_bind",
               "nm_batch_step", "nm_batch_tune", "nm_batch_system", "nm_batch_check"):
         getattr(L, f).restype = ctypes.c_int
@@ -176,6 +177,16 @@ def knn_fov(ws: Workspace, k: int, theta: torch.Tensor, cos_q: int, nbr: torch.T
     _ok(lib().nm_knn_fov(ctypes.byref(ws.grid), ws.ptr, k, _dev(theta, torch.float32, n, "theta"), cos_q,
                          _dev(nbr, torch.int32, n * k, "nbr"), _stream(ws.device)), "knn_fov")
     return nbr
+
+
+KNN_LAYOUT_FIELDS = ("kernel", "tw", "th", "hx", "hy", "bfix", "wide", "bmax", "ntx", "nty")
+
+
+def knn_layout(n: int, box: int, cell_w: int, block: int, k: int) -> dict:
+    """The strip layout nm_knn / nm_step run for this grid and k (host only)."""
+    out = (_c_i32 * 10)()
+    _ok(lib().nm_knn_layout(ctypes.byref(Grid(n, box, cell_w, block)), k, out), "knn_layout")
+    return dict(zip(KNN_LAYOUT_FIELDS, [int(v) for v in out]))
 
 
 def polar_order(theta: torch.Tensor, sums: torch.Tensor | None = None) -> float:
