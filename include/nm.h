@@ -179,7 +179,9 @@ int nm_metric_list(const nm_grid* g, void* ws, int64_t rc2, int32_t* offsets, in
  * and headings at t give r(t+1)).
  *   x, y, theta     int32/int32/fp32 [n], time t
  *   nbr             fixed-k lists int32[n * k] (offsets == NULL), k >= 0, or
- *                   CSR column indices int32[nnz_cap] (offsets != NULL)
+ *                   CSR column indices int32[nnz_cap] (offsets != NULL); a
+ *                   fixed-k row may end early, padded with -1 after its last
+ *                   neighbour (rows of varying length such as nm_voronoi's)
  *   offsets         int32[n + 1] CSR row starts, or NULL
  *   nnz_cap         length of the CSR index array (ignored for fixed k)
  *   x_out, y_out, theta_out  [n], time t+1; must not alias the inputs
@@ -208,6 +210,63 @@ int nm_align_step(const int32_t* x, const int32_t* y, const float* theta, int32_
  * particle with the exact ring search.  The lists are the same. */
 int nm_knn_fov(const nm_grid* g, const void* ws, int32_t k, const float* theta, int32_t cos_q,
                int32_t* nbr, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Voronoi (Delaunay) neighbour lists: the topological rule of Sec. III in
+ * which neighbours are the edges of a Delaunay triangulation, through its
+ * dual, the Voronoi diagram (Sec. IV).  i and j are neighbours when their
+ * Voronoi cells share an edge of positive length; where four or more
+ * particles are co-circular (a square lattice) cells that touch in a single
+ * point are not neighbours, so the lists are unique for every input and
+ * reciprocal.  Positions as for the other rules (minimum images in the
+ * periodic box).  The lists are defined when every particle's cell lies
+ * within L/8 of it and no two particles coincide; otherwise nm_check()
+ * reports NM_E_RANGE and the affected rows are unspecified.
+ *
+ * Rows: ring int32[n * dmax], row i = the neighbours of particle i
+ * counter-clockwise by the direction of the minimum-image offset, starting
+ * at the +x axis (offsets with dy > 0, or dy = 0 and dx > 0, first), padded
+ * with -1; deg int32[n] = the row lengths.  Consecutive entries a_t, a_{t+1}
+ * of row i are the triangles (i, a_t, a_{t+1}) of the Delaunay
+ * triangulation, whose circumcentres are the cell's vertices.  A row longer
+ * than dmax records NM_E_CAPACITY (the row keeps its first dmax entries).
+ * ------------------------------------------------------------------------ */
+#define NM_VORONOI_MAX_DEG 64
+
+/* Voronoi lists from the cells built in ws (nm_build_cells or nm_bin_step).
+ *   dmax   3 <= dmax <= NM_VORONOI_MAX_DEG (16 holds any row of a uniform
+ *          system with overwhelming probability)
+ * The workspace's Voronoi list and counters are used as scratch (ws is not
+ * const).  Enqueued on `stream`. */
+int nm_voronoi(const nm_grid* g, void* ws, int32_t dmax, int32_t* ring, int32_t* deg, void* stream);
+
+/* "Do I need to recompute the Voronoi diagram?" (Sec. IV), as a test of the
+ * triangulation held in (ring, deg) -- rows built for earlier positions --
+ * against the positions x, y (device int32[n], caller order): every
+ * triangle of consecutive row entries must still turn counter-clockwise,
+ * the three rows of each triangle must agree, every row must wind once
+ * around its particle with offsets below L/4, and every edge must be
+ * strictly locally Delaunay (the fourth particle strictly outside the
+ * circumcircle).  If all hold, the rows are still exactly the Voronoi
+ * lists of x, y, up to the start of each row.
+ *   stale  device uint8[n], out: 1 for every particle whose own test failed
+ *          and every particle of its row (the rows a flip may change)
+ *   nfail  device int32 or NULL, out: how many particles failed; 0 means
+ *          no recomputation is needed
+ * ws (grid g, n particles) holds the counters only. */
+int nm_voronoi_check(const nm_grid* g, void* ws, const int32_t* x, const int32_t* y, int32_t dmax,
+                     const int32_t* ring, const int32_t* deg, uint8_t* stale, int32_t* nfail,
+                     void* stream);
+
+/* Bring rows built for earlier positions up to date for the positions
+ * x, y, whose cells ws must hold (nm_build_cells / nm_bin_step with x, y):
+ * twice, nm_voronoi_check, then the stale rows recomputed and the others
+ * rotated to start at the +x axis again; then the check once more, and if
+ * any row still fails, every row recomputed.  Afterwards (ring, deg) equal
+ * what nm_voronoi gives for x, y.  nfail (device int32 or NULL) receives
+ * the first check's count.  stale: device uint8[n] scratch. */
+int nm_voronoi_update(const nm_grid* g, void* ws, const int32_t* x, const int32_t* y, int32_t dmax,
+                      int32_t* ring, int32_t* deg, uint8_t* stale, int32_t* nfail, void* stream);
 
 /* Polar order parameter of the headings (Sec. III: the ordered, flocking
  * phase is the one whose headings agree): sums[0] = sum_i cos theta_i,

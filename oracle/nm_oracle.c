@@ -355,6 +355,10 @@ int orc_align_step(const int32_t* x, const int32_t* y, const float* theta, int32
     double sx = 0.0, sy = 0.0;
     for (int64_t t = begin; t < end; ++t) {
       int32_t j = nbr[t];
+      if (j == -1 && !offsets) { /* a fixed-k row padded after its last neighbour */
+        end = t;
+        break;
+      }
       if (j < 0 || j >= n) {
 #pragma omp atomic write
         bad = 1;

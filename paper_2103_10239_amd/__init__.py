@@ -11,4 +11,5 @@ from .nm import (NM_E_CAPACITY, NM_E_DEVICE, NM_E_INVAL, NM_E_NOMEM, NM_E_RANGE,
                  NM_BLOCK_SUBSTRIPS, NM_MOVE_NEW_HEADING, NM_NOISE_SCALAR, NM_OK, Batch, Grid, NMError, Params, Server, System,
                  Workspace, align_step, bin_step, build_cells, check, knn, knn_align, knn_fov, knn_layout, make_params,
                  metric_list,
-                 polar_order, server_job_bytes, step, suggest_cell_w, tune_grid)
+                 polar_order, server_job_bytes, step, suggest_cell_w, tune_grid, voronoi, voronoi_check,
+                 voronoi_update)

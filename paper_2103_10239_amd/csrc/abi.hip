@@ -72,6 +72,8 @@ bool make_layout(const nm_grid* g, Layout* out) {
   L.chunk_cap = g->n / 32 + 1024;
   L.off_chunks = off;
   off += round_up(16 * static_cast<int64_t>(L.chunk_cap));
+  L.off_vlist = off;
+  off += round_up(4 * static_cast<int64_t>(g->n));
   // two-level binning when a coarse bin of at most kFineCells cells suffices
   L.sb = 0;
   while ((L.C >> L.sb) > kCoarseBins) ++L.sb;
@@ -105,6 +107,7 @@ DevWs dev_ws(const nm_grid* g, const Layout& lay, void* ws) {
   w.cs = reinterpret_cast<double2*>(b + lay.off_cs);
   w.dflag = reinterpret_cast<uint8_t*>(b + lay.off_dflag);
   w.chunks = reinterpret_cast<int4*>(b + lay.off_chunks);
+  w.vlist = reinterpret_cast<int32_t*>(b + lay.off_vlist);
   w.chunk_cap = lay.chunk_cap;
   w.sb = lay.sb;
   w.nbins = lay.nbins;
@@ -239,6 +242,36 @@ int nm_metric_list(const nm_grid* g, void* ws, int64_t rc2, int32_t* offsets, in
   }
   if (idx == nullptr) return NM_OK;
   return status_of(launch_metric_fill(w, rc2, offsets, idx, cap, s));
+}
+
+int nm_voronoi(const nm_grid* g, void* ws, int32_t dmax, int32_t* ring, int32_t* deg, void* stream) {
+  Layout lay;
+  if (!make_layout(g, &lay) || ws == nullptr || ring == nullptr || deg == nullptr) return NM_E_INVAL;
+  if (g->n < 3 || g->box < 8 || dmax < 3 || dmax > NM_VORONOI_MAX_DEG) return NM_E_INVAL;
+  return status_of(launch_voronoi(dev_ws(g, lay, ws), dmax, ring, deg, as_stream(stream)));
+}
+
+int nm_voronoi_check(const nm_grid* g, void* ws, const int32_t* x, const int32_t* y, int32_t dmax,
+                     const int32_t* ring, const int32_t* deg, uint8_t* stale, int32_t* nfail,
+                     void* stream) {
+  Layout lay;
+  if (!make_layout(g, &lay) || ws == nullptr || x == nullptr || y == nullptr || ring == nullptr ||
+      deg == nullptr || stale == nullptr)
+    return NM_E_INVAL;
+  if (g->n < 3 || g->box < 8 || dmax < 3 || dmax > NM_VORONOI_MAX_DEG) return NM_E_INVAL;
+  return status_of(launch_voronoi_check(dev_ws(g, lay, ws), x, y, dmax, ring, deg, stale, nfail,
+                                        as_stream(stream)));
+}
+
+int nm_voronoi_update(const nm_grid* g, void* ws, const int32_t* x, const int32_t* y, int32_t dmax,
+                      int32_t* ring, int32_t* deg, uint8_t* stale, int32_t* nfail, void* stream) {
+  Layout lay;
+  if (!make_layout(g, &lay) || ws == nullptr || x == nullptr || y == nullptr || ring == nullptr ||
+      deg == nullptr || stale == nullptr)
+    return NM_E_INVAL;
+  if (g->n < 3 || g->box < 8 || dmax < 3 || dmax > NM_VORONOI_MAX_DEG) return NM_E_INVAL;
+  return status_of(launch_voronoi_update(dev_ws(g, lay, ws), x, y, dmax, ring, deg, stale, nfail, 2,
+                                         as_stream(stream)));
 }
 
 int nm_polar_order(const float* theta, int32_t n, double* sums, void* stream) {

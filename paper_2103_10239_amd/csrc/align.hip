@@ -47,6 +47,7 @@ __global__ __launch_bounds__(kBlock) void k_align(const int32_t* __restrict__ x,
   long long m = 0;
   for (long long t = begin; t < end; ++t) {
     const int j = nbr[t];
+    if (j == -1 && !offsets) break;  // a fixed-k row padded after its last neighbour
     if (static_cast<uint32_t>(j) >= static_cast<uint32_t>(n)) {
       set_err(err, NM_E_INVAL);
       continue;

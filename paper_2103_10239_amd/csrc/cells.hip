@@ -48,6 +48,11 @@ __device__ __forceinline__ void ws_init_body(const DevWs& w, int b, int nb) {
         w.hdr->ndefer[ph] = 0u;
         w.hdr->nchunk[ph] = 0u;
       }
+      w.hdr->nvwide = 0u;
+      w.hdr->nvdone = 0u;
+      w.hdr->nvstale = 0u;
+      w.hdr->nvfail = 0u;
+      w.hdr->varea2 = 0ull;
     }
   }
 }

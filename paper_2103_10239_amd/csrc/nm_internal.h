@@ -13,6 +13,7 @@
 //   dflag       uint8[n]     1 for a slot whose k-NN search is deferred (kept 0
 //                            between launches)
 //   chunks      int4[cap]    row chunks of dense metric strips, cap = n / 32 + 1024
+//   vlist       int32[n]     slots of Voronoi cells handed to the 64-bit kernel
 //   coarse      int4[n]      particles in coarse-bin order (two-level binning)
 //   hist        int32[nbins * nblk + 1]  per-workgroup coarse-bin counts, then
 //                            their exclusive prefix sum (bin-major)
@@ -50,7 +51,12 @@ struct WsHeader {
   uint32_t built;
   uint32_t ndefer[2];  // metric rows deferred to the wave kernels (count, fill pass)
   uint32_t nchunk[2];  // metric strip chunks pushed to the chunk kernels (count, fill pass)
-  int32_t pad[54];
+  uint32_t nvwide;     // Voronoi cells listed for the 64-bit kernel (in vlist)
+  uint32_t nvdone;     // workgroups of that kernel finished (the last one empties the list)
+  uint32_t nvstale;    // Voronoi rows listed for recomputation (in rank)
+  uint32_t nvfail;     // particles whose Voronoi row failed the last reuse test
+  unsigned long long varea2;  // sum over Voronoi rows of a_t x a_{t+1} (six times the area covered)
+  int32_t pad[48];
 };
 static_assert(sizeof(WsHeader) == 256, "header is one 256-byte block");
 
@@ -72,6 +78,7 @@ struct DevWs {
   double2* cs;
   uint8_t* dflag;
   int4* chunks;
+  int32_t* vlist;
   int4* coarse;
   int32_t* hist;
   ScanState* scan_h;
@@ -90,7 +97,7 @@ struct DevWs {
 
 struct Layout {
   int64_t off_scan_c, off_scan_m, off_count, off_start, off_rank, off_sorted, off_cs,
-      off_dflag, off_chunks, off_coarse, off_hist, off_scan_h, total;
+      off_dflag, off_chunks, off_vlist, off_coarse, off_hist, off_scan_h, total;
   int32_t log2_box, log2_w, G, nb_scan_c, nb_scan_m, chunk_cap, sb, nbins, nblk, nb_scan_h;
   int64_t C;
 };
@@ -598,6 +605,13 @@ hipError_t launch_knn_fov(const DevWs& w, int block, const float* theta, int k, 
 hipError_t launch_knn_fov_strips(const DevWs& w, int block, const float* theta, int k, int c,
                                  int32_t* nbr, hipStream_t s);
 hipError_t launch_polar_order(const float* theta, int32_t n, double* sums, hipStream_t s);
+hipError_t launch_voronoi(const DevWs& w, int dmax, int32_t* ring, int32_t* deg, hipStream_t s);
+hipError_t launch_voronoi_check(const DevWs& w, const int32_t* x, const int32_t* y, int dmax,
+                                const int32_t* ring, const int32_t* deg, uint8_t* stale, int32_t* nfail,
+                                hipStream_t s);
+hipError_t launch_voronoi_update(const DevWs& w, const int32_t* x, const int32_t* y, int dmax,
+                                 int32_t* ring, int32_t* deg, uint8_t* stale, int32_t* nfail, int rounds,
+                                 hipStream_t s);
 hipError_t launch_align(const int32_t* x, const int32_t* y, const float* theta, int32_t n,
                         const int32_t* nbr, const int32_t* offsets, int32_t k, long long nnz_cap,
                         const nm_params* p, uint64_t step, int32_t* x_out, int32_t* y_out,

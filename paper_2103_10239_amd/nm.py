@@ -99,6 +99,9 @@ def lib():
     L.nm_polar_order.argtypes = [_vp, _c_i32, _vp, _vp]
     L.nm_knn_fov.argtypes = [gp, _vp, _c_i32, _vp, _c_i32, _vp, _vp]
     L.nm_knn_layout.argtypes = [gp, _c_i32, ctypes.POINTER(_c_i32)]
+    L.nm_voronoi.argtypes = [gp, _vp, _c_i32, _vp, _vp, _vp]
+    L.nm_voronoi_check.argtypes = [gp, _vp, _vp, _vp, _c_i32, _vp, _vp, _vp, _vp, _vp]
+    L.nm_voronoi_update.argtypes = [gp, _vp, _vp, _vp, _c_i32, _vp, _vp, _vp, _vp, _vp]
     L.nm_tune_grid.argtypes = [gp, _c_i32, _vp, _vp, _vp, _c_i32, pp, _c_u64, _vp, ctypes.c_size_t,
                                _vp, _vp, _vp, _vp, _c_i32, ctypes.POINTER(_c_i32),
                                ctypes.POINTER(ctypes.c_float), _vp]
@@ -121,7 +124,8 @@ def lib():
     for f in ("nm_server_create", "nm_server_submit", "nm_server_poll", "nm_server_wait",
               "nm_server_stats"):
         getattr(L, f).restype = ctypes.c_int
-    for f in ("nm_workspace_init", "nm_build_cells", "nm_knn", "nm_knn_layout", "nm_metric_list", "nm_align_step",
+    for f in ("nm_workspace_init", "nm_build_cells", "nm_knn", "nm_knn_layout", "nm_voronoi",
+              "nm_voronoi_check", "nm_voronoi_update", "nm_metric_list", "nm_align_step",
               "nm_step", "nm_bin_step", "nm_knn_align", "nm_check", "nm_tune_grid", "nm_batch_plan", "nm_batch_bind",
               "nm_batch_step", "nm_batch_tune", "nm_batch_system", "nm_batch_check"):
         getattr(L, f).restype = ctypes.c_int
@@ -177,6 +181,58 @@ def knn_fov(ws: Workspace, k: int, theta: torch.Tensor, cos_q: int, nbr: torch.T
     _ok(lib().nm_knn_fov(ctypes.byref(ws.grid), ws.ptr, k, _dev(theta, torch.float32, n, "theta"), cos_q,
                          _dev(nbr, torch.int32, n * k, "nbr"), _stream(ws.device)), "knn_fov")
     return nbr
+
+
+NM_VORONOI_MAX_DEG = 64
+
+
+def voronoi(ws: Workspace, dmax: int = 16, ring: torch.Tensor | None = None,
+            deg: torch.Tensor | None = None):
+    """Voronoi (Delaunay) neighbour rows from the cells built in ws: (ring [n, dmax]
+    counter-clockwise from +x, padded with -1; deg [n])."""
+    n = ws.n
+    if ring is None:
+        ring = torch.empty((n, dmax), dtype=torch.int32, device=ws.device)
+    if deg is None:
+        deg = torch.empty(n, dtype=torch.int32, device=ws.device)
+    _ok(lib().nm_voronoi(ctypes.byref(ws.grid), ws.ptr, dmax, _dev(ring, torch.int32, n * dmax, "ring"),
+                         _dev(deg, torch.int32, n, "deg"), _stream(ws.device)), "voronoi")
+    return ring, deg
+
+
+def voronoi_check(ws: Workspace, x, y, ring, deg, stale: torch.Tensor | None = None,
+                  nfail: torch.Tensor | None = None):
+    """The reuse test of rows (ring, deg) against positions x, y: (stale uint8 [n],
+    nfail int32 [1] on the device; 0 means the rows are still exact)."""
+    n = ws.n
+    dmax = int(ring.shape[1])
+    if stale is None:
+        stale = torch.empty(n, dtype=torch.uint8, device=ws.device)
+    if nfail is None:
+        nfail = torch.empty(1, dtype=torch.int32, device=ws.device)
+    _ok(lib().nm_voronoi_check(ctypes.byref(ws.grid), ws.ptr, _dev(x, torch.int32, n, "x"),
+                               _dev(y, torch.int32, n, "y"), dmax, _dev(ring, torch.int32, n * dmax, "ring"),
+                               _dev(deg, torch.int32, n, "deg"), _dev(stale, torch.uint8, n, "stale"),
+                               _dev(nfail, torch.int32, 1, "nfail"), _stream(ws.device)), "voronoi_check")
+    return stale, nfail
+
+
+def voronoi_update(ws: Workspace, x, y, ring, deg, stale: torch.Tensor | None = None,
+                   nfail: torch.Tensor | None = None):
+    """Bring rows (ring, deg) up to date, in place, for positions x, y whose cells
+    ws holds; returns nfail (device int32 [1]: particles that failed the first
+    reuse test)."""
+    n = ws.n
+    dmax = int(ring.shape[1])
+    if stale is None:
+        stale = torch.empty(n, dtype=torch.uint8, device=ws.device)
+    if nfail is None:
+        nfail = torch.empty(1, dtype=torch.int32, device=ws.device)
+    _ok(lib().nm_voronoi_update(ctypes.byref(ws.grid), ws.ptr, _dev(x, torch.int32, n, "x"),
+                                _dev(y, torch.int32, n, "y"), dmax, _dev(ring, torch.int32, n * dmax, "ring"),
+                                _dev(deg, torch.int32, n, "deg"), _dev(stale, torch.uint8, n, "stale"),
+                                _dev(nfail, torch.int32, 1, "nfail"), _stream(ws.device)), "voronoi_update")
+    return nfail
 
 
 KNN_LAYOUT_FIELDS = ("kernel", "tw", "th", "hx", "hy", "bfix", "wide", "bmax", "ntx", "nty")
