@@ -721,6 +721,10 @@ def main():
             "kernel_ms_avg": r["k_ms"],
             "kernel_ms_p50": r["k_p50"],
             "kernel_ms_p99": r["k_p99"],
+            # in a kernel trace of this process, the timed launches are this
+            # kernel's launches [first, first + steps): the tuner's candidate
+            # steps (one untimed and five timed each) and the warm-up come first
+            "timed_launches_first": (len(r["tuned"]) * 6 if r["tuned"] else 0) + args.warmup,
         },
         "step_roofline_frac": bytes_per_ps * n / (r["ms_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
