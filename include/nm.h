@@ -300,6 +300,26 @@ int nm_knn_align(const nm_grid* g, const void* ws, int32_t k, const nm_params* p
                  const float* theta, int32_t* nbr, int32_t* x_out, int32_t* y_out,
                  float* theta_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): nm_step
+ * with the workspace in a file-scope device array of the library instead of
+ * a caller buffer.  Same arguments and results as nm_step without ws and
+ * ws_bytes; the grid's nm_workspace_bytes must not exceed
+ * NM_STEP_NOALLOC_MAX_BYTES (32 MiB, about 3e5 particles at one per cell),
+ * else NM_E_NOMEM before anything is enqueued.  Device-side errors (a
+ * coordinate outside [0, L)) are written to *err (device int32, NM_OK or the
+ * first error of this call; err may be NULL) on `stream`, without
+ * synchronising.  The array is looked up once per device with that device
+ * current (call with the stream's device current); each device holds its own
+ * copy until the process ends.  Every call on a device shares that array and
+ * re-initialises it: calls that overlap on one device (concurrent streams or
+ * host threads) race and must be serialised by the caller.  Calls no
+ * hipMalloc, hipFree or allocating library routine. */
+#define NM_STEP_NOALLOC_MAX_BYTES (32ll << 20)
+int nm_step_noalloc(const nm_grid* g, const int32_t* x, const int32_t* y, const float* theta, int32_t k,
+                    const nm_params* p, uint64_t step, int32_t* nbr, int32_t* x_out, int32_t* y_out,
+                    float* theta_out, int32_t* err, void* stream);
+
 /* Synchronise `stream`, return the first error recorded in `ws` since the
  * last check (NM_OK if none) and clear it. */
 int nm_check(void* ws, void* stream);

@@ -100,6 +100,7 @@ def lib():
     L.nm_knn_fov.argtypes = [gp, _vp, _c_i32, _vp, _c_i32, _vp, _vp]
     L.nm_knn_layout.argtypes = [gp, _c_i32, ctypes.POINTER(_c_i32)]
     L.nm_voronoi.argtypes = [gp, _vp, _c_i32, _vp, _vp, _vp]
+    L.nm_step_noalloc.argtypes = [gp, _vp, _vp, _vp, _c_i32, pp, _c_u64, _vp, _vp, _vp, _vp, _vp, _vp]
     L.nm_voronoi_check.argtypes = [gp, _vp, _vp, _vp, _c_i32, _vp, _vp, _vp, _vp, _vp]
     L.nm_voronoi_update.argtypes = [gp, _vp, _vp, _vp, _c_i32, _vp, _vp, _vp, _vp, _vp]
     L.nm_tune_grid.argtypes = [gp, _c_i32, _vp, _vp, _vp, _c_i32, pp, _c_u64, _vp, ctypes.c_size_t,
@@ -124,7 +125,7 @@ def lib():
     for f in ("nm_server_create", "nm_server_submit", "nm_server_poll", "nm_server_wait",
               "nm_server_stats"):
         getattr(L, f).restype = ctypes.c_int
-    for f in ("nm_workspace_init", "nm_build_cells", "nm_knn", "nm_knn_layout", "nm_voronoi",
+    for f in ("nm_workspace_init", "nm_build_cells", "nm_knn", "nm_knn_layout", "nm_voronoi", "nm_step_noalloc",
               "nm_voronoi_check", "nm_voronoi_update", "nm_metric_list", "nm_align_step",
               "nm_step", "nm_bin_step", "nm_knn_align", "nm_check", "nm_tune_grid", "nm_batch_plan", "nm_batch_bind",
               "nm_batch_step", "nm_batch_tune", "nm_batch_system", "nm_batch_check"):
