@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--clustered-steps", type=int, default=100)
     ap.add_argument("--no-clustered", action="store_true")
     ap.add_argument("--no-fov", action="store_true")
+    ap.add_argument("--no-voronoi", action="store_true")
+    ap.add_argument("--voronoi-steps", type=int, default=50)
     ap.add_argument("--no-metric", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -349,6 +351,93 @@ def bench_variants(args, torch, nm, workloads):
     out["polar_order_kernel_ms"] = o
     out["polar_order_roofline_frac"] = 4 * n / (o * 1e-3) / 1e9 / HBM_PEAK_GBS
     return out
+
+
+def bench_voronoi(args, torch, nm, workloads):
+    """Voronoi (Delaunay) neighbour rows and the Voronoi model at N = 2^20
+    uniform: the full build (nm_voronoi), the reuse test (nm_voronoi_check)
+    and the in-place update after one move, Vicsek steps with Voronoi
+    neighbours (cells, rows updated in place, Eq. 2 / Eq. 1 over the rows),
+    and the forces of Eq. (3) (nm_voronoi_forces).  Kernel times by HIP
+    events on the stream the library runs on."""
+    n, box, dmax = args.n, workloads.BOX, 32
+    dev = torch.device("cuda:0")
+    x, y, th = workloads.uniform(n)
+    X, Y, T = (torch.as_tensor(a).to(dev) for a in (x, y, th))
+    w = nm.suggest_cell_w(n, box, 1.0)
+    ws = nm.Workspace(n, box, w, dev)
+    nm.build_cells(ws, X, Y)
+    ring = torch.empty((n, dmax), dtype=torch.int32, device=dev)
+    deg = torch.empty(n, dtype=torch.int32, device=dev)
+    stale = torch.empty(n, dtype=torch.uint8, device=dev)
+    nfail = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    full_ms = timed(lambda: nm.voronoi(ws, dmax, ring, deg))
+    mean_deg = float(deg.double().mean().item())
+    check_ms = timed(lambda: nm.voronoi_check(ws, X, Y, ring, deg, stale, nfail))
+    a_mean = box * box / n
+    va = dict(ka=1.0 / a_mean, kp=1.0, a0=a_mean, p0=3.8 * a_mean ** 0.5)
+    forces_ms = timed(lambda: nm.voronoi_forces(X, Y, box, ring, deg, ws=ws, **va))
+    if nm.check(ws) != 0:
+        raise RuntimeError("device error in the Voronoi rows")
+    # Vicsek steps with Voronoi neighbours: the rows of step t are brought up
+    # to date in place for the positions of step t+1
+    p = nm.make_params(box, v0=64, eta=0.2, include_self=1, seed=workloads.NOISE_SEED)
+    s = {"x": X, "y": Y, "t": T, "xb": torch.empty_like(X), "yb": torch.empty_like(Y),
+         "tb": torch.empty_like(T)}
+    steps = args.voronoi_steps
+    fails = torch.zeros(steps, dtype=torch.int32, device=dev)
+    out = {}
+    for mode in ("update", "rebuild"):
+        nm.voronoi(ws, dmax, ring, deg)
+        for warm in (True, False):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(3 if warm else steps):
+                nm.align_step(s["x"], s["y"], s["t"], p, i, nbr=ring, out=(s["xb"], s["yb"], s["tb"]), ws=ws)
+                s["x"], s["xb"] = s["xb"], s["x"]
+                s["y"], s["yb"] = s["yb"], s["y"]
+                s["t"], s["tb"] = s["tb"], s["t"]
+                nm.build_cells(ws, s["x"], s["y"])
+                if mode == "update":
+                    nm.voronoi_update(ws, s["x"], s["y"], ring, deg, stale, fails[i:i + 1] if not warm else nfail)
+                else:
+                    nm.voronoi(ws, dmax, ring, deg)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        st = nm.check(ws)
+        if st != 0:
+            raise RuntimeError(f"device error in Voronoi Vicsek steps ({mode}): {nm.nm.status_str(st)}, "
+                               f"largest row {int(deg.max().item())}")
+        ms = (t1 - t0) * 1e3 / steps
+        out[mode] = {"ms_per_step": ms, "particle_steps_per_s": n / (ms * 1e-3)}
+        if mode == "update":
+            f = fails.cpu().numpy()
+            out[mode]["failed_rows_mean"] = float(f.mean())
+            out[mode]["failed_rows_frac"] = float(f.mean()) / n
+    log(f"[bench] voronoi N={n}: rows {full_ms:.4f} ms (mean degree {mean_deg:.3f}), check {check_ms:.4f} ms, "
+        f"forces {forces_ms:.4f} ms; Vicsek steps {out['update']['ms_per_step']:.4f} ms (update) / "
+        f"{out['rebuild']['ms_per_step']:.4f} ms (rebuild), failed rows per step "
+        f"{out['update']['failed_rows_mean']:.0f}")
+    rows_bytes = 8 + 4 * mean_deg + 4  # read x, y; write the row and its length
+    force_bytes = 8 + 4 * mean_deg + 4 + 32  # read x, y, row, length; write area, perimeter, force
+    return {"n": n, "cell_w": w, "dmax": dmax, "mean_degree": mean_deg,
+            "rows_ms": full_ms, "rows_per_s": n / (full_ms * 1e-3),
+            "rows_roofline_frac": rows_bytes * n / (full_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "check_ms": check_ms, "forces_ms": forces_ms,
+            "forces_roofline_frac": force_bytes * n / (forces_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "vicsek_steps": steps, "vicsek_update": out["update"], "vicsek_rebuild": out["rebuild"]}
 
 
 def grid_label(w, b):
@@ -736,6 +825,8 @@ def main():
         out["clustered_4m"] = bench_clustered(args, torch, nm, workloads)
     if not args.no_fov:
         out["field_of_view"] = bench_fov(args, torch, nm, workloads)
+    if not args.no_voronoi:
+        out["voronoi"] = bench_voronoi(args, torch, nm, workloads)
     if not args.no_batched:
         out["batched"] = bench_batched(args, torch, nm, workloads)
     if not args.no_served:

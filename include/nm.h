@@ -218,16 +218,20 @@ int nm_knn_fov(const nm_grid* g, const void* ws, int32_t k, const float* theta, 
  * Voronoi cells share an edge of positive length; where four or more
  * particles are co-circular (a square lattice) cells that touch in a single
  * point are not neighbours, so the lists are unique for every input and
- * reciprocal.  Positions as for the other rules (minimum images in the
- * periodic box).  The lists are defined when every particle's cell lies
- * within L/8 of it and no two particles coincide; otherwise nm_check()
- * reports NM_E_RANGE and the affected rows are unspecified.
+ * reciprocal.  Particles at the same position share one site: the diagram
+ * is that of the distinct positions, and a particle's neighbours are the
+ * other particles of its own site and every particle of each neighbouring
+ * site.  Positions as for the other rules (minimum images in the periodic
+ * box).  The lists are defined when every site's cell lies within L/8 of
+ * it; otherwise nm_check() reports NM_E_RANGE and the affected rows are
+ * unspecified.
  *
- * Rows: ring int32[n * dmax], row i = the neighbours of particle i
- * counter-clockwise by the direction of the minimum-image offset, starting
- * at the +x axis (offsets with dy > 0, or dy = 0 and dx > 0, first), padded
- * with -1; deg int32[n] = the row lengths.  Consecutive entries a_t, a_{t+1}
- * of row i are the triangles (i, a_t, a_{t+1}) of the Delaunay
+ * Rows: ring int32[n * dmax], row i = the other particles at particle i's
+ * position by index, then the neighbouring sites counter-clockwise by the
+ * direction of the minimum-image offset, starting at the +x axis (offsets
+ * with dy > 0, or dy = 0 and dx > 0, first), each site's particles by index;
+ * padded with -1; deg int32[n] = the row lengths.  Consecutive sites a_t,
+ * a_{t+1} of row i are the triangles (i, a_t, a_{t+1}) of the Delaunay
  * triangulation, whose circumcentres are the cell's vertices.  A row longer
  * than dmax records NM_E_CAPACITY (the row keeps its first dmax entries).
  * ------------------------------------------------------------------------ */
@@ -267,6 +271,37 @@ int nm_voronoi_check(const nm_grid* g, void* ws, const int32_t* x, const int32_t
  * the first check's count.  stale: device uint8[n] scratch. */
 int nm_voronoi_update(const nm_grid* g, void* ws, const int32_t* x, const int32_t* y, int32_t dmax,
                       int32_t* ring, int32_t* deg, uint8_t* stale, int32_t* nfail, void* stream);
+
+/* Voronoi model of dense tissue (Sec. V): each particle owns its Voronoi
+ * cell and the energy is Eq. (3), E = sum_i K_A (A_i - A_0)^2 +
+ * K_P (P_i - P_0)^2, in grid units (areas in units^2, lengths in units). */
+typedef struct nm_vm_params {
+  double ka, kp; /* area and perimeter moduli K_A, K_P                      */
+  double a0, p0; /* preferred area A_0 and perimeter P_0                    */
+} nm_vm_params;
+
+/* Cell areas and perimeters, the force on every particle, -dE/dr_i (Eq. 9,
+ * by the chain rule through the cell vertices, Eqs. 10-19), and optionally
+ * the energy and the vertex forces -dE/dh (Eqs. 5-8), all fp64, from the
+ * rows of nm_voronoi (ring int32[n * dmax], deg int32[n]) for positions
+ * x, y (device int32[n] in [0, box)).  The printed formulas are read as the
+ * gradient of Eq. (3): Eq. (8) dP/dh = t_ij/|t_ij| - t_ik/|t_ik|, c =
+ * r_ij x r_jk in Eqs. (15) and (19), Eq. (18) ending in -|r_ij|^2 r_jk.
+ *   area, perim, fx, fy  device double[n], out (area and perim required)
+ *   energy               device double or NULL: Eq. (3), summed in a fixed order
+ *   vertex               device double[n * dmax * 4] or NULL: for slot t of
+ *                        row i, vertex t of cell i (the circumcentre of
+ *                        (i, a_t, a_{t+1}), relative to particle i) and the
+ *                        force -dE/dh on it: (hx, hy, fx, fy)
+ *   ws_err               workspace whose error word receives NM_E_INVAL for
+ *                        rows that are not one triangulation and NM_E_RANGE
+ *                        for coincident particles (the model needs a cell per
+ *                        particle), or NULL
+ * box is L (power of two, 8 <= L <= 2^20). */
+int nm_voronoi_forces(const int32_t* x, const int32_t* y, int32_t n, int32_t box, int32_t dmax,
+                      const int32_t* ring, const int32_t* deg, const nm_vm_params* vp, double* area,
+                      double* perim, double* fx, double* fy, double* energy, double* vertex,
+                      void* ws_err, void* stream);
 
 /* Polar order parameter of the headings (Sec. III: the ordered, flocking
  * phase is the one whose headings agree): sums[0] = sum_i cos theta_i,

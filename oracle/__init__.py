@@ -97,7 +97,7 @@ def _load():
     lib.orc_voronoi_local.restype = ctypes.c_int
     _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
     lib.orc_voronoi_forces.argtypes = [_f64p, _f64p, ctypes.c_int32, ctypes.c_double, _i64p, _i32p] + \
-        [ctypes.c_double] * 4 + [_vp] * 9
+        [ctypes.c_double] * 4 + [_vp, ctypes.c_int32] + [_vp] * 9
     lib.orc_voronoi_forces.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
@@ -277,26 +277,30 @@ def voronoi(x, y, box: int, rows=None, dmax: int = 64, rho0: int | None = None):
 
 
 def voronoi_forces(x, y, box, offsets, idx, ka: float, kp: float, a0: float, p0: float,
-                   vertices: bool = False) -> dict:
+                   vertices: bool = False, rows=None) -> dict:
     """Voronoi model (Sec. V) on the rings (offsets, idx) of every particle, at
     real positions x, y in a periodic box: area, perimeter, force (fx, fy) per
     particle, the energy of Eq. (3), and with vertices=True per ring slot the
-    vertex h (relative to its particle) and the vertex force -dE/dh."""
+    vertex h (relative to its particle) and the vertex force -dE/dh.  With
+    rows, only those particles' forces (fx[r] for rows[r]); rows of fewer than
+    three entries then mark particles without a cell (NaN areas)."""
     xd = np.ascontiguousarray(x, dtype=np.float64)
     yd = np.ascontiguousarray(y, dtype=np.float64)
     n = int(xd.size)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
-    ix = _i32(idx)
+    ix = _i32(idx) if len(idx) else np.zeros(1, np.int32)
     nnz = int(off[-1])
-    out = {k: np.zeros(n) for k in ("area", "perim", "fx", "fy")}
+    rp, nr, _keep = _rows_arg(rows, n)
+    out = {k: np.zeros(n) for k in ("area", "perim")}
+    out.update({k: np.zeros(nr) for k in ("fx", "fy")})
     e = np.zeros(1)
     vk = ("hx", "hy", "vfx", "vfy")
     if vertices:
         out.update({k: np.zeros(nnz) for k in vk})
     ptr = lambda a: a.ctypes.data_as(_vp)
-    rc = _load().orc_voronoi_forces(xd, yd, n, float(box), off, ix, ka, kp, a0, p0, ptr(out["area"]),
+    rc = _load().orc_voronoi_forces(xd, yd, n, float(box), off, ix, ka, kp, a0, p0, rp, nr, ptr(out["area"]),
                                     ptr(out["perim"]), ptr(out["fx"]), ptr(out["fy"]), ptr(e),
                                     *[ptr(out[k]) if vertices else None for k in vk])
     _check(rc, "voronoi_forces")
-    out["energy"] = float(e[0])
+    out["energy"] = float(e[0]) if rows is None else None
     return out

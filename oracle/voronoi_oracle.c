@@ -20,20 +20,26 @@
  * pair is not a neighbour pair, so the relation is unique for every input
  * (it is the set of edges common to all Delaunay triangulations).
  *
- * Periodic box (readings):
+ * Periodic box and coincident particles (readings):
  *   - positions are integers in [0, L), vectors are minimum images with each
  *     component in [-L/2, L/2), as for the other neighbour rules;
+ *   - particles at the same position share one site: the diagram is that of
+ *     the distinct positions, and a particle's neighbours are the other
+ *     particles at its own site and every particle at each neighbouring site
+ *     (the paper's rule assumes distinct points; two coincident particles
+ *     have no bisector, and are each other's nearest possible neighbours);
  *   - the lists are defined when every Voronoi vertex lies strictly within
- *     L/8 of its particle (then only minimum images can shape a cell, every
+ *     L/8 of its site (then only minimum images can shape a cell, every
  *     Delaunay edge is shorter than L/4, and the minimum images of a
- *     triangle's three edges agree); otherwise the oracle reports E_RANGE;
- *   - two particles at the same position have no bisector: E_RANGE.
+ *     triangle's three edges agree); otherwise the oracle reports E_RANGE.
  *
- * Row order: each row lists the neighbours counter-clockwise by the direction
- * of the minimum-image vector from the particle, starting at the +x axis
+ * Row order: first the other particles at the particle's own site, by index;
+ * then the neighbouring sites counter-clockwise by the direction of the
+ * minimum-image vector from the particle, starting at the +x axis
  * (directions with dy > 0, or dy = 0 and dx > 0, come first; within a half
- * plane by the sign of the cross product).  Two neighbours never share a
- * direction, so the order is exact and unique.
+ * plane by the sign of the cross product), the particles of one site by
+ * index.  Two neighbouring sites never share a direction, so the order is
+ * exact and unique.
  *
  * The bisector test works on exact integers: for the bisector of 0 and d,
  * x(t) = d/2 + t (-d_y, d_x), every other particle q bounds t by the linear
@@ -82,7 +88,8 @@ static int bisector_open(int64_t dx, int64_t dy, const int64_t* qx, const int64_
                          int32_t skip, bound_t* lo, bound_t* hi) {
   bound_t l = {0, 1, 0}, h = {0, 1, 0};
   for (int32_t s = 0; s < m; ++s) {
-    if (s == skip) continue;
+    if (s == skip || (qx[s] == dx && qy[s] == dy)) continue; /* d itself, or its site */
+    if (qx[s] == 0 && qy[s] == 0) continue;                   /* the particle's own site */
     const int64_t num = qx[s] * qx[s] + qy[s] * qy[s] - (dx * qx[s] + dy * qy[s]);
     const int64_t den = 2 * (-dy * qx[s] + dx * qy[s]);
     if (den == 0) {
@@ -132,9 +139,20 @@ static int cell_of(const int64_t* qx, const int64_t* qy, const int32_t* id, int3
   int64_t* ry = rx + dmax;
   int32_t cnt = 0;
   int rc = ORC_OK;
-  for (int32_t s = 0; s < m && rc == ORC_OK; ++s)
-    if (qx[s] == 0 && qy[s] == 0) rc = ORC_E_RANGE;
+  /* the other particles at the particle's own site, by index (candidates come
+   * in ascending index) */
+  int32_t own = 0;
+  for (int32_t s = 0; s < m; ++s)
+    if (qx[s] == 0 && qy[s] == 0) {
+      if (own == dmax) {
+        rc = ORC_E_CAPACITY;
+        break;
+      }
+      row[own++] = id[s];
+    }
+  cnt = own;
   for (int32_t s = 0; s < m && rc == ORC_OK; ++s) {
+    if (qx[s] == 0 && qy[s] == 0) continue;
     bound_t lo, hi;
     if (!bisector_open(qx[s], qy[s], qx, qy, m, s, &lo, &hi)) continue;
     if (!lo.set || !hi.set || !vertex_within(qx[s], qy[s], lo, r2) ||
@@ -146,9 +164,10 @@ static int cell_of(const int64_t* qx, const int64_t* qy, const int32_t* id, int3
       rc = ORC_E_CAPACITY;
       break;
     }
-    /* insertion into the counter-clockwise order */
+    /* insertion into the counter-clockwise order (after the own site's
+     * particles, and after the particles of the same site met before) */
     int32_t pos = cnt++;
-    while (pos > 0 && ccw_before(qx[s], qy[s], rx[pos - 1], ry[pos - 1])) {
+    while (pos > own && ccw_before(qx[s], qy[s], rx[pos - 1], ry[pos - 1])) {
       row[pos] = row[pos - 1];
       rx[pos] = rx[pos - 1];
       ry[pos] = ry[pos - 1];
@@ -159,8 +178,12 @@ static int cell_of(const int64_t* qx, const int64_t* qy, const int32_t* id, int3
     ry[pos] = qy[s];
   }
   free(rx);
-  /* a bounded cell has at least three edges (with none, the cell is the whole plane) */
-  if (rc == ORC_OK && cnt < 3) rc = ORC_E_RANGE;
+  /* a bounded cell has at least three edges (with none, the cell is the whole
+   * plane); sites count once however many particles they hold */
+  int32_t sites = 0;
+  for (int32_t u = own; u < cnt; ++u)
+    if (u == own || rx[u] != rx[u - 1] || ry[u] != ry[u - 1]) ++sites;
+  if (rc == ORC_OK && sites < 3) rc = ORC_E_RANGE;
   *deg = cnt;
   return rc;
 }
@@ -375,12 +398,18 @@ static int64_t ring_pos(const int64_t* off, const int32_t* idx, int32_t c, int32
 }
 
 int orc_voronoi_forces(const double* x, const double* y, int32_t n, double box, const int64_t* off,
-                       const int32_t* idx, double ka, double kp, double a0, double p0, double* area,
-                       double* perim, double* fx, double* fy, double* energy, double* hx, double* hy,
-                       double* vfx, double* vfy) {
+                       const int32_t* idx, double ka, double kp, double a0, double p0, const int32_t* rows,
+                       int32_t nrows, double* area, double* perim, double* fx, double* fy, double* energy,
+                       double* hx, double* hy, double* vfx, double* vfy) {
   if (n < 3 || !(box > 0.0)) return ORC_E_INVAL;
-  for (int32_t i = 0; i < n; ++i)
-    if (off[i + 1] - off[i] < 3) return ORC_E_INVAL;
+  /* rows == NULL: every particle (every row must hold a cell).  Otherwise
+   * only the forces of particles rows[0..nrows) (output index r), from the
+   * rows given (a particle with fewer than three entries has no cell: its
+   * area and perimeter are NaN, and so is any force that needs them). */
+  if (!rows)
+    for (int32_t i = 0; i < n; ++i)
+      if (off[i + 1] - off[i] < 3) return ORC_E_INVAL;
+  const int32_t count = rows ? nrows : n;
   const int64_t nnz = off[n];
   double* A = (double*)malloc(sizeof(double) * (size_t)n);
   double* P = (double*)malloc(sizeof(double) * (size_t)n);
@@ -397,6 +426,18 @@ int orc_voronoi_forces(const double* x, const double* y, int32_t n, double box, 
   for (int32_t i = 0; i < n; ++i) {
     const int64_t b = off[i], m = off[i + 1] - off[i];
     double a2 = 0.0, per = 0.0;
+    if (m < 3) {
+      A[i] = P[i] = NAN;
+      continue;
+    }
+    /* the model gives each particle its own cell: coincident particles have none */
+    for (int64_t t = 0; t < m; ++t) {
+      const int32_t j = idx[b + t];
+      if (x[j] == x[i] && y[j] == y[i]) {
+#pragma omp atomic write
+        status = ORC_E_RANGE;
+      }
+    }
     for (int64_t t = 0; t < m; ++t) {
       const int32_t j = idx[b + t], k = idx[b + (t + 1) % m];
       const v2 rij = {fmin_image(x[j] - x[i], box), fmin_image(y[j] - y[i], box)};
@@ -411,9 +452,16 @@ int orc_voronoi_forces(const double* x, const double* y, int32_t n, double box, 
     A[i] = 0.5 * a2;
     P[i] = per;
   }
+  if (status != ORC_OK) { /* coincident particles: no model */
+    free(A);
+    free(P);
+    free(H);
+    return status;
+  }
   /* pass 2: dE/dh of every vertex (three cells, Eq. 5) and the forces (Eq. 9) */
 #pragma omp parallel for schedule(static)
-  for (int32_t i = 0; i < n; ++i) {
+  for (int32_t r = 0; r < count; ++r) {
+    const int32_t i = rows ? rows[r] : r;
     const int64_t b = off[i], m = off[i + 1] - off[i];
     v2 F = {0.0, 0.0};
     for (int64_t t = 0; t < m; ++t) {
@@ -427,7 +475,7 @@ int orc_voronoi_forces(const double* x, const double* y, int32_t n, double box, 
        * of (j, mm, k), mm the neighbour of j just before k */
       const int64_t sk = ring_pos(off, idx, j, k);
       const int64_t mj = off[j + 1] - off[j];
-      if (sk < 0 || idx[off[j] + ((sk - off[j]) + 1) % mj] != i) {
+      if (sk < 0 || mj < 3 || idx[off[j] + ((sk - off[j]) + 1) % mj] != i) {
 #pragma omp atomic write
         status = ORC_E_INVAL; /* the rings are not one triangulation */
         continue;
@@ -448,12 +496,12 @@ int orc_voronoi_forces(const double* x, const double* y, int32_t n, double box, 
       F.x -= g.x * J[0][0] + g.y * J[1][0];
       F.y -= g.x * J[0][1] + g.y * J[1][1];
     }
-    if (fx) fx[i] = F.x;
-    if (fy) fy[i] = F.y;
+    if (fx) fx[r] = F.x;
+    if (fy) fy[r] = F.y;
   }
   if (area) memcpy(area, A, sizeof(double) * (size_t)n);
   if (perim) memcpy(perim, P, sizeof(double) * (size_t)n);
-  if (energy) {
+  if (energy && !rows) {
     double e = 0.0;
     for (int32_t i = 0; i < n; ++i) e += ka * (A[i] - a0) * (A[i] - a0) + kp * (P[i] - p0) * (P[i] - p0);
     *energy = e;

@@ -12,4 +12,4 @@ from .nm import (NM_E_CAPACITY, NM_E_DEVICE, NM_E_INVAL, NM_E_NOMEM, NM_E_RANGE,
                  Workspace, align_step, bin_step, build_cells, check, knn, knn_align, knn_fov, knn_layout, make_params,
                  metric_list,
                  polar_order, server_job_bytes, step, suggest_cell_w, tune_grid, voronoi, voronoi_check,
-                 voronoi_update)
+                 voronoi_forces, voronoi_update)

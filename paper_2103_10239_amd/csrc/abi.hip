@@ -274,6 +274,21 @@ int nm_voronoi_update(const nm_grid* g, void* ws, const int32_t* x, const int32_
                                          as_stream(stream)));
 }
 
+int nm_voronoi_forces(const int32_t* x, const int32_t* y, int32_t n, int32_t box, int32_t dmax,
+                      const int32_t* ring, const int32_t* deg, const nm_vm_params* vp, double* area,
+                      double* perim, double* fx, double* fy, double* energy, double* vertex,
+                      void* ws_err, void* stream) {
+  if (x == nullptr || y == nullptr || ring == nullptr || deg == nullptr || vp == nullptr ||
+      area == nullptr || perim == nullptr || fx == nullptr || fy == nullptr)
+    return NM_E_INVAL;
+  if (n < 3 || n > kMaxParticles || !is_pow2(box) || box < 8 || box > (1 << 20)) return NM_E_INVAL;
+  if (dmax < 3 || dmax > NM_VORONOI_MAX_DEG) return NM_E_INVAL;
+  if (!isfinite(vp->ka) || !isfinite(vp->kp) || !isfinite(vp->a0) || !isfinite(vp->p0)) return NM_E_INVAL;
+  return status_of(launch_voronoi_forces(x, y, n, ilog2(box), dmax, ring, deg, vp, area, perim, fx, fy,
+                                         energy, vertex, static_cast<WsHeader*>(ws_err),
+                                         as_stream(stream)));
+}
+
 int nm_polar_order(const float* theta, int32_t n, double* sums, void* stream) {
   if (theta == nullptr || sums == nullptr || n < 1) return NM_E_INVAL;
   return status_of(launch_polar_order(theta, n, sums, as_stream(stream)));

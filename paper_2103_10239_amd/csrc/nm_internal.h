@@ -606,6 +606,10 @@ hipError_t launch_knn_fov_strips(const DevWs& w, int block, const float* theta, 
                                  int32_t* nbr, hipStream_t s);
 hipError_t launch_polar_order(const float* theta, int32_t n, double* sums, hipStream_t s);
 hipError_t launch_voronoi(const DevWs& w, int dmax, int32_t* ring, int32_t* deg, hipStream_t s);
+hipError_t launch_voronoi_forces(const int32_t* x, const int32_t* y, int32_t n, int log2_box, int dmax,
+                                 const int32_t* ring, const int32_t* deg, const nm_vm_params* p,
+                                 double* area, double* perim, double* fx, double* fy, double* energy,
+                                 double* vert, WsHeader* err, hipStream_t s);
 hipError_t launch_voronoi_check(const DevWs& w, const int32_t* x, const int32_t* y, int dmax,
                                 const int32_t* ring, const int32_t* deg, uint8_t* stale, int32_t* nfail,
                                 hipStream_t s);

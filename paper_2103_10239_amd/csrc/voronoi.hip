@@ -37,6 +37,13 @@
 // histories) are listed for the wide one (32-bit offsets, D in 128-bit
 // integers, 64 edges, rings out to the box).  Rows whose cell reaches L/8
 // or more from its particle are outside the lists' domain: NM_E_RANGE.
+//
+// Coincident particles share one site (the diagram is that of the distinct
+// positions): a candidate at the particle's own position is skipped, and a
+// candidate at the position of a clipping particle never cuts (it lies on
+// that particle's bisector).  The row then lists the other particles of the
+// own site, then every particle of each neighbouring site, by index within
+// a site (found in the site's grid cell).
 #include "nm_internal.h"
 
 namespace nm {
@@ -268,11 +275,7 @@ __device__ int build_cell(const DevWs& w, Cell<CAP, BLK, WIDE>& cell, int s, int
         const int4 e = w.sorted[t];
         const int ex = wrap_axis(e.x - px, sh);
         const int ey = wrap_axis(e.y - py, sh);
-        if (ex == 0 && ey == 0) {  // coincident particles: no bisector
-          set_err(w.hdr, NM_E_RANGE);
-          outcome = kCellFail;
-          break;
-        }
+        if (ex == 0 && ey == 0) continue;  // the particle's own site
         const double d2 = static_cast<double>(ex) * ex + static_cast<double>(ey) * ey;
         if (d2 >= bound) continue;
         const int rc = cell.clip(ex, ey, e.z);
@@ -308,12 +311,35 @@ __device__ int build_cell(const DevWs& w, Cell<CAP, BLK, WIDE>& cell, int s, int
   return kCellDone;
 }
 
-// Write the cell's row: drop clipping particles whose edge has zero length,
-// list the rest counter-clockwise from the +x axis.
+// Append the particles at position (sx, sy), in ascending index, except
+// `skip`, to row[*cnt ..] (each found by a scan of the position's grid cell).
+__device__ __forceinline__ void site_members(const DevWs& w, int sx, int sy, int skip, int total,
+                                             int32_t* __restrict__ row, int dmax, int& cnt) {
+  const int64_t c = static_cast<int64_t>(sy >> w.log2_w) * w.G + (sx >> w.log2_w);
+  const int beg = w.start[c];
+  const int end = min(w.start[c + 1], total);
+  int last = -1;
+  for (;;) {
+    int best = 0x7FFFFFFF;
+    for (int t = beg; t < end; ++t) {
+      const int4 e = w.sorted[t];
+      if (e.x == sx && e.y == sy && e.z > last && e.z < best && e.z != skip) best = e.z;
+    }
+    if (best == 0x7FFFFFFF) break;
+    if (cnt < dmax) row[cnt] = best;
+    ++cnt;
+    last = best;
+  }
+}
+
+// Write the cell's row: the other particles of the own site, then the
+// clipping particles whose edge has positive length, counter-clockwise from
+// the +x axis, each expanded to all particles of its site.
 template <int CAP, int BLK, bool WIDE>
-__device__ void write_row(const DevWs& w, const Cell<CAP, BLK, WIDE>& cell, int who, int dmax,
-                          int32_t* __restrict__ ring, int32_t* __restrict__ deg) {
+__device__ void write_row(const DevWs& w, const Cell<CAP, BLK, WIDE>& cell, int who, int px, int py,
+                          int total, int dmax, int32_t* __restrict__ ring, int32_t* __restrict__ deg) {
   const int m = cell.m;
+  const int mask = w.box - 1;
   // start: the clipping particle with the smallest angle from +x
   int t0 = 0, bx0, by0;
   cell.get(0, bx0, by0);
@@ -328,17 +354,16 @@ __device__ void write_row(const DevWs& w, const Cell<CAP, BLK, WIDE>& cell, int 
   }
   int32_t* row = ring + static_cast<long long>(who) * dmax;
   int cnt = 0;
-  int px, py, cx, cy, nx, ny;
-  cell.get((t0 + m - 1) % m, px, py);
+  site_members(w, px, py, who, total, row, dmax, cnt);
+  int qx, qy, cx, cy, nx, ny;
+  cell.get((t0 + m - 1) % m, qx, qy);
   cell.get(t0, cx, cy);
   for (int u = 0; u < m; ++u) {
     cell.get((t0 + u + 1) % m, nx, ny);
-    if (cell.inc(px, py, cx, cy, nx, ny) != 0) {
-      if (cnt < dmax) row[cnt] = cell.id[cell.slot((t0 + u) % m)];
-      ++cnt;
-    }
-    px = cx;
-    py = cy;
+    if (cell.inc(qx, qy, cx, cy, nx, ny) != 0)
+      site_members(w, (px + cx) & mask, (py + cy) & mask, -1, total, row, dmax, cnt);
+    qx = cx;
+    qy = cy;
     cx = nx;
     cy = ny;
   }
@@ -392,7 +417,7 @@ __global__ __launch_bounds__(kVnBlock) void k_voronoi(DevWs w, int dmax, int32_t
     const int4 e = w.sorted[s];
     Cell<kVnCap, kVnBlock, false> cell{sxy + threadIdx.x, nullptr, sid + threadIdx.x, 0, 0};
     const int rc = build_cell(w, cell, s, e.x, e.y, total);
-    if (rc == kCellDone) write_row(w, cell, e.z, dmax, ring, deg);
+    if (rc == kCellDone) write_row(w, cell, e.z, e.x, e.y, total, dmax, ring, deg);
     wide = rc == kCellWide;
   }
   list_wide(w, wide, s);
@@ -411,7 +436,7 @@ __global__ __launch_bounds__(kVwBlock) void k_voronoi_wide(DevWs w, int dmax, in
     const int s = w.vlist[k];
     const int4 e = w.sorted[s];
     Cell<kVwCap, kVwBlock, true> cell{sx + threadIdx.x, sy + threadIdx.x, sid + threadIdx.x, 0, 0};
-    if (build_cell(w, cell, s, e.x, e.y, total) == kCellDone) write_row(w, cell, e.z, dmax, ring, deg);
+    if (build_cell(w, cell, s, e.x, e.y, total) == kCellDone) write_row(w, cell, e.z, e.x, e.y, total, dmax, ring, deg);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -436,7 +461,10 @@ __global__ __launch_bounds__(kVwBlock) void k_voronoi_wide(DevWs w, int dmax, in
 //   - a_t's row holds a_{t+1} directly followed by i (the three rows agree
 //     on the triangle),
 //   - a_{t+2} lies strictly outside the circle through i, a_t, a_{t+1}
-//     (the edge i - a_{t+1} is locally Delaunay, strictly).
+//     (the edge i - a_{t+1} is locally Delaunay, strictly),
+// where a_t are the row's sites (runs of particles at one position, the
+// own site's particles left out), and every particle listed at the own site
+// lists this one back.
 // and, over all rows, the cross products a_t x a_{t+1} sum to exactly 6 L^2
 // (each triangle is counted from its three corners: the triangles cover the
 // box once).  Then the rows form a triangulation of the torus that is
@@ -458,9 +486,59 @@ __global__ __launch_bounds__(kBlock) void k_vor_clear(WsHeader* hdr, uint8_t* __
   }
 }
 
-__device__ __forceinline__ bool row_holds_then(const int32_t* __restrict__ row, int m, int a, int b) {
-  for (int t = 0; t < m; ++t)
-    if (row[t] == a) return row[t + 1 < m ? t + 1 : 0] == b;
+// Rows hold sites: a prefix of particles at the row's own position, then
+// runs of particles sharing a position.  These helpers walk a row site by
+// site; entries are valid indices (checked before).
+struct RowView {
+  const int32_t* row;
+  int m;
+  int own;  // length of the own-site prefix
+  const int32_t* x;
+  const int32_t* y;
+  __device__ __forceinline__ bool same(int t, int u) const {
+    const int a = row[t], b = row[u];
+    return x[a] == x[b] && y[a] == y[b];
+  }
+  // the first entry of the site after the one entry t belongs to (cyclic over
+  // the site part of the row)
+  __device__ __forceinline__ int next_site(int t) const {
+    int u = t;
+    for (int guard = 0; guard < m; ++guard) {
+      u = u + 1 < m ? u + 1 : own;
+      if (!same(u, t)) return u;
+    }
+    return t;
+  }
+  // the first entry of the site that entry t belongs to
+  __device__ __forceinline__ int site_start(int t) const {
+    int u = t;
+    for (int guard = 0; guard < m; ++guard) {
+      const int v = u > own ? u - 1 : m - 1;
+      if (!same(v, t)) return u;
+      u = v;
+    }
+    return t;
+  }
+};
+
+__device__ __forceinline__ RowView row_view(const int32_t* row, int m, int self, const int32_t* x,
+                                            const int32_t* y) {
+  RowView r{row, m, 0, x, y};
+  while (r.own < m && x[row[r.own]] == x[self] && y[row[r.own]] == y[self]) ++r.own;
+  return r;
+}
+
+// Row `rv` (of particle a) holds the site at (bxp, byp) followed directly by
+// the site at (ixp, iyp).
+__device__ __forceinline__ bool row_holds_then(const RowView& rv, int bxp, int byp, int ixp, int iyp) {
+  for (int t = rv.own; t < rv.m; ++t) {
+    const int j = rv.row[t];
+    if (rv.x[j] == bxp && rv.y[j] == byp) {
+      const int u = rv.next_site(t);
+      const int k = rv.row[u];
+      return rv.x[k] == ixp && rv.y[k] == iyp;
+    }
+  }
   return false;
 }
 
@@ -484,20 +562,43 @@ __global__ __launch_bounds__(kBlock) void k_vor_check(const int32_t* __restrict_
     }
     if (!fail) {
       const int xi = x[i], yi = y[i];
+      const RowView rv = row_view(row, m, i, x, y);
+      // the own site counts once in the area total: from its lowest index;
+      // and every particle listed at the own site lists this one back
+      bool lowest = true;
+      for (int t = 0; t < rv.own && !fail; ++t) {
+        const int p = row[t];
+        lowest = lowest && p > i;
+        const int mp = deg[p];
+        bool back = false;
+        if (mp >= 1 && mp <= dmax) {
+          const int32_t* rowp = ring + static_cast<long long>(p) * dmax;
+          for (int u = 0; u < mp; ++u) {
+            const int q = rowp[u];
+            if (static_cast<unsigned>(q) >= static_cast<unsigned>(n) || x[q] != xi || y[q] != yi) break;
+            back = back || q == i;
+          }
+        }
+        if (!back) fail = true;
+      }
+      if (m - rv.own < 3) fail = true;
       auto off = [&](int j, int& ox, int& oy) {
         ox = wrap_axis(x[j] - xi, sh);
         oy = wrap_axis(y[j] - yi, sh);
       };
-      int a = row[0], b = row[1];
+      const int t0 = fail ? 0 : rv.site_start(rv.own);
+      int ta = t0, tb = fail ? 0 : rv.next_site(t0);
       int ax, ay, bx, by;
-      off(a, ax, ay);
-      off(b, bx, by);
-      int wraps = 0;
-      for (int t = 0; t < m && !fail; ++t) {
-        const int c = row[t + 2 < m ? t + 2 : t + 2 - m];
+      if (!fail) {
+        off(row[ta], ax, ay);
+        off(row[tb], bx, by);
+      }
+      int wraps = 0, nsites = 0;
+      for (int guard = 0; guard < m && !fail; ++guard) {
+        const int tc = rv.next_site(tb);
         int cx, cy;
-        off(c, cx, cy);
-        if (abs(ax) >= quarter || abs(ay) >= quarter) {
+        off(row[tc], cx, cy);
+        if (abs(ax) >= quarter || abs(ay) >= quarter || (ax == 0 && ay == 0)) {
           fail = true;
           break;
         }
@@ -506,17 +607,28 @@ __global__ __launch_bounds__(kBlock) void k_vor_check(const int32_t* __restrict_
         area2 += cr;
         if (!ccw_before(ax, ay, bx, by)) ++wraps;
         if (inc_sign_w(ax, ay, bx, by, cx, cy) <= 0) fail = true;
+        const int a = row[ta];
         const int ma = deg[a];
-        if (ma < 3 || ma > dmax || !row_holds_then(ring + static_cast<long long>(a) * dmax, ma, b, i))
+        if (ma < 3 || ma > dmax) {
           fail = true;
-        a = b;
+        } else {
+          const int32_t* rowa = ring + static_cast<long long>(a) * dmax;
+          bool okidx = true;
+          for (int u = 0; u < ma; ++u) okidx = okidx && static_cast<unsigned>(rowa[u]) < static_cast<unsigned>(n);
+          if (!okidx || !row_holds_then(row_view(rowa, ma, a, x, y), x[row[tb]], y[row[tb]], xi, yi))
+            fail = true;
+        }
+        ++nsites;
+        ta = tb;
         ax = bx;
         ay = by;
-        b = c;
+        tb = tc;
         bx = cx;
         by = cy;
+        if (ta == t0) break;
       }
-      if (wraps != 1) fail = true;
+      if (wraps != 1 || nsites < 3) fail = true;
+      if (!lowest) area2 = 0;
     }
     if (fail) {
       stale[i] = 1;
@@ -536,8 +648,8 @@ __global__ __launch_bounds__(kBlock) void k_vor_check(const int32_t* __restrict_
   if ((threadIdx.x & 63) == 0 && area2 != 0) atomicAdd(&hdr->varea2, static_cast<unsigned long long>(area2));
 }
 
-// Rows that passed: rotate to start at the +x axis again (positions moved).
-// Stale rows: list the particle's slot for recomputation.
+// Rows that passed: rotate the site part to start at the +x axis again
+// (positions moved).  Stale rows: list the particle's slot for recomputation.
 __global__ __launch_bounds__(kBlock) void k_vor_sweep(DevWs w, const int32_t* __restrict__ x,
                                                       const int32_t* __restrict__ y, int dmax,
                                                       int32_t* __restrict__ ring,
@@ -554,10 +666,12 @@ __global__ __launch_bounds__(kBlock) void k_vor_sweep(DevWs w, const int32_t* __
       const int sh = 32 - w.log2_box;
       const int m = deg[i];
       int32_t* row = ring + static_cast<long long>(i) * dmax;
+      const RowView rv = row_view(row, m, i, x, y);
       const int xi = x[i], yi = y[i];
-      int t0 = 0;
-      int bx = wrap_axis(x[row[0]] - xi, sh), by = wrap_axis(y[row[0]] - yi, sh);
-      for (int t = 1; t < m; ++t) {
+      // the first entry of the site with the smallest angle
+      int t0 = rv.own;
+      int bx = wrap_axis(x[row[t0]] - xi, sh), by = wrap_axis(y[row[t0]] - yi, sh);
+      for (int t = rv.own + 1; t < m; ++t) {
         const int j = row[t];
         const int ox = wrap_axis(x[j] - xi, sh), oy = wrap_axis(y[j] - yi, sh);
         if (ccw_before(ox, oy, bx, by)) {
@@ -566,7 +680,8 @@ __global__ __launch_bounds__(kBlock) void k_vor_sweep(DevWs w, const int32_t* __
           by = oy;
         }
       }
-      if (t0 != 0) {  // rotate left by t0: three reversals
+      t0 = rv.site_start(t0);
+      if (t0 != rv.own) {  // rotate the site part left by t0 - own: three reversals
         auto rev = [&](int lo, int hi) {
           for (--hi; lo < hi; ++lo, --hi) {
             const int v = row[lo];
@@ -574,9 +689,9 @@ __global__ __launch_bounds__(kBlock) void k_vor_sweep(DevWs w, const int32_t* __
             row[hi] = v;
           }
         };
-        rev(0, t0);
+        rev(rv.own, t0);
         rev(t0, m);
-        rev(0, m);
+        rev(rv.own, m);
       }
     }
   }

@@ -45,6 +45,12 @@ class Params(ctypes.Structure):
                 ("seed", _c_u64), ("sys_id", _c_u32), ("variant", _c_u32)]
 
 
+class VmParams(ctypes.Structure):
+    """nm_vm_params: the moduli and preferred area / perimeter of Eq. (3)."""
+    _fields_ = [("ka", ctypes.c_double), ("kp", ctypes.c_double), ("a0", ctypes.c_double),
+                ("p0", ctypes.c_double)]
+
+
 class BatchIO(ctypes.Structure):
     """nm_batch_io: concatenated double-buffered state and the list output."""
     _fields_ = [("x", _vp * 2), ("y", _vp * 2), ("theta", _vp * 2), ("nbr", _vp)]
@@ -100,6 +106,8 @@ def lib():
     L.nm_knn_fov.argtypes = [gp, _vp, _c_i32, _vp, _c_i32, _vp, _vp]
     L.nm_knn_layout.argtypes = [gp, _c_i32, ctypes.POINTER(_c_i32)]
     L.nm_voronoi.argtypes = [gp, _vp, _c_i32, _vp, _vp, _vp]
+    L.nm_voronoi_forces.argtypes = [_vp, _vp, _c_i32, _c_i32, _c_i32, _vp, _vp, ctypes.POINTER(VmParams)] + \
+        [_vp] * 8
     L.nm_step_noalloc.argtypes = [gp, _vp, _vp, _vp, _c_i32, pp, _c_u64, _vp, _vp, _vp, _vp, _vp, _vp]
     L.nm_voronoi_check.argtypes = [gp, _vp, _vp, _vp, _c_i32, _vp, _vp, _vp, _vp, _vp]
     L.nm_voronoi_update.argtypes = [gp, _vp, _vp, _vp, _c_i32, _vp, _vp, _vp, _vp, _vp]
@@ -126,6 +134,7 @@ def lib():
               "nm_server_stats"):
         getattr(L, f).restype = ctypes.c_int
     for f in ("nm_workspace_init", "nm_build_cells", "nm_knn", "nm_knn_layout", "nm_voronoi", "nm_step_noalloc",
+              "nm_voronoi_forces",
               "nm_voronoi_check", "nm_voronoi_update", "nm_metric_list", "nm_align_step",
               "nm_step", "nm_bin_step", "nm_knn_align", "nm_check", "nm_tune_grid", "nm_batch_plan", "nm_batch_bind",
               "nm_batch_step", "nm_batch_tune", "nm_batch_system", "nm_batch_check"):
@@ -234,6 +243,26 @@ def voronoi_update(ws: Workspace, x, y, ring, deg, stale: torch.Tensor | None = 
                                 _dev(deg, torch.int32, n, "deg"), _dev(stale, torch.uint8, n, "stale"),
                                 _dev(nfail, torch.int32, 1, "nfail"), _stream(ws.device)), "voronoi_update")
     return nfail
+
+
+def voronoi_forces(x, y, box: int, ring, deg, ka: float, kp: float, a0: float, p0: float,
+                   energy: bool = True, vertices: bool = False, ws: Workspace | None = None) -> dict:
+    """Voronoi model (Sec. V) on the rows of voronoi(): device tensors area, perim,
+    fx, fy [n] (fp64), energy [1] and, with vertices, [n, dmax, 4] (hx, hy, fx, fy)."""
+    n = int(x.numel())
+    dmax = int(ring.shape[1])
+    dev = x.device
+    out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("area", "perim", "fx", "fy")}
+    out["energy"] = torch.empty(1, dtype=torch.float64, device=dev) if energy else None
+    out["vertex"] = torch.empty((n, dmax, 4), dtype=torch.float64, device=dev) if vertices else None
+    vp = VmParams(ka, kp, a0, p0)
+    ptr = lambda t: t.data_ptr() if t is not None else None
+    _ok(lib().nm_voronoi_forces(_dev(x, torch.int32, n, "x"), _dev(y, torch.int32, n, "y"), n, box, dmax,
+                                _dev(ring, torch.int32, n * dmax, "ring"), _dev(deg, torch.int32, n, "deg"),
+                                ctypes.byref(vp), ptr(out["area"]), ptr(out["perim"]), ptr(out["fx"]),
+                                ptr(out["fy"]), ptr(out["energy"]), ptr(out["vertex"]),
+                                ws.ptr if ws is not None else None, _stream(dev)), "voronoi_forces")
+    return out
 
 
 KNN_LAYOUT_FIELDS = ("kernel", "tw", "th", "hx", "hy", "bfix", "wide", "bmax", "ntx", "nty")

@@ -131,3 +131,33 @@ def test_batch_plan_is_host_only():
     L_.nm_batch_destroy(h)
     bad = (ctypes.c_int32 * 2)(300, 7)  # a system with n < k + 1
     assert L_.nm_batch_plan(2, bad, L, 7, ctypes.byref(p), None, ctypes.byref(h), ctypes.byref(nbytes)) == nm.NM_E_INVAL
+
+
+def test_voronoi_and_noalloc_entry_points_check_arguments_on_the_host():
+    # every call below fails validation before touching a device (and exercises
+    # the binding's argument lists)
+    lib = nm.lib()
+    fake = ctypes.c_void_p(256)
+    g = nm.Grid(1024, 1 << 20, 1 << 15, 0)
+    assert lib.nm_voronoi(ctypes.byref(g), fake, 2, fake, fake, None) == nm.NM_E_INVAL  # dmax < 3
+    assert lib.nm_voronoi(ctypes.byref(g), fake, 65, fake, fake, None) == nm.NM_E_INVAL
+    assert lib.nm_voronoi(ctypes.byref(g), None, 16, fake, fake, None) == nm.NM_E_INVAL
+    assert lib.nm_voronoi_check(ctypes.byref(g), fake, fake, fake, 16, fake, fake, None, None,
+                                None) == nm.NM_E_INVAL  # stale missing
+    assert lib.nm_voronoi_update(ctypes.byref(g), fake, None, fake, 16, fake, fake, fake, None,
+                                 None) == nm.NM_E_INVAL
+    vp = nm.VmParams(1.0, 1.0, 1.0, float("nan"))
+    assert lib.nm_voronoi_forces(fake, fake, 1024, 1 << 20, 16, fake, fake, ctypes.byref(vp), fake, fake,
+                                 fake, fake, None, None, None, None) == nm.NM_E_INVAL  # non-finite P0
+    vp = nm.VmParams(1.0, 1.0, 1.0, 1.0)
+    assert lib.nm_voronoi_forces(fake, fake, 1024, 1000, 16, fake, fake, ctypes.byref(vp), fake, fake,
+                                 fake, fake, None, None, None, None) == nm.NM_E_INVAL  # box not 2^m
+    p = nm.make_params(1 << 20)
+    big = nm.Grid(1 << 20, 1 << 20, 1024, 0)
+    assert lib.nm_step_noalloc(ctypes.byref(big), fake, fake, fake, 7, ctypes.byref(p), 0, fake, fake, fake,
+                               fake, None, None) == nm.NM_E_NOMEM  # beyond the device array
+    assert lib.nm_step_noalloc(ctypes.byref(nm.Grid(1, 1 << 20, 1024, 0)), fake, fake, fake, 7,
+                               ctypes.byref(p), 0, fake, fake, fake, fake, None, None) == nm.NM_E_INVAL
+    out = (ctypes.c_int32 * 10)()
+    assert lib.nm_knn_layout(ctypes.byref(g), 0, out) == nm.NM_E_INVAL
+    assert lib.nm_knn_layout(ctypes.byref(g), 7, out) == nm.NM_OK

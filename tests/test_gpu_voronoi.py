@@ -108,11 +108,23 @@ def test_voronoi_centred_lattice_and_small_box():
     assert st == 0 and _rows_of(ring, deg) == _oracle_rows(x // s, y // s, 1 << 12)
 
 
+@pytest.mark.parametrize("case", ["pairs", "lattice_sites"])
+def test_voronoi_coincident_particles_share_a_site(case):
+    if case == "pairs":  # a few coincident pairs and a triple in a uniform set
+        n, box, w = 4097, 1 << 16, 1024
+        x, y, _ = workloads.uniform(n, box=box, seed_pos=31)
+        for a, b in ((9, 5), (40, 5), (100, 3000), (7, 8)):
+            x[a], y[a] = x[b], y[b]
+    else:  # 4097 particles on the sites of a 32 x 32 lattice (degenerate too)
+        n, box, w = 4097, 1 << 16, 2048
+        x, y, _ = workloads.uniform(n, box=box, seed_pos=32)
+        x, y = (x // 2048) * 2048, (y // 2048) * 2048
+    ring, deg, st, _ = _gpu_rows(x, y, box, w, dmax=64)
+    assert st == 0
+    assert _rows_of(ring, deg) == _oracle_rows(x, y, box)
+
+
 def test_voronoi_errors():
-    x, y, _ = workloads.uniform(500, box=1 << 16)
-    x[5], y[5] = x[9], y[9]  # coincident
-    _, _, st, _ = _gpu_rows(x, y, 1 << 16, 1024)
-    assert st == nm.NM_E_RANGE
     x, y, _ = workloads.uniform(6)  # cells beyond L/8
     _, _, st, _ = _gpu_rows(x, y, workloads.BOX, 1 << 17)
     assert st == nm.NM_E_RANGE
@@ -153,11 +165,20 @@ def _moved(x, y, box, step, seed):
            ((y + rng.integers(-step, step + 1, len(y))) % box).astype(np.int32)
 
 
-@pytest.mark.parametrize("step", [0, 8, 64, 400])
-def test_reuse_test_and_update(step):
+@pytest.mark.parametrize("step,coincide", [(0, None), (8, None), (64, None), (400, None), (0, "stay"),
+                                           (8, "stay"), (0, "change"), (8, "change")])
+def test_reuse_test_and_update(step, coincide):
     n, box, w = 8191, 1 << 16, 1024
     x0, y0, _ = workloads.uniform(n, box=box, seed_pos=71)
     x1, y1 = _moved(x0, y0, box, step, 72)
+    if coincide:  # coincident pairs (and a triple) that stay together
+        for a, b in ((5, 6), (70, 71), (72, 71)):
+            x0[a], y0[a] = x0[b], y0[b]
+            x1[a], y1[a] = x1[b], y1[b]
+    if coincide == "change":  # pairs that form, a pair that parts
+        for a, b in ((300, 301), (4000, 17)):
+            x1[a], y1[a] = x1[b], y1[b]
+        x0[900], y0[900] = x0[901], y0[901]
     ring0, deg0, st, _ = _gpu_rows(x0, y0, box, w)
     assert st == 0
     ref1 = _oracle_rows(x1, y1, box)
@@ -170,7 +191,7 @@ def test_reuse_test_and_update(step):
     stale = stale.cpu().numpy().astype(bool)
     old = _rows_of(ring0, deg0)
     changed = np.array([set(old[i]) != set(ref1[i]) for i in range(n)])
-    if step == 0:
+    if step == 0 and coincide != "change":  # nothing moved: the rows are certified as they are
         assert int(nfail.item()) == 0 and not stale.any()
     if int(nfail.item()) == 0:  # the certificate: no failure, no change
         assert not changed.any() and not stale.any()
@@ -223,3 +244,108 @@ def test_voronoi_vicsek_step_matches_oracle(include_self, variant):
     rx2, ry2, rt2 = oracle.align_step(x, y, th, box, nbr=ring, v0=64, eta=0.3, seed=4, sys_id=1,
                                       include_self=include_self, step=3, variant=variant)
     assert np.array_equal(rx2, rx) and np.array_equal(ry2, ry) and np.array_equal(rt2, rt)
+
+
+def _vm_args(n, box):
+    a_mean = box * box / n
+    return dict(ka=1.0 / a_mean, kp=1.0, a0=0.9 * a_mean, p0=3.7 * np.sqrt(a_mean))
+
+
+def _force_scale(a):
+    return 2 * a["ka"] * a["a0"] * np.sqrt(a["a0"]) + 2 * a["kp"] * a["p0"]
+
+
+@pytest.mark.parametrize("kind,n,box,w", [("uniform", 4097, 1 << 16, 1024), ("uniform", 3001, 1 << 20, 16384),
+                                          ("clustered", 8191, 1 << 20, 4096)])
+def test_voronoi_forces_match_oracle(kind, n, box, w):
+    # Sec. V: areas, perimeters, Eq. (3), vertex forces (Eqs. 5-8), particle
+    # forces (Eqs. 9-19); the oracle works from its own rows
+    x, y, _ = _gen(kind, n, box)
+    ring, deg, st, ws = _gpu_rows(x, y, box, w)
+    assert st == 0
+    off, idx = oracle.voronoi(x, y, box)
+    a = _vm_args(n, box)
+    ref = oracle.voronoi_forces(x, y, box, off, idx, vertices=True, **a)
+    got = nm.voronoi_forces(_dev(x, torch.int32), _dev(y, torch.int32), box, _dev(ring, torch.int32),
+                            _dev(deg, torch.int32), vertices=True, ws=ws, **a)
+    assert nm.check(ws) == 0
+    g = {k: v.cpu().numpy() for k, v in got.items()}
+    scale = _force_scale(a)
+    assert np.allclose(g["area"], ref["area"], rtol=1e-12, atol=0)
+    assert np.allclose(g["perim"], ref["perim"], rtol=1e-12, atol=0)
+    assert abs(g["energy"][0] - ref["energy"]) <= 1e-12 * abs(ref["energy"])
+    assert np.abs(g["fx"] - ref["fx"]).max() <= 1e-9 * scale
+    assert np.abs(g["fy"] - ref["fy"]).max() <= 1e-9 * scale
+    v = g["vertex"]
+    sel = np.arange(ring.shape[1])[None, :] < deg[:, None]
+    for c, key in enumerate(("hx", "hy", "vfx", "vfy")):
+        tol = 1e-9 * (box if c < 2 else scale)
+        assert np.abs(v[..., c][sel] - ref[key]).max() <= tol
+
+
+def test_voronoi_forces_vanish_on_the_centred_lattice():
+    m, box = 16, 1 << 20
+    a = box // m
+    idx = np.arange(m * m)
+    r, c = idx // m, idx % m
+    x = (c * a + (r % 2) * (a // 2)).astype(np.int32)
+    y = (r * a).astype(np.int32)
+    ring, deg, st, ws = _gpu_rows(x, y, box, a)
+    assert st == 0
+    args = dict(ka=1.0, kp=1.0, a0=0.9 * a * a, p0=3.0 * a)
+    got = nm.voronoi_forces(_dev(x, torch.int32), _dev(y, torch.int32), box, _dev(ring, torch.int32),
+                            _dev(deg, torch.int32), ws=ws, **args)
+    assert np.allclose(got["area"].cpu().numpy(), a * a, rtol=1e-13)
+    assert np.allclose(got["perim"].cpu().numpy(), a * (np.sqrt(5.0) + 1.5), rtol=1e-13)
+    scale = 2 * (0.1 * a * a) * a + 2 * abs(a * (np.sqrt(5.0) + 1.5) - 3.0 * a)
+    assert got["fx"].abs().max().item() <= 1e-9 * scale and got["fy"].abs().max().item() <= 1e-9 * scale
+
+
+def test_voronoi_forces_full_size_sampled():
+    n, box = 1 << 20, workloads.BOX
+    x, y, _ = workloads.uniform(n)
+    ring, deg, st, ws = _gpu_rows(x, y, box, 1024)
+    assert st == 0
+    a = _vm_args(n, box)
+    got = nm.voronoi_forces(_dev(x, torch.int32), _dev(y, torch.int32), box, _dev(ring, torch.int32),
+                            _dev(deg, torch.int32), ws=ws, **a)
+    assert nm.check(ws) == 0
+    area = got["area"].cpu().numpy()
+    assert abs(area.sum() - float(box) ** 2) <= 1e-9 * float(box) ** 2  # the cells tile the torus
+    rows = np.unique(np.random.default_rng(8).integers(0, n, 200)).astype(np.int32)
+    # the oracle's own rows for the sampled particles and their neighbours
+    o1, i1 = oracle.voronoi(x, y, box, rows=rows, rho0=4096)
+    nb = np.unique(np.concatenate([rows, i1])).astype(np.int32)
+    o2, i2 = oracle.voronoi(x, y, box, rows=nb, rho0=4096)
+    keep = [np.zeros(0, np.int32)] * n
+    for r, p in enumerate(nb):
+        keep[p] = i2[o2[r]:o2[r + 1]]
+    off = np.zeros(n + 1, np.int64)
+    np.cumsum([len(k) for k in keep], out=off[1:])
+    ref = oracle.voronoi_forces(x, y, box, off, np.concatenate(keep), rows=rows, **a)
+    scale = _force_scale(a)
+    assert np.abs(got["fx"].cpu().numpy()[rows] - ref["fx"]).max() <= 1e-9 * scale
+    assert np.abs(got["fy"].cpu().numpy()[rows] - ref["fy"]).max() <= 1e-9 * scale
+    assert np.allclose(area[nb], ref["area"][nb], rtol=1e-12, atol=0)
+
+
+def test_voronoi_forces_reject_coincident_particles():
+    n, box = 4097, 1 << 16
+    x, y, _ = workloads.uniform(n, box=box, seed_pos=6)
+    x[11], y[11] = x[12], y[12]
+    ring, deg, st, ws = _gpu_rows(x, y, box, 1024)
+    assert st == 0
+    nm.voronoi_forces(_dev(x, torch.int32), _dev(y, torch.int32), box, _dev(ring, torch.int32),
+                      _dev(deg, torch.int32), ws=ws, **_vm_args(n, box))
+    assert nm.check(ws) == nm.NM_E_RANGE
+
+
+def test_voronoi_forces_reject_inconsistent_rows():
+    n, box = 4097, 1 << 16
+    x, y, _ = workloads.uniform(n, box=box, seed_pos=6)
+    assert len(np.unique(x.astype(np.int64) * box + y)) == n  # no coincident particles
+    ring, deg, st, ws = _gpu_rows(x, y, box, 1024)
+    ring[10, :2] = ring[10, 1::-1]  # swap two neighbours: not a triangulation any more
+    nm.voronoi_forces(_dev(x, torch.int32), _dev(y, torch.int32), box, _dev(ring, torch.int32),
+                      _dev(deg, torch.int32), ws=ws, **_vm_args(n, box))
+    assert nm.check(ws) == nm.NM_E_INVAL

@@ -207,12 +207,35 @@ def test_voronoi_local_rows_equal_full_rows():
     assert _rows(o2, i2) == [full[r] for r in rows]
 
 
-def test_voronoi_errors():
-    x, y, _ = workloads.uniform(100)
-    x[5], y[5] = x[9], y[9]  # coincident particles
+def test_coincident_particles_share_a_site():
+    # the diagram of distinct positions: a set with particle 9 moved onto
+    # particle 5 has the rows of the set without particle 9, with 9 listed
+    # beside 5 wherever 5 appears, and 5 and 9 listing each other first
+    n, box = 700, 1 << 20
+    x, y, _ = workloads.uniform(n, box=box, seed_pos=12)
+    x[9], y[9] = x[5], y[5]
+    x[40], y[40] = x[5], y[5]  # a third particle at the same site
+    rows = _rows(*oracle.voronoi(x, y, box))
+    keep = np.array([i for i in range(n) if i not in (9, 40)])
+    sub = _rows(*oracle.voronoi(x[keep], y[keep], box))
+    back = {k: int(i) for k, i in enumerate(keep)}
+    for k, r in enumerate(sub):
+        i = back[k]
+        want = []
+        for j in (back[v] for v in r):
+            want += [5, 9, 40] if j == 5 else [j]
+        if i == 5:
+            want = [9, 40] + want
+        assert rows[i] == want, i
+    assert rows[9] == [5, 40] + rows[5][2:] and rows[40] == [5, 9] + rows[5][2:]
+    # the Voronoi model gives every particle its own cell: coincident ones have none
+    off, idx = oracle.voronoi(x, y, box)
     with pytest.raises(oracle.OracleError) as e:
-        oracle.voronoi(x, y, workloads.BOX)
+        oracle.voronoi_forces(x, y, box, off, idx, 1.0, 1.0, 1.0, 1.0)
     assert e.value.status == oracle.E_RANGE
+
+
+def test_voronoi_errors():
     x, y, _ = workloads.uniform(6)  # cells far larger than L/8
     with pytest.raises(oracle.OracleError) as e:
         oracle.voronoi(x, y, workloads.BOX)
@@ -303,3 +326,22 @@ def test_vertex_forces_are_minus_the_energy_gradient():
             vp[key] = q
             em = energy(vp)
             assert abs(-(ep - em) / (2 * h) - f[name][s]) <= 1e-6 * fmax
+
+
+def test_forces_of_sampled_rows_equal_the_full_forces():
+    n, box = 1500, 1 << 20
+    x, y, _ = workloads.uniform(n, box=box, seed_pos=99)
+    off, idx = oracle.voronoi(x, y, box)
+    a_mean = box * box / n
+    args = (1.0 / a_mean, 1.0, a_mean, 3.8 * np.sqrt(a_mean))
+    full = oracle.voronoi_forces(x, y, box, off, idx, *args)
+    rows = np.array([3, 77, 1499, 640], np.int32)
+    # only the rows the sampled forces need: the particles and their neighbours
+    need = set(rows.tolist())
+    for r in rows:
+        need |= set(idx[off[r]:off[r + 1]].tolist())
+    keep = [idx[off[i]:off[i + 1]] if i in need else np.zeros(0, np.int32) for i in range(n)]
+    off2 = np.zeros(n + 1, np.int64)
+    np.cumsum([len(k) for k in keep], out=off2[1:])
+    part = oracle.voronoi_forces(x, y, box, off2, np.concatenate(keep), *args, rows=rows)
+    assert np.array_equal(part["fx"], full["fx"][rows]) and np.array_equal(part["fy"], full["fy"][rows])
