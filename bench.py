@@ -310,7 +310,7 @@ def bench_variants(args, torch, nm, workloads):
     dev = torch.device("cuda:0")
     x, y, th = workloads.uniform(n)
     out = {"steps": args.variant_steps, "grid": [2048, 4]}
-    sums = torch.empty(2, dtype=torch.float64, device=dev)
+    sums = torch.empty(3, dtype=torch.float64, device=dev)
     order_ms = []
     for name, var in (("eq2_old_heading", 0), ("angular_noise", nm.NM_NOISE_SCALAR),
                       ("new_heading_move", nm.NM_MOVE_NEW_HEADING),

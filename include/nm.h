@@ -304,11 +304,11 @@ int nm_voronoi_forces(const int32_t* x, const int32_t* y, int32_t n, int32_t box
                       void* ws_err, void* stream);
 
 /* Polar order parameter of the headings (Sec. III: the ordered, flocking
- * phase is the one whose headings agree): sums[0] = sum_i cos theta_i,
- * sums[1] = sum_i sin theta_i, in fp64, into the caller's DEVICE double[2];
- * the order parameter is |(sums[0], sums[1])| / n.  theta: device fp32[n],
- * n >= 1.  Enqueued on `stream` without synchronising; the summation order
- * varies between calls (the sums agree to fp64 rounding). */
+ * phase is the one whose headings agree), into the caller's DEVICE
+ * double[3]: sums[0] = sum_i cos theta_i, sums[1] = sum_i sin theta_i (fp64)
+ * and sums[2] = |(sums[0], sums[1])| / n, the order parameter.  theta:
+ * device fp32[n], n >= 1.  Enqueued on `stream` without synchronising; the
+ * summation order varies between calls (the sums agree to fp64 rounding). */
 int nm_polar_order(const float* theta, int32_t n, double* sums, void* stream);
 
 /* One full step of the topological model (Alg. 1) = nm_bin_step followed by

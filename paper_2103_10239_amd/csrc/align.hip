@@ -92,9 +92,14 @@ __global__ __launch_bounds__(kBlock) void k_align(const int32_t* __restrict__ x,
 
 // Polar order parameter: sums of cos and sin of the headings, fp64.  Each
 // workgroup reduces a strided share in registers and LDS, then adds its two
-// sums to the output with one atomic each (vector memory atomics).
+// sums to the output with one atomic each (vector memory atomics); a last
+// one-lane kernel forms |(sum cos, sum sin)| / n.
 __global__ __launch_bounds__(64) void k_order_zero(double* sums) {
   if (threadIdx.x < 2) sums[threadIdx.x] = 0.0;
+}
+
+__global__ void k_order_norm(double* sums, int32_t n) {
+  sums[2] = sqrt(sums[0] * sums[0] + sums[1] * sums[1]) / static_cast<double>(n);
 }
 
 __global__ __launch_bounds__(kBlock) void k_polar_order(const float* __restrict__ theta, int32_t n,
@@ -134,10 +139,12 @@ __global__ __launch_bounds__(kBlock) void k_polar_order(const float* __restrict_
 
 hipError_t launch_polar_order(const float* theta, int32_t n, double* sums, hipStream_t s) {
   hipLaunchKernelGGL(k_order_zero, dim3(1), dim3(64), 0, s, sums);
-  // one workgroup per CU at most: the two same-address atomics per workgroup
-  // are serialised where the memory is, so fewer, longer workgroups are faster
-  const int grid = max(1, min(256, (n + kBlock - 1) / kBlock));
+  // four workgroups per CU at most: enough waves to hide the fp64 sincos
+  // latency, few enough that the two same-address atomics per workgroup
+  // (serialised where the memory is) stay cheap
+  const int grid = max(1, min(1024, (n + kBlock - 1) / kBlock));
   hipLaunchKernelGGL(k_polar_order, dim3(grid), dim3(kBlock), 0, s, theta, n, sums);
+  hipLaunchKernelGGL(k_order_norm, dim3(1), dim3(1), 0, s, sums, n);
   return hipGetLastError();
 }
 

@@ -235,11 +235,27 @@ __global__ __launch_bounds__(kEBlock) void k_vm_energy(const double* __restrict_
                                                        const double* __restrict__ perim, int n, VmArgs va,
                                                        double* __restrict__ energy) {
   __shared__ double part[kEBlock];
-  double e = 0.0;
-  for (int i = threadIdx.x; i < n; i += kEBlock) {
-    const double da = area[i] - va.a0, dp = perim[i] - va.p0;
-    e += va.ka * da * da + va.kp * dp * dp;
+  // eight independent partial sums per lane (eight loads in flight), then
+  // combined in a fixed order
+  constexpr int kU = 8;
+  double acc[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) acc[u] = 0.0;
+  int i = threadIdx.x;
+  for (; i + (kU - 1) * kEBlock < n; i += kU * kEBlock) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const double da = area[i + u * kEBlock] - va.a0, dp = perim[i + u * kEBlock] - va.p0;
+      acc[u] += va.ka * da * da + va.kp * dp * dp;
+    }
   }
+  for (; i < n; i += kEBlock) {
+    const double da = area[i] - va.a0, dp = perim[i] - va.p0;
+    acc[0] += va.ka * da * da + va.kp * dp * dp;
+  }
+  double e = 0.0;
+#pragma unroll
+  for (int u = 0; u < kU; ++u) e += acc[u];
   part[threadIdx.x] = e;
   __syncthreads();
   for (int s = kEBlock / 2; s > 0; s >>= 1) {

@@ -175,8 +175,27 @@ struct Cell {
     put(3, 0, -2 * half, -1);
   }
 
-  // Largest squared vertex distance.
+  // Largest squared vertex distance (narrow cells in fp32: |values| < 2^88,
+  // relative error below 1e-6, absorbed by the callers' margin).
   __device__ double max_r2() const {
+    if (!WIDE) {
+      float r = 0.0f;
+      int ax, ay, fx, fy;
+      get(0, ax, ay);
+      fx = ax;
+      fy = ay;
+      for (int t = 0; t < m; ++t) {
+        int bx, by;
+        if (t + 1 < m) get(t + 1, bx, by); else { bx = fx; by = fy; }
+        const float na = static_cast<float>(ax * ax + ay * ay), nb = static_cast<float>(bx * bx + by * by);
+        const float dx = static_cast<float>(ax - bx), dy = static_cast<float>(ay - by);
+        const float cr = static_cast<float>(ax * by - ay * bx);
+        r = fmaxf(r, na * nb * (dx * dx + dy * dy) / (4.0f * cr * cr));
+        ax = bx;
+        ay = by;
+      }
+      return static_cast<double>(r);
+    }
     double r = 0.0;
     int ax, ay, fx, fy;
     get(0, ax, ay);
@@ -252,9 +271,9 @@ __device__ int build_cell(const DevWs& w, Cell<CAP, BLK, WIDE>& cell, int s, int
   // bounding square: narrow cells stay within 2^13 of the particle, wide
   // ones start at L/8 (a vertex there is already outside the domain)
   cell.init(WIDE ? (w.box >> 3) : (kVnSpan >> 1));
-  // fp64 vertex distances are within ~1e-15 relative: the margin keeps every
-  // skip and the stop test on the safe side
-  constexpr double margin = 1.0 + 1e-9;
+  // vertex distances are within ~1e-6 (narrow, fp32) or ~1e-15 (wide, fp64)
+  // relative: the margin keeps every skip and the stop test on the safe side
+  constexpr double margin = WIDE ? 1.0 + 1e-9 : 1.0 + 1e-4;
   double bound = 4.0 * cell.max_r2() * margin;  // candidates beyond cannot cut
   int outcome = -1;
   for (int r = 0; r <= q.rmax && outcome < 0; ++r) {
@@ -320,15 +339,19 @@ __device__ __forceinline__ void site_members(const DevWs& w, int sx, int sy, int
   const int end = min(w.start[c + 1], total);
   int last = -1;
   for (;;) {
-    int best = 0x7FFFFFFF;
+    int best = 0x7FFFFFFF, left = 0;  // the next index, and how many remain
     for (int t = beg; t < end; ++t) {
       const int4 e = w.sorted[t];
-      if (e.x == sx && e.y == sy && e.z > last && e.z < best && e.z != skip) best = e.z;
+      if (e.x == sx && e.y == sy && e.z > last && e.z != skip) {
+        ++left;
+        best = min(best, e.z);
+      }
     }
-    if (best == 0x7FFFFFFF) break;
+    if (left == 0) break;
     if (cnt < dmax) row[cnt] = best;
     ++cnt;
     last = best;
+    if (left == 1) break;  // that was the last one (no second scan for a lone particle)
   }
 }
 
@@ -612,10 +635,19 @@ __global__ __launch_bounds__(kBlock) void k_vor_check(const int32_t* __restrict_
         if (ma < 3 || ma > dmax) {
           fail = true;
         } else {
+          // a's row must hold b's site directly followed by i's site.  When it
+          // lists b directly followed by i the sites are adjacent (b and i lie
+          // at different positions) and no position is needed; otherwise the
+          // row is walked site by site.
           const int32_t* rowa = ring + static_cast<long long>(a) * dmax;
-          bool okidx = true;
-          for (int u = 0; u < ma; ++u) okidx = okidx && static_cast<unsigned>(rowa[u]) < static_cast<unsigned>(n);
-          if (!okidx || !row_holds_then(row_view(rowa, ma, a, x, y), x[row[tb]], y[row[tb]], xi, yi))
+          const int b = row[tb];
+          bool okidx = true, adjacent = false;
+          for (int u = 0; u < ma; ++u) {
+            const int q = rowa[u];
+            okidx = okidx && static_cast<unsigned>(q) < static_cast<unsigned>(n);
+            adjacent = adjacent || (q == b && rowa[u + 1 < ma ? u + 1 : 0] == i);
+          }
+          if (!okidx || (!adjacent && !row_holds_then(row_view(rowa, ma, a, x, y), x[b], y[b], xi, yi)))
             fail = true;
         }
         ++nsites;

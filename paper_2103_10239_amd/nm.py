@@ -277,14 +277,13 @@ def knn_layout(n: int, box: int, cell_w: int, block: int, k: int) -> dict:
 
 def polar_order(theta: torch.Tensor, sums: torch.Tensor | None = None) -> float:
     """Polar order parameter |sum_i (cos, sin) theta_i| / n of device headings
-    (synchronises to read the two fp64 sums)."""
+    (synchronises to read it)."""
     n = int(theta.numel())
     if sums is None:
-        sums = torch.empty(2, dtype=torch.float64, device=theta.device)
+        sums = torch.empty(3, dtype=torch.float64, device=theta.device)
     _ok(lib().nm_polar_order(_dev(theta, torch.float32, n, "theta"), n,
-                             _dev(sums, torch.float64, 2, "sums"), _stream(theta.device)), "polar_order")
-    c, s = sums.cpu().tolist()
-    return float((c * c + s * s) ** 0.5 / n)
+                             _dev(sums, torch.float64, 3, "sums"), _stream(theta.device)), "polar_order")
+    return float(sums[2].item())
 
 
 class Workspace:
