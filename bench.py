@@ -25,6 +25,9 @@ Beside it, on the same GPU:
            [1024, 2^20], k in {7, 12}, 1..100 steps, half clustered) through
            the served form under a 200 GB and a 1 GB budget, and the same
            stream run one job at a time with the plain calls
+  voronoi  Voronoi rows, the reuse certificate and Voronoi-model forces at
+           N = 2^20, and Vicsek steps over Voronoi neighbours (in-place
+           update against a rebuild every step)
 
 roofline: the fused k-NN + alignment kernel (k_knn<7, align>) bracketed by
 HIP events on the stream it runs on; its algorithmic traffic is 24 + 4k bytes
@@ -71,7 +74,7 @@ def parse():
     ap.add_argument("--retune-reps", type=int, default=1, help="timed steps per candidate when re-picking")
     ap.add_argument("--metric-steps", type=int, default=100)
     ap.add_argument("--batched-steps", type=int, default=50)
-    ap.add_argument("--served-seconds", type=float, default=15.0)
+    ap.add_argument("--served-seconds", type=float, default=60.0)
     ap.add_argument("--variant-steps", type=int, default=100)
     ap.add_argument("--clustered-steps", type=int, default=100)
     ap.add_argument("--no-clustered", action="store_true")
