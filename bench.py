@@ -581,9 +581,14 @@ def bench_batched(args, torch, nm, workloads):
     lat = [a.elapsed_time(e) for a, e in ev]
     ms_step = (t1 - t0) * 1e3 / steps
     widths = sorted({b.grid(s).cell_w for s in range(len(sizes))})
+    blocks = {}  # block choice -> systems using it
+    for s in range(len(sizes)):
+        blk = b.grid(s).block
+        name = (f"{blk & ~nm.NM_BLOCK_SUBSTRIPS}s" if blk >= 0 and blk & nm.NM_BLOCK_SUBSTRIPS else str(blk))
+        blocks[name] = blocks.get(name, 0) + 1
     b.close()
     log(f"[bench] batched: {len(sizes)} systems, {total} particles, {ms_step:.4f} ms/step "
-        f"(p50 {pct(lat, 50):.4f}, p99 {pct(lat, 99):.4f}), tune {tune_s:.2f} s")
+        f"(p50 {pct(lat, 50):.4f}, p99 {pct(lat, 99):.4f}), tune {tune_s:.2f} s, blocks {blocks}")
 
     # Baseline: the plain one-system calls for every system, eager and captured.
     systems = [nm.System.create(xs[s], ys[s], ts[s], k, nm.make_params(box, 64, 0.2, 1, workloads.NOISE_SEED, s),
@@ -620,7 +625,7 @@ def bench_batched(args, torch, nm, workloads):
             "ms_per_step": ms_step, "particle_steps_per_s": total / (ms_step * 1e-3),
             "step_latency_ms_p50": pct(lat, 50), "step_latency_ms_p99": pct(lat, 99),
             "roofline_frac": (24 + 4 * k) * total / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "cell_widths": widths, "tune_seconds": tune_s,
+            "cell_widths": widths, "blocks": blocks, "tune_seconds": tune_s,
             "plain_eager_ms_per_step": plain_ms, "plain_graph_ms_per_step": plain_graph_ms,
             "speedup_vs_plain_eager": plain_ms / ms_step, "speedup_vs_plain_graph": plain_graph_ms / ms_step}
 

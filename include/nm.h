@@ -424,10 +424,20 @@ int nm_batch_step(nm_batch* b, int32_t nsteps, int32_t use_graph, void* stream);
 
 /* Autotuner: for each size class (systems with equal floor(log2 n)), time
  * `reps` steps of the class alone under each candidate cell width (about
- * 0.5, 1, 2 and 4 particles per cell) and keep the fastest.  The tuning
- * steps read the current state and write only the other buffer and nbr, and
- * do not advance the step count.  Synchronises; drops the captured graph. */
+ * 0.5, 1, 2 and 4 particles per cell, blocks chosen per query) and keep the
+ * fastest; then, at that width, the k-NN block choice (per query, fixed
+ * sides 4 and 6, or the sub-strip kernel: nm_grid.block), which also sets
+ * the strip shape.  The tuning steps read the current state and write only
+ * the other buffer and nbr, and do not advance the step count.  The lists
+ * are the same for every choice.  Synchronises; drops the captured graph. */
 int nm_batch_tune(nm_batch* b, int32_t reps, void* stream);
+
+/* Sets every system's k-NN block choice (nm_grid.block: 0, a side 3..15,
+ * -1, optionally with NM_BLOCK_SUBSTRIPS), keeping the tuned cell widths:
+ * for callers that know their workload.  The lists are the same for every
+ * choice.  NM_E_INVAL for a value nm_grid does not accept.  Synchronises;
+ * drops the captured graph. */
+int nm_batch_set_block(nm_batch* b, int32_t block, void* stream);
 
 /* The grid chosen for system s (cell width, block) and its particle offset. */
 int nm_batch_system(const nm_batch* b, int32_t s, nm_grid* g, int32_t* offset);

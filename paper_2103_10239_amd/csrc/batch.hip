@@ -86,7 +86,8 @@ BatchSys make_batch_sys(const SysSpec& s, int k) {
   d.nitems[kStCount] = (s.g.n + kBlock - 1) / kBlock;
   d.nitems[kStScan] = lay.nb_scan_c;
   d.nitems[kStScatter] = (s.g.n + 4 * kBlock - 1) / (4 * kBlock);
-  d.nitems[kStKnn] = d.ntiles;
+  d.nitems[kStKnn] = d.f.split ? 0 : d.ntiles;
+  d.nitems[kStKnnSplit] = d.f.split ? d.ntiles : 0;
   return d;
 }
 
@@ -152,6 +153,11 @@ int ilog2i(int64_t v) {
 // Candidate cell occupancies of the tuner, finest first.
 const double kPerCell[] = {0.5, 1.0, 2.0, 4.0};
 constexpr int kNumPerCell = 4;
+// Candidate k-NN block choices, weighed at the chosen cell width: the block
+// side chosen per query, fixed sides 4 and 6 (which also set the strip's halo
+// and width), and the sub-strip kernel with per-query sides.
+const int32_t kBlockCand[] = {0, 4, 6, NM_BLOCK_SUBSTRIPS};
+constexpr int kNumBlockCand = 4;
 
 int32_t cell_w_for(int32_t n, int32_t box, double per_cell) {
   return nm_suggest_cell_w(n, box, per_cell);
@@ -198,14 +204,16 @@ void build_tables(nm_batch* b, const std::vector<int>& which, std::vector<BatchS
 int64_t max_items(const nm_batch* b, int s) {
   int64_t best = 0;
   for (int c = 0; c < kNumPerCell; ++c) {
-    nm_grid g{b->n[s], b->box, cell_w_for(b->n[s], b->box, kPerCell[c]), 0};
-    Layout lay;
-    if (!make_layout(&g, &lay)) continue;
-    const DevWs w = dev_ws(&g, lay, nullptr);  // geometry only
-    const TileCfg tc = tile_cfg(w, fast_cfg(w, b->k, 0), b->k);
-    const int64_t tiles = static_cast<int64_t>(tc.ntx) * tc.nty;
-    best = std::max<int64_t>(best, 64 + (g.n + kBlock - 1) / kBlock + lay.nb_scan_c +
-                                       (g.n + 4 * kBlock - 1) / (4 * kBlock) + tiles);
+    for (int bc = 0; bc < kNumBlockCand; ++bc) {
+      nm_grid g{b->n[s], b->box, cell_w_for(b->n[s], b->box, kPerCell[c]), kBlockCand[bc]};
+      Layout lay;
+      if (!make_layout(&g, &lay)) continue;
+      const DevWs w = dev_ws(&g, lay, nullptr);  // geometry only
+      const TileCfg tc = tile_cfg(w, fast_cfg(w, b->k, g.block), b->k);
+      const int64_t tiles = static_cast<int64_t>(tc.ntx) * tc.nty;
+      best = std::max<int64_t>(best, 64 + (g.n + kBlock - 1) / kBlock + lay.nb_scan_c +
+                                         (g.n + 4 * kBlock - 1) / (4 * kBlock) + tiles);
+    }
   }
   return best;
 }
@@ -380,12 +388,33 @@ int nm_batch_tune(nm_batch* b, int32_t reps, void* stream) {
   for (int q = 0; q < b->nsys; ++q) cls[ilog2i(b->n[q] + 1) - 1].push_back(q);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return NM_E_DEVICE;
-  const std::vector<int32_t> wlog0 = b->wlog;
+  const std::vector<int32_t> wlog0 = b->wlog, block0 = b->block;
   int rc = NM_OK;
+  // Time `reps` steps of the class `mem` alone under the current choices
+  // (after one untimed step on freshly initialised workspaces); < 0 on error.
+  auto time_class = [&](const std::vector<int>& mem) -> float {
+    std::vector<BatchSys> sys;
+    std::vector<int32_t> items;
+    int32_t begin[kStages + 1];
+    build_tables(b, mem, sys, items, begin);
+    if (upload(b, sys, items, begin, s) != hipSuccess || launch_batch_bin(b->ref, kStInit, s) != hipSuccess ||
+        enqueue_batch_step(b->ref, b->k, false, s) != hipSuccess || hipEventRecord(e0, s) != hipSuccess)
+      return -1.0f;
+    for (int t = 0; t < reps; ++t)
+      if (enqueue_batch_step(b->ref, b->k, false, s) != hipSuccess) return -1.0f;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return -1.0f;
+    return ms;
+  };
   for (auto& kv : cls) {
     const std::vector<int>& mem = kv.second;
+    // First the cell width (blocks chosen per query), then the block choice
+    // at that width.
     float best_ms = 0.0f;
     int best_c = -1;
+    for (int q : mem) b->block[q] = 0;
     for (int c = 0; c < kNumPerCell && rc == NM_OK; ++c) {
       for (int q : mem) b->wlog[q] = ilog2i(cell_w_for(b->n[q], b->box, kPerCell[c]));
       bool dup = false;  // same widths as an earlier candidate: nothing new to time
@@ -394,21 +423,8 @@ int nm_batch_tune(nm_batch* b, int32_t reps, void* stream) {
         for (int q : mem) dup = dup && ilog2i(cell_w_for(b->n[q], b->box, kPerCell[c2])) == b->wlog[q];
       }
       if (dup) continue;
-      std::vector<BatchSys> sys;
-      std::vector<int32_t> items;
-      int32_t begin[kStages + 1];
-      build_tables(b, mem, sys, items, begin);
-      if (upload(b, sys, items, begin, s) != hipSuccess ||
-          launch_batch_bin(b->ref, kStInit, s) != hipSuccess ||
-          enqueue_batch_step(b->ref, b->k, false, s) != hipSuccess || hipEventRecord(e0, s) != hipSuccess) {
-        rc = NM_E_DEVICE;
-        break;
-      }
-      for (int t = 0; t < reps && rc == NM_OK; ++t)
-        if (enqueue_batch_step(b->ref, b->k, false, s) != hipSuccess) rc = NM_E_DEVICE;
-      float ms = 0.0f;
-      if (rc != NM_OK || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      const float ms = time_class(mem);
+      if (ms < 0.0f) {
         rc = NM_E_DEVICE;
         break;
       }
@@ -419,15 +435,43 @@ int nm_batch_tune(nm_batch* b, int32_t reps, void* stream) {
     }
     if (rc != NM_OK) break;
     for (int q : mem) b->wlog[q] = ilog2i(cell_w_for(b->n[q], b->box, kPerCell[best_c]));
+    int best_b = 0;  // kBlockCand[0] = 0, timed above at this width
+    for (int bc = 1; bc < kNumBlockCand && rc == NM_OK; ++bc) {
+      for (int q : mem) b->block[q] = kBlockCand[bc];
+      const float ms = time_class(mem);
+      if (ms < 0.0f) {
+        rc = NM_E_DEVICE;
+        break;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_b = bc;
+      }
+    }
+    if (rc != NM_OK) break;
+    for (int q : mem) b->block[q] = kBlockCand[best_b];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != NM_OK) {
     b->wlog = wlog0;
+    b->block = block0;
     rebuild_all(b, s);
     return rc;
   }
   return rebuild_all(b, s);
+}
+
+int nm_batch_set_block(nm_batch* b, int32_t block, void* stream) {
+  if (b == nullptr || b->ws == nullptr) return NM_E_INVAL;
+  for (int q = 0; q < b->nsys; ++q) {
+    nm_grid g = grid_of(b, q);
+    g.block = block;
+    Layout lay;
+    if (!make_layout(&g, &lay)) return NM_E_INVAL;
+  }
+  b->block.assign(b->nsys, block);
+  return rebuild_all(b, reinterpret_cast<hipStream_t>(stream));
 }
 
 int nm_batch_system(const nm_batch* b, int32_t s, nm_grid* g, int32_t* offset) {

@@ -871,9 +871,10 @@ __device__ __forceinline__ AlignArgs uniform_load_align(const BatchSys* d) {
   return a;
 }
 
-template <int KMAX>
+template <int KMAX, int kMode>
 __global__ __launch_bounds__(kBlock) void k_bb_knn(BatchRef b, int k) {
-  const int ni = b.begin[kStKnn + 1] - b.begin[kStKnn];
+  constexpr int kSt = kMode == kOverflowSplit ? kStKnnSplit : kStKnn;
+  const int ni = b.begin[kSt + 1] - b.begin[kSt];
   const int per = gridDim.x & ~7;  // whole rounds of the 8 XCDs
   for (int hw = blockIdx.x; hw < ni; hw += gridDim.x) {
     // Remap within the rounds that every workgroup of a multiple-of-8 grid takes.
@@ -881,13 +882,13 @@ __global__ __launch_bounds__(kBlock) void k_bb_knn(BatchRef b, int k) {
     const int round_base = (hw / gridDim.x) * gridDim.x;
     if (per == static_cast<int>(gridDim.x) && round_base + per <= ni)
       it = round_base + xcd_tile(hw - round_base, per);
-    const BatchSys* g = b.sys + b.items[b.begin[kStKnn] + it];
+    const BatchSys* g = b.sys + b.items[b.begin[kSt] + it];
     const DevWs w = uniform_load(&g->w);
     const FastCfg f = uniform_load(&g->f);
     const TileCfg tc = uniform_load(&g->tc);
     const AlignArgs a = uniform_load_align(g);
-    const int li = it - __builtin_amdgcn_readfirstlane(g->base[kStKnn]);
-    knn_tile_body<KMAX, true, kOverflowGlobal>(w, f, tc, k, uniform_ptr(g->nbr), nullptr, a, li);
+    const int li = it - __builtin_amdgcn_readfirstlane(g->base[kSt]);
+    knn_tile_body<KMAX, true, kMode>(w, f, tc, k, uniform_ptr(g->nbr), nullptr, a, li);
     __syncthreads();
   }
 }
@@ -987,16 +988,27 @@ hipError_t dispatch_k(int k, F&& f) {
 
 }  // namespace
 
-TileCfg tile_cfg(const DevWs& w, const FastCfg& f, int k) { return tile_cfg_impl(w, f, k, false); }
+TileCfg tile_cfg(const DevWs& w, const FastCfg& f, int k) { return tile_cfg_impl(w, f, k, f.split != 0); }
 
+// The tiles of the plain-strip systems, then those of the sub-strip systems
+// (each launch only when it has items).
 hipError_t launch_batch_knn(const BatchRef& b, int k, hipStream_t s) {
   const int nt = b.begin[kStKnn + 1] - b.begin[kStKnn];
-  if (nt <= 0) return hipSuccess;
+  const int ns = b.begin[kStKnnSplit + 1] - b.begin[kStKnnSplit];
   return dispatch_k(k, [&](auto km) {
     constexpr int KM = decltype(km)::value;
-    const int g = batch_grid(reinterpret_cast<const void*>(k_bb_knn<KM>), nt);
-    hipLaunchKernelGGL((k_bb_knn<KM>), dim3(g), dim3(kBlock), 0, s, b, k);
-    return hipGetLastError();
+    if (nt > 0) {
+      const int g = batch_grid(reinterpret_cast<const void*>(k_bb_knn<KM, kOverflowGlobal>), nt);
+      hipLaunchKernelGGL((k_bb_knn<KM, kOverflowGlobal>), dim3(g), dim3(kBlock), 0, s, b, k);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (ns > 0) {
+      const int g = batch_grid(reinterpret_cast<const void*>(k_bb_knn<KM, kOverflowSplit>), ns);
+      hipLaunchKernelGGL((k_bb_knn<KM, kOverflowSplit>), dim3(g), dim3(kBlock), 0, s, b, k);
+      return hipGetLastError();
+    }
+    return hipSuccess;
   });
 }
 

@@ -530,7 +530,9 @@ struct AlignArgs {
 // `parity` and writes buffer 1 - parity; the advance stage flips the parity
 // and increments the step, so one captured step replays for any step.
 // ---------------------------------------------------------------------------
-enum BatchStage { kStInit = 0, kStCount, kStScan, kStScatter, kStKnn, kStages };
+// The k-NN stage is two: systems whose grid uses the sub-strip kernel
+// (NM_BLOCK_SUBSTRIPS) have their tiles in kStKnnSplit, the others in kStKnn.
+enum BatchStage { kStInit = 0, kStCount, kStScan, kStScatter, kStKnn, kStKnnSplit, kStages };
 
 struct BatchSys {
   DevWs w;

@@ -119,6 +119,7 @@ def lib():
     L.nm_batch_bind.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.POINTER(BatchIO), _c_u64, _vp]
     L.nm_batch_step.argtypes = [_vp, _c_i32, _c_i32, _vp]
     L.nm_batch_tune.argtypes = [_vp, _c_i32, _vp]
+    L.nm_batch_set_block.argtypes = [_vp, _c_i32, _vp]
     L.nm_batch_system.argtypes = [_vp, _c_i32, gp, ctypes.POINTER(_c_i32)]
     L.nm_batch_steps_done.argtypes, L.nm_batch_steps_done.restype = [_vp], _c_i64
     L.nm_batch_check.argtypes = [_vp, _vp]
@@ -137,7 +138,7 @@ def lib():
               "nm_voronoi_forces",
               "nm_voronoi_check", "nm_voronoi_update", "nm_metric_list", "nm_align_step",
               "nm_step", "nm_bin_step", "nm_knn_align", "nm_check", "nm_tune_grid", "nm_batch_plan", "nm_batch_bind",
-              "nm_batch_step", "nm_batch_tune", "nm_batch_system", "nm_batch_check"):
+              "nm_batch_step", "nm_batch_tune", "nm_batch_set_block", "nm_batch_system", "nm_batch_check"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -531,6 +532,10 @@ class Batch:
 
     def tune(self, reps: int = 3) -> None:
         _ok(lib().nm_batch_tune(self._h, int(reps), _stream(self.device)), "batch_tune")
+
+    def set_block(self, block: int) -> None:
+        """Every system's k-NN block choice (nm_grid.block), widths kept."""
+        _ok(lib().nm_batch_set_block(self._h, int(block), _stream(self.device)), "batch_set_block")
 
     def grid(self, s: int) -> Grid:
         g, off = Grid(), _c_i32()

@@ -128,6 +128,9 @@ def test_batch_plan_is_host_only():
     sizes = (ctypes.c_int32 * 3)(300, 5000, 65536)
     assert L_.nm_batch_plan(3, sizes, L, 7, ctypes.byref(p), None, ctypes.byref(h), ctypes.byref(nbytes)) == 0
     assert nbytes.value > sum((24 + 4 * 7) * n for n in (300, 5000, 65536))
+    # not bound to device memory yet: no block choice or tuning can be set
+    assert L_.nm_batch_set_block(h, 4, None) == nm.NM_E_INVAL
+    assert L_.nm_batch_tune(h, 1, None) == nm.NM_E_INVAL
     L_.nm_batch_destroy(h)
     bad = (ctypes.c_int32 * 2)(300, 7)  # a system with n < k + 1
     assert L_.nm_batch_plan(2, bad, L, 7, ctypes.byref(p), None, ctypes.byref(h), ctypes.byref(nbytes)) == nm.NM_E_INVAL

@@ -152,6 +152,31 @@ def test_batch_tune_keeps_results():
     bu.close()
 
 
+@pytest.mark.parametrize("block", [4, 6, nm.NM_BLOCK_SUBSTRIPS, nm.NM_BLOCK_SUBSTRIPS | 4, -1])
+def test_batch_block_choices_match_plain_steps(block):
+    # every block choice the tuner weighs (and the exact search alone) gives
+    # the plain calls' results; a third of the systems clustered
+    sizes = [int(v) for v in workloads.batched_sizes(9, lo=256, hi=65536, seed=21)]
+    k = 7
+    xs, ys, ts = _systems(sizes, clustered_every=3, seed=31)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=77)
+    b = nm.Batch(sizes, np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), k, p)
+    b.set_block(block)
+    assert all(b.grid(s).block == block for s in range(len(sizes)))
+    nsteps = 2
+    b.step(nsteps, use_graph=True)
+    torch.cuda.synchronize()
+    assert b.check() == 0
+    for s, n in enumerate(sizes):
+        ps = nm.make_params(L, v0=64, eta=0.2, seed=77, sys_id=s)
+        ex, ey, et, en = _plain_run(xs[s], ys[s], ts[s], k, ps, nsteps)
+        bx, by, bth, bn = (t.cpu().numpy() for t in b.system(s))
+        assert np.array_equal(bx, ex) and np.array_equal(by, ey), f"system {s} (n={n})"
+        assert np.array_equal(bth.view(np.uint32), et.view(np.uint32)), f"system {s} (n={n})"
+        assert np.array_equal(bn, en), f"system {s} (n={n})"
+    b.close()
+
+
 def test_batch_reports_out_of_range_coordinate():
     sizes = [500, 700, 300]
     xs, ys, ts = _systems(sizes)
