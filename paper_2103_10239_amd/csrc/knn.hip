@@ -231,11 +231,13 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
   int32_t* row = nbr + static_cast<int64_t>(q.z) * k;
   const int sh = 32 - w.log2_box;
   double sx = 0.0, sy = 0.0;
+  int rv[KMAX];
 #pragma unroll
   for (int t = 0; t < KMAX; ++t) {
+    rv[t] = 0;
     if (t >= KMAX - k) {
       const int4 e = w.sorted[slot[t]];
-      row[t - (KMAX - k)] = e.z;
+      rv[t] = e.z;
       if (!kAlign && d2out) {
         const int ex = wrap_axis(e.x - q.x, sh), ey = wrap_axis(e.y - q.y, sh);
         d2out[static_cast<int64_t>(q.z) * k + t - (KMAX - k)] =
@@ -248,6 +250,7 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
       }
     }
   }
+  store_row<KMAX>(row, rv, k);
   if (!kAlign) return;
 
   // Eq. (2): average of the neighbours' unit vectors (plus the particle's own),
@@ -356,16 +359,23 @@ __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, 
                                              int pq, int pqy, int rx, int oy, int cy, int k, int Bq,
                                              const Filter& filt, int (&lds)[KMAX]) {
   constexpr int KT = KMAX + 1;
+  // Without a filter the query's own key (distance 0, its LDS index) goes
+  // through the network with the others, one more list entry, and is taken
+  // out at the end: cheaper than masking every candidate against it.
+  constexpr bool kWithSelf = !Filter::kActive;
+  constexpr int KS = kWithSelf ? KT + 1 : KT;
   const int2* lpos2 = reinterpret_cast<const int2*>(lpos);
   if (Bq > tc.bmax) return false;
   for (int attempt = 0; attempt < 2; ++attempt) {
     const StripBlock b = strip_block(rx, oy, cy, Bq, W, w.log2_w);
-    uint32_t key[KT];
+    uint32_t kl[KS];
 #pragma unroll
-    for (int t = 0; t < KT; ++t) key[t] = (t < KT - (k + 1)) ? 0u : kKey32Inf;
+    for (int t = 0; t < KS; ++t) kl[t] = (t < KS - (k + 1 + (kWithSelf ? 1 : 0))) ? 0u : kKey32Inf;
     const int sh = b.sh;
     const int a = rbase[b.r0], e = rbase[b.r0 + Bq];
-    for (int i = a; i < e; i += kUnroll) {
+    // One round: candidates i .. i + kUnroll - 1.  Only the last round of a
+    // block (tail) can pass its end; it masks what lies beyond.
+    auto round = [&](int i, bool tail) {
       uint32_t kk[kUnroll];
       if (kWide) {
         int2 pc[kUnroll];
@@ -387,7 +397,7 @@ __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, 
         const uint32_t clampd = static_cast<uint32_t>(b.bound);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const uint32_t d2 = static_cast<uint32_t>(rel_d2(pc[u], pq));
+          const uint32_t d2 = rel_d2_u(pc[u], pq);
           kk[u] = ((min(d2, clampd) >> sh) << 13) | static_cast<uint32_t>(i + u);
           if constexpr (Filter::kActive) {
             const short2v dd = __builtin_bit_cast(short2v, pc[u]) - __builtin_bit_cast(short2v, pq);
@@ -396,8 +406,26 @@ __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, 
         }
       }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        net_insert(key, (i + u == self || i + u >= e) ? kKey32Inf : kk[u]);
+      for (int u = 0; u < kUnroll; ++u) {
+        uint32_t c = kk[u];
+        if (!kWithSelf && i + u == self) c = kKey32Inf;
+        if (tail && i + u >= e) c = kKey32Inf;
+        net_insert(kl, c);
+      }
+    };
+    const int full = a + ((e - a) & ~(kUnroll - 1));
+    for (int i = a; i < full; i += kUnroll) round(i, false);
+    if (full < e) round(full, true);
+    uint32_t key[KT];
+    if constexpr (kWithSelf) {
+      // the first entry not below the query's own key is that key (it is in
+      // the list unless more than KS duplicates of lower index precede it)
+      const uint32_t selfkey = static_cast<uint32_t>(self);
+#pragma unroll
+      for (int t = 0; t < KT; ++t) key[t] = kl[t] < selfkey ? kl[t] : kl[t + 1];
+    } else {
+#pragma unroll
+      for (int t = 0; t < KT; ++t) key[t] = kl[t];
     }
     const uint32_t kth = key[KT - 2];
     const long long dmax = (static_cast<long long>(key32_d(kth) + 1) << sh) - 1;
@@ -572,6 +600,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   __shared__ int s_defer;
   __shared__ int s_dq[kDeferCap];  // slots of the strip's uncertified queries
   __shared__ uint8_t s_rowid[kStripPts];   // halo row of each staged particle
+  __shared__ uint16_t s_qmap[kStripPts];   // LDS index of each of the strip's queries
   __shared__ int s_sub[kStripRows + 1];    // sub-strip rows (kOverflowSplit)
   __shared__ int s_nsub;
   int* lpos = reinterpret_cast<int*>(lpos_store);
@@ -595,7 +624,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   // built at each use: an aggregate of LDS addresses shared by the lambdas
   // below would become a constant global, which the target cannot express
   auto strip_lds = [&]() {
-    return StripLds{lpos_store, lidx, s_rbase, s_ga0, s_n0, s_ga1, s_qoff, s_tself, s_wsum, s_rowid};
+    return StripLds{lpos_store, lidx, s_rbase, s_ga0, s_n0, s_ga1, s_qoff, s_tself, s_wsum, s_rowid, s_qmap};
   };
   if (threadIdx.x == 0) s_defer = 0;
 
@@ -653,11 +682,13 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
     const int qi = lidx[self];
     int32_t* row = nbr + static_cast<int64_t>(qi) * k;
     double sx = 0.0, sy = 0.0;
+    int rv[KMAX];
 #pragma unroll
     for (int t = 0; t < KMAX; ++t) {
+      rv[t] = 0;
       if (t >= KMAX - k) {
         const int i = nb[t];
-        row[t - (KMAX - k)] = lidx[i];
+        rv[t] = lidx[i];
         if (!kAlign && d2out)
           d2out[static_cast<int64_t>(qi) * k + t - (KMAX - k)] =
               wide ? staged_d2<true>(lpos, i, pq, pqy) : staged_d2<false>(lpos, i, pq, pqy);
@@ -668,6 +699,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
         }
       }
     }
+    store_row<KMAX>(row, rv, k);
     if (kAlign) {
       // Eq. (2) and Eq. (1) as in finish_query, the position from the staged copy
       const double2 own = w.cs[2 * s];
@@ -709,11 +741,12 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
     const bool staged = strip_stage<true>(w, geo, strip_lds(), total, npts, nq);
     if (nq == 0) return;
     for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
-      const int r = row_of(qi);
-      if (staged)
-        staged_query(s_tself[r] + (qi - s_qoff[r]), r + hy);
-      else
-        global_query(qi, r);
+      if (staged) {
+        const int self = s_qmap[qi];
+        staged_query(self, s_rowid[self]);
+      } else {
+        global_query(qi, row_of(qi));
+      }
     }
   } else {
     // The strip is staged whole when its halo fits LDS.  Otherwise it runs
@@ -751,8 +784,8 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
       } else {
         if (st) {
           for (int qi = threadIdx.x; qi < nq_cur; qi += kBlock) {
-            const int r = row_of(qi);
-            staged_query(s_tself[r] + (qi - s_qoff[r]), r + hy);
+            const int self = s_qmap[qi];
+            staged_query(self, s_rowid[self]);
           }
         } else {
           for (int qi = threadIdx.x; qi < nq_cur; qi += kBlock) global_query(qi, row_of(qi));

@@ -377,6 +377,29 @@ __device__ __forceinline__ void net_insert(uint32_t (&key)[KT], uint32_t kk) {
 
 __device__ __forceinline__ uint32_t key32_d(uint32_t kk) { return kk >> 13; }
 
+// One list row of k entries, v[KMAX - k .. KMAX): a full row goes out as
+// 16-byte and smaller vector stores (rows start on any 4-byte boundary), so
+// that a wavefront's scattered rows cost a few stores per lane, not k.
+typedef int nm_int4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef int nm_int3u __attribute__((ext_vector_type(3), aligned(4)));
+typedef int nm_int2u __attribute__((ext_vector_type(2), aligned(4)));
+template <int KMAX>
+__device__ __forceinline__ void store_row(int32_t* row, const int (&v)[KMAX], int k) {
+  if (k == KMAX) {
+#pragma unroll
+    for (int t = 0; t + 4 <= KMAX; t += 4)
+      *reinterpret_cast<nm_int4u*>(row + t) = nm_int4u{v[t], v[t + 1], v[t + 2], v[t + 3]};
+    constexpr int b = KMAX & ~3, r = KMAX & 3;
+    if constexpr (r == 3) *reinterpret_cast<nm_int3u*>(row + b) = nm_int3u{v[b], v[b + 1], v[b + 2]};
+    if constexpr (r == 2) *reinterpret_cast<nm_int2u*>(row + b) = nm_int2u{v[b], v[b + 1]};
+    if constexpr (r == 1) row[b] = v[b];
+  } else {
+#pragma unroll
+    for (int t = 0; t < KMAX; ++t)
+      if (t >= KMAX - k) row[t - (KMAX - k)] = v[t];
+  }
+}
+
 // Geometry of one query's block.
 struct QBlock {
   int hx, hy, lo_x, lo_y, B, sh;

@@ -54,6 +54,15 @@ __device__ __forceinline__ int rel_d2(int packed_c, int packed_q) {
   return __builtin_amdgcn_sdot2(d, d, 0, false);
 }
 
+// The same as an unsigned 32-bit value (below 2^31 + 1), the dot product
+// taken with a zero accumulator operand, so that no register is cleared first.
+__device__ __forceinline__ uint32_t rel_d2_u(int packed_c, int packed_q) {
+  const short2v d = __builtin_bit_cast(short2v, packed_c) - __builtin_bit_cast(short2v, packed_q);
+  uint32_t r;
+  asm("v_dot2_i32_i16 %0, %1, %1, 0" : "=v"(r) : "v"(__builtin_bit_cast(int, d)));
+  return r;
+}
+
 __device__ __forceinline__ int pack_rel(int rx, int ry) {
   return static_cast<int>((static_cast<uint32_t>(rx) & 0xFFFFu) | (static_cast<uint32_t>(ry) << 16));
 }
@@ -74,6 +83,7 @@ struct StripLds {
   int* tself;        // [kStripRows]
   int* wsum;         // [kBlock / 64]
   uint8_t* rowid;    // [kStripPts] halo row of each staged particle
+  uint16_t* qmap;    // [kStripPts] LDS index of each query of the strip (may be null)
 };
 
 // Cell-ordered slot of staged particle i (the inverse of the staging copy).
@@ -148,6 +158,8 @@ __device__ __forceinline__ bool strip_stage(const DevWs& w, const StripGeo& g, c
     // particles as offsets from the halo corner, one per thread per round.
     if (rho < R)
       for (int p = rb; p < rb + rlen; ++p) s.rowid[p] = static_cast<uint8_t>(rho);
+    if (s.qmap && qrow)
+      for (int j = 0; j < qlen; ++j) s.qmap[qo + j] = static_cast<uint16_t>(rb + qrow_off + j);
     __syncthreads();
     for (int pidx = threadIdx.x; pidx < npts; pidx += kBlock) {
       const int r = s.rowid[pidx];
