@@ -278,6 +278,11 @@ __device__ __forceinline__ bool in_box(int xi, int yi, const DevWs& w) {
          static_cast<uint32_t>(yi) < static_cast<uint32_t>(w.box);
 }
 
+// The two-level kernels take kCoarseP particles per workgroup, kCoarseU per
+// lane: every lane issues all its loads before its first LDS atomic, so that
+// a workgroup has its whole share in flight at once.
+constexpr int kCoarseU = kCoarseP / kBlock;
+
 __global__ __launch_bounds__(kBlock) void k_coarse_count(const int32_t* __restrict__ x,
                                                          const int32_t* __restrict__ y, DevWs w) {
   __shared__ int h[kCoarseBins];
@@ -289,16 +294,24 @@ __global__ __launch_bounds__(kBlock) void k_coarse_count(const int32_t* __restri
       w.hdr->built = 0u;
     }
   }
+  const int i0 = b * kCoarseP + threadIdx.x, i1 = min((b + 1) * kCoarseP, w.n);
+  int xv[kCoarseU], yv[kCoarseU];
+#pragma unroll
+  for (int u = 0; u < kCoarseU; ++u) {
+    const int i = i0 + u * kBlock;
+    xv[u] = i < i1 ? x[i] : 0;
+    yv[u] = i < i1 ? y[i] : 0;
+  }
   for (int t = threadIdx.x; t < w.nbins; t += kBlock) h[t] = 0;
   __syncthreads();
-  const int i1 = min((b + 1) * kCoarseP, w.n);
-  for (int i = b * kCoarseP + threadIdx.x; i < i1; i += kBlock) {
-    const int xi = x[i], yi = y[i];
-    if (!in_box(xi, yi, w)) {
+#pragma unroll
+  for (int u = 0; u < kCoarseU; ++u) {
+    if (i0 + u * kBlock >= i1) break;
+    if (!in_box(xv[u], yv[u], w)) {
       set_err(w.hdr, NM_E_RANGE);
       continue;
     }
-    const int64_t c = static_cast<int64_t>(yi >> w.log2_w) * w.G + (xi >> w.log2_w);
+    const int64_t c = static_cast<int64_t>(yv[u] >> w.log2_w) * w.G + (xv[u] >> w.log2_w);
     atomicAdd(&h[static_cast<int>(c >> w.sb)], 1);
   }
   __syncthreads();
@@ -313,27 +326,43 @@ __global__ __launch_bounds__(kBlock) void k_coarse_scatter(const int32_t* __rest
   __shared__ int cur[kCoarseBins];
   if (!ws_header_ok(w)) return;
   const int b = blockIdx.x;
+  const int i0 = b * kCoarseP + threadIdx.x, i1 = min((b + 1) * kCoarseP, w.n);
+  int xv[kCoarseU], yv[kCoarseU], tv[kCoarseU];
+#pragma unroll
+  for (int u = 0; u < kCoarseU; ++u) {
+    const int i = i0 + u * kBlock;
+    xv[u] = i < i1 ? x[i] : 0;
+    yv[u] = i < i1 ? y[i] : 0;
+    tv[u] = (kFused && i < i1) ? __float_as_int(theta[i]) : 0;
+  }
   for (int t = threadIdx.x; t < w.nbins; t += kBlock) cur[t] = w.hist[static_cast<int64_t>(t) * w.nblk + b];
   __syncthreads();
-  const int i1 = min((b + 1) * kCoarseP, w.n);
-  for (int i = b * kCoarseP + threadIdx.x; i < i1; i += kBlock) {
-    const int xi = x[i], yi = y[i];
-    if (!in_box(xi, yi, w)) continue;
-    const int64_t c = static_cast<int64_t>(yi >> w.log2_w) * w.G + (xi >> w.log2_w);
+#pragma unroll
+  for (int u = 0; u < kCoarseU; ++u) {
+    const int i = i0 + u * kBlock;
+    if (i >= i1) break;
+    if (!in_box(xv[u], yv[u], w)) continue;
+    const int64_t c = static_cast<int64_t>(yv[u] >> w.log2_w) * w.G + (xv[u] >> w.log2_w);
     const int pos = atomicAdd(&cur[static_cast<int>(c >> w.sb)], 1);
     if (static_cast<uint32_t>(pos) >= static_cast<uint32_t>(w.n)) {  // inconsistent table
       set_err(w.hdr, NM_E_INVAL);
       continue;
     }
-    w.coarse[pos] = make_int4(xi, yi, i, kFused ? __float_as_int(theta[i]) : 0);
+    w.coarse[pos] = make_int4(xv[u], yv[u], i, tv[u]);
   }
 }
+
+// Per bin: counting sort of its particles by cell in LDS.  The first
+// kFineU entries of each lane stay in registers between the count and the
+// scatter (a bin holds about kFineU * kBlock particles at the mean density
+// the cell width is tuned for); entries beyond are read twice.
+constexpr int kFineU = 8;
 
 template <bool kFused>
 __global__ __launch_bounds__(kBlock) void k_fine_sort(DevWs w, uint32_t step_lo, uint32_t step_hi,
                                                       uint32_t sys_id, uint32_t seed_lo,
                                                       uint32_t seed_hi) {
-  __shared__ int h[kFineCells];
+  __shared__ __align__(16) int h[kFineCells];
   __shared__ int s_wsum[kBlock / 64];
   if (!ws_header_ok(w)) return;
   const int bin = blockIdx.x;
@@ -346,29 +375,54 @@ __global__ __launch_bounds__(kBlock) void k_fine_sort(DevWs w, uint32_t step_lo,
     if (threadIdx.x == 0) set_err(w.hdr, NM_E_INVAL);
     return;
   }
-  for (int t = threadIdx.x; t < S; t += kBlock) h[t] = 0;
-  __syncthreads();
   auto cell_of = [&](const int4& e) {
     return static_cast<int>(static_cast<int64_t>(e.y >> w.log2_w) * w.G + (e.x >> w.log2_w) - c0);
   };
-  for (int p = b0 + threadIdx.x; p < b1; p += kBlock) {
-    const int cl = cell_of(w.coarse[p]);
+  const int p0 = b0 + threadIdx.x;
+  int4 ev[kFineU];
+#pragma unroll
+  for (int u = 0; u < kFineU; ++u) {
+    const int p = p0 + u * kBlock;
+    ev[u] = p < b1 ? w.coarse[p] : make_int4(0, 0, 0, 0);
+  }
+  for (int t = threadIdx.x; t < S; t += kBlock) h[t] = 0;
+  __syncthreads();
+  auto count = [&](const int4& e) {
+    const int cl = cell_of(e);
     if (static_cast<uint32_t>(cl) < static_cast<uint32_t>(S))
       atomicAdd(&h[cl], 1);
     else
       set_err(w.hdr, NM_E_INVAL);  // inconsistent table
-  }
+  };
+#pragma unroll
+  for (int u = 0; u < kFineU; ++u)
+    if (p0 + u * kBlock < b1) count(ev[u]);
+  for (int p = p0 + kFineU * kBlock; p < b1; p += kBlock) count(w.coarse[p]);
   __syncthreads();
-  // exclusive prefix over the bin's cells: kFineCells / kBlock consecutive cells per lane
-  constexpr int kPer = kFineCells / kBlock;
-  const int j0 = threadIdx.x * kPer;
-  int cnt[kPer];
+  // Exclusive prefix over the bin's S cells (a power of two): lane t takes
+  // `per` consecutive cells, read and written as 16-byte vectors when per >= 4.
+  const int per = S >= kBlock ? S / kBlock : 1;
+  const int j0 = threadIdx.x * per;
+  constexpr int kMaxPer = kFineCells / kBlock;
+  int cnt[kMaxPer];
   int sum = 0;
 #pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    cnt[j] = j0 + j < S ? h[j0 + j] : 0;
-    sum += cnt[j];
+  for (int j = 0; j < kMaxPer; j += 4) {
+    if (j < per && j0 + j < S) {
+      if (per >= 4) {
+        const int4 v = *reinterpret_cast<const int4*>(&h[j0 + j]);
+        cnt[j] = v.x; cnt[j + 1] = v.y; cnt[j + 2] = v.z; cnt[j + 3] = v.w;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cnt[j + q] = (q < per) ? h[j0 + q] : 0;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cnt[j + q] = 0;
+    }
   }
+#pragma unroll
+  for (int j = 0; j < kMaxPer; ++j) sum += cnt[j];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int incl = sum;
 #pragma unroll
@@ -382,20 +436,37 @@ __global__ __launch_bounds__(kBlock) void k_fine_sort(DevWs w, uint32_t step_lo,
 #pragma unroll
   for (int q = 0; q < kBlock / 64; ++q)
     if (q < wave) run += s_wsum[q];
+  int ex[kMaxPer];
 #pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    if (j0 + j < S) {
-      h[j0 + j] = run;
-      w.start[c0 + j0 + j] = b0 + run;
-    }
+  for (int j = 0; j < kMaxPer; ++j) {
+    ex[j] = run;
     run += cnt[j];
+  }
+  if (j0 < S) {
+    if (per >= 4) {
+#pragma unroll
+      for (int j = 0; j < kMaxPer; j += 4) {
+        if (j < per) {
+          *reinterpret_cast<int4*>(&h[j0 + j]) = make_int4(ex[j], ex[j + 1], ex[j + 2], ex[j + 3]);
+          *reinterpret_cast<nm_int4u*>(&w.start[c0 + j0 + j]) =
+              nm_int4u{b0 + ex[j], b0 + ex[j + 1], b0 + ex[j + 2], b0 + ex[j + 3]};
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q < per) {
+          h[j0 + q] = ex[q];
+          w.start[c0 + j0 + q] = b0 + ex[q];
+        }
+      }
+    }
   }
   if (bin == w.nbins - 1 && threadIdx.x == 0) w.start[w.C] = b1;
   __syncthreads();
-  for (int p = b0 + threadIdx.x; p < b1; p += kBlock) {
-    const int4 e = w.coarse[p];
+  auto place = [&](const int4& e, int p) {
     const int cl = cell_of(e);
-    if (static_cast<uint32_t>(cl) >= static_cast<uint32_t>(S)) continue;
+    if (static_cast<uint32_t>(cl) >= static_cast<uint32_t>(S)) return;
     const int pos = b0 + atomicAdd(&h[cl], 1);
     uint32_t word = 0u;
     if (kFused) {
@@ -409,7 +480,12 @@ __global__ __launch_bounds__(kBlock) void k_fine_sort(DevWs w, uint32_t step_lo,
       w.cs[2 * pos + 1] = make_double2(xc, xs);  // the random unit vector xi of Eq. (2)
     }
     w.sorted[pos] = make_int4(e.x, e.y, e.z, static_cast<int>(word));
-  }
+    (void)p;
+  };
+#pragma unroll
+  for (int u = 0; u < kFineU; ++u)
+    if (p0 + u * kBlock < b1) place(ev[u], p0 + u * kBlock);
+  for (int p = p0 + kFineU * kBlock; p < b1; p += kBlock) place(w.coarse[p], p);
   if (bin == 0 && threadIdx.x == 0) w.hdr->built = kBuilt;
 }
 

@@ -161,21 +161,37 @@ __device__ __forceinline__ bool strip_stage(const DevWs& w, const StripGeo& g, c
     if (s.qmap && qrow)
       for (int j = 0; j < qlen; ++j) s.qmap[qo + j] = static_cast<uint16_t>(rb + qrow_off + j);
     __syncthreads();
-    for (int pidx = threadIdx.x; pidx < npts; pidx += kBlock) {
-      const int r = s.rowid[pidx];
-      const int inrow = pidx - s.rbase[r];
-      const int n0 = s.n0[r];
-      const bool second = inrow >= n0;
-      const int src = second ? s.ga1[r] + (inrow - n0) : s.ga0[r] + inrow;
-      const int sx = (second ? (uL < 0 ? 0 : L) : (uL < 0 ? -L : 0)) - ox0;
-      const int v = g.y0 - hy + r;
-      const int sy = (v < 0 ? -L : (v >= G ? L : 0)) - oy0;
-      const int4 e = w.sorted[src];
-      if (g.wide)
-        s.lpos_store[pidx] = make_int2(e.x + sx, e.y + sy);
-      else
-        lpos[pidx] = pack_rel(e.x + sx, e.y + sy);
-      s.lslot[pidx] = kStoreIndex ? e.z : src;
+    constexpr int kCopyU = 4;  // particles per thread per round: their loads go out together
+    for (int base = threadIdx.x; base < npts; base += kCopyU * kBlock) {
+      int4 e[kCopyU];
+      int ox[kCopyU], oy[kCopyU], sv[kCopyU];
+#pragma unroll
+      for (int u = 0; u < kCopyU; ++u) {
+        const int pidx = base + u * kBlock;
+        if (pidx < npts) {
+          const int r = s.rowid[pidx];
+          const int inrow = pidx - s.rbase[r];
+          const int n0 = s.n0[r];
+          const bool second = inrow >= n0;
+          const int src = second ? s.ga1[r] + (inrow - n0) : s.ga0[r] + inrow;
+          ox[u] = (second ? (uL < 0 ? 0 : L) : (uL < 0 ? -L : 0)) - ox0;
+          const int v = g.y0 - hy + r;
+          oy[u] = (v < 0 ? -L : (v >= G ? L : 0)) - oy0;
+          sv[u] = src;
+          e[u] = w.sorted[src];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kCopyU; ++u) {
+        const int pidx = base + u * kBlock;
+        if (pidx < npts) {
+          if (g.wide)
+            s.lpos_store[pidx] = make_int2(e[u].x + ox[u], e[u].y + oy[u]);
+          else
+            lpos[pidx] = pack_rel(e[u].x + ox[u], e[u].y + oy[u]);
+          s.lslot[pidx] = kStoreIndex ? e[u].z : sv[u];
+        }
+      }
     }
     __syncthreads();
   }
