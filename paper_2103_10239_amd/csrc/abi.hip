@@ -74,10 +74,17 @@ bool make_layout(const nm_grid* g, Layout* out) {
   off += round_up(16 * static_cast<int64_t>(L.chunk_cap));
   L.off_vlist = off;
   off += round_up(4 * static_cast<int64_t>(g->n));
-  // two-level binning when a coarse bin of at most kFineCells cells suffices
+  // Two-level binning when a coarse bin of at most kFineCells cells suffices:
+  // at most kCoarseBins bins, each of about kBinTarget particles at the mean
+  // density where the cells allow.  The space is there from kCoarseMinBatch
+  // particles (the batched stages use it); a single system bins in two
+  // levels from kCoarseMinN.
   L.sb = 0;
   while ((L.C >> L.sb) > kCoarseBins) ++L.sb;
-  if ((int64_t(1) << L.sb) <= kFineCells && g->n >= kCoarseMinN) {
+  while ((int64_t(1) << L.sb) < kFineCells &&
+         (static_cast<int64_t>(g->n) << L.sb) < static_cast<int64_t>(kBinTarget) * L.C)
+    ++L.sb;
+  if ((int64_t(1) << L.sb) <= kFineCells && g->n >= kCoarseMinBatch) {
     L.nbins = static_cast<int32_t>((L.C + (int64_t(1) << L.sb) - 1) >> L.sb);
     L.nblk = (g->n + kCoarseP - 1) / kCoarseP;
     const int64_t hsize = static_cast<int64_t>(L.nbins) * L.nblk + 1;

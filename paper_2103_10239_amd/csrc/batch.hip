@@ -83,9 +83,17 @@ BatchSys make_batch_sys(const SysSpec& s, int k) {
   const int64_t big = std::max<int64_t>(lay.C, s.g.n);
   d.nitems[kStInit] = static_cast<int32_t>(
       std::max<int64_t>(1, std::min<int64_t>(64, (big + 4 * kBlock - 1) / (4 * kBlock))));
-  d.nitems[kStCount] = (s.g.n + kBlock - 1) / kBlock;
-  d.nitems[kStScan] = lay.nb_scan_c;
-  d.nitems[kStScatter] = (s.g.n + 4 * kBlock - 1) / (4 * kBlock);
+  if (lay.nbins > 0) {  // two levels: coarse count, table scan, coarse scatter, per-bin sort
+    d.nitems[kStCount] = lay.nblk;
+    d.nitems[kStScan] = lay.nb_scan_h;
+    d.nitems[kStScatter] = lay.nblk;
+    d.nitems[kStFine] = lay.nbins;
+  } else {
+    d.nitems[kStCount] = (s.g.n + kBlock - 1) / kBlock;
+    d.nitems[kStScan] = lay.nb_scan_c;
+    d.nitems[kStScatter] = (s.g.n + 4 * kBlock - 1) / (4 * kBlock);
+    d.nitems[kStFine] = 0;
+  }
   d.nitems[kStKnn] = d.f.split ? 0 : d.ntiles;
   d.nitems[kStKnnSplit] = d.f.split ? d.ntiles : 0;
   return d;
@@ -107,6 +115,7 @@ hipError_t enqueue_batch_step(const BatchRef& r, int k, bool advance, hipStream_
   hipError_t e = launch_batch_bin(r, kStCount, s);
   if (e == hipSuccess) e = launch_batch_bin(r, kStScan, s);
   if (e == hipSuccess) e = launch_batch_bin(r, kStScatter, s);
+  if (e == hipSuccess) e = launch_batch_bin(r, kStFine, s);
   if (e == hipSuccess) e = launch_batch_knn(r, k, s);
   if (e == hipSuccess && advance) e = launch_batch_advance(r, s);
   return e;
@@ -211,8 +220,11 @@ int64_t max_items(const nm_batch* b, int s) {
       const DevWs w = dev_ws(&g, lay, nullptr);  // geometry only
       const TileCfg tc = tile_cfg(w, fast_cfg(w, b->k, g.block), b->k);
       const int64_t tiles = static_cast<int64_t>(tc.ntx) * tc.nty;
-      best = std::max<int64_t>(best, 64 + (g.n + kBlock - 1) / kBlock + lay.nb_scan_c +
-                                         (g.n + 4 * kBlock - 1) / (4 * kBlock) + tiles);
+      const int64_t bin_items = lay.nbins > 0
+                                    ? 2 * static_cast<int64_t>(lay.nblk) + lay.nb_scan_h + lay.nbins
+                                    : (g.n + kBlock - 1) / kBlock + lay.nb_scan_c +
+                                          (g.n + 4 * kBlock - 1) / (4 * kBlock);
+      best = std::max<int64_t>(best, 64 + bin_items + tiles);
     }
   }
   return best;

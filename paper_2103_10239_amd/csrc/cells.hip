@@ -283,10 +283,9 @@ __device__ __forceinline__ bool in_box(int xi, int yi, const DevWs& w) {
 // a workgroup has its whole share in flight at once.
 constexpr int kCoarseU = kCoarseP / kBlock;
 
-__global__ __launch_bounds__(kBlock) void k_coarse_count(const int32_t* __restrict__ x,
-                                                         const int32_t* __restrict__ y, DevWs w) {
+__device__ __forceinline__ void coarse_count_body(const int32_t* __restrict__ x,
+                                                  const int32_t* __restrict__ y, const DevWs& w, int b) {
   __shared__ int h[kCoarseBins];
-  const int b = blockIdx.x;
   if (b == 0) {
     reset_scan(w.scan_h, w.nb_scan_h);
     if (threadIdx.x == 0) {
@@ -319,13 +318,18 @@ __global__ __launch_bounds__(kBlock) void k_coarse_count(const int32_t* __restri
     w.hist[static_cast<int64_t>(t) * w.nblk + b] = h[t];
 }
 
+__global__ __launch_bounds__(kBlock) void k_coarse_count(const int32_t* __restrict__ x,
+                                                         const int32_t* __restrict__ y, DevWs w) {
+  coarse_count_body(x, y, w, blockIdx.x);
+}
+
 template <bool kFused>
-__global__ __launch_bounds__(kBlock) void k_coarse_scatter(const int32_t* __restrict__ x,
-                                                           const int32_t* __restrict__ y,
-                                                           const float* __restrict__ theta, DevWs w) {
+__device__ __forceinline__ void coarse_scatter_body(const int32_t* __restrict__ x,
+                                                    const int32_t* __restrict__ y,
+                                                    const float* __restrict__ theta, const DevWs& w,
+                                                    int b) {
   __shared__ int cur[kCoarseBins];
   if (!ws_header_ok(w)) return;
-  const int b = blockIdx.x;
   const int i0 = b * kCoarseP + threadIdx.x, i1 = min((b + 1) * kCoarseP, w.n);
   int xv[kCoarseU], yv[kCoarseU], tv[kCoarseU];
 #pragma unroll
@@ -352,6 +356,13 @@ __global__ __launch_bounds__(kBlock) void k_coarse_scatter(const int32_t* __rest
   }
 }
 
+template <bool kFused>
+__global__ __launch_bounds__(kBlock) void k_coarse_scatter(const int32_t* __restrict__ x,
+                                                           const int32_t* __restrict__ y,
+                                                           const float* __restrict__ theta, DevWs w) {
+  coarse_scatter_body<kFused>(x, y, theta, w, blockIdx.x);
+}
+
 // Per bin: counting sort of its particles by cell in LDS.  The first
 // kFineU entries of each lane stay in registers between the count and the
 // scatter (a bin holds about kFineU * kBlock particles at the mean density
@@ -359,13 +370,11 @@ __global__ __launch_bounds__(kBlock) void k_coarse_scatter(const int32_t* __rest
 constexpr int kFineU = 8;
 
 template <bool kFused>
-__global__ __launch_bounds__(kBlock) void k_fine_sort(DevWs w, uint32_t step_lo, uint32_t step_hi,
-                                                      uint32_t sys_id, uint32_t seed_lo,
-                                                      uint32_t seed_hi) {
+__device__ __forceinline__ void fine_sort_body(const DevWs& w, int bin, uint32_t step_lo, uint32_t step_hi,
+                                               uint32_t sys_id, uint32_t seed_lo, uint32_t seed_hi) {
   __shared__ __align__(16) int h[kFineCells];
   __shared__ int s_wsum[kBlock / 64];
   if (!ws_header_ok(w)) return;
-  const int bin = blockIdx.x;
   const int64_t m = static_cast<int64_t>(w.nbins) * w.nblk;
   const int b0 = w.hist[static_cast<int64_t>(bin) * w.nblk];
   const int b1 = bin + 1 < w.nbins ? w.hist[static_cast<int64_t>(bin + 1) * w.nblk] : w.hist[m];
@@ -489,6 +498,13 @@ __global__ __launch_bounds__(kBlock) void k_fine_sort(DevWs w, uint32_t step_lo,
   if (bin == 0 && threadIdx.x == 0) w.hdr->built = kBuilt;
 }
 
+template <bool kFused>
+__global__ __launch_bounds__(kBlock) void k_fine_sort(DevWs w, uint32_t step_lo, uint32_t step_hi,
+                                                      uint32_t sys_id, uint32_t seed_lo,
+                                                      uint32_t seed_hi) {
+  fine_sort_body<kFused>(w, blockIdx.x, step_lo, step_hi, sys_id, seed_lo, seed_hi);
+}
+
 // ---------------------------------------------------------------------------
 // Batched stages.  Workgroup g of a persistent launch takes the stage's items
 // g, g + gridDim.x, ...; an item is one workgroup's share of one system.
@@ -513,7 +529,11 @@ __global__ __launch_bounds__(kBlock) void k_bb_count(BatchRef b) {
   for (int it = blockIdx.x; it < ni; it += gridDim.x) {
     int li;
     const BatchSys& d = batch_item(b, kStCount, it, li);
-    bin_count_body(d.x[d.parity], d.y[d.parity], d.w, li);
+    if (d.w.nbins > 0)
+      coarse_count_body(d.x[d.parity], d.y[d.parity], d.w, li);
+    else
+      bin_count_body(d.x[d.parity], d.y[d.parity], d.w, li);
+    __syncthreads();  // the next item's LDS histogram
   }
 }
 
@@ -524,7 +544,10 @@ __global__ __launch_bounds__(kBlock) void k_bb_scan(BatchRef b) {
   for (int it = blockIdx.x; it < ni; it += gridDim.x) {
     int li;
     const BatchSys& d = batch_item(b, kStScan, it, li);
-    scan_body(d.w.count, d.w.start, d.w.C, d.w.scan_c, d.w.hdr, 1);
+    if (d.w.nbins > 0)
+      scan_body(d.w.hist, d.w.hist, static_cast<int64_t>(d.w.nbins) * d.w.nblk, d.w.scan_h, d.w.hdr, 0);
+    else
+      scan_body(d.w.count, d.w.start, d.w.C, d.w.scan_c, d.w.hdr, 1);
     __syncthreads();
   }
 }
@@ -535,8 +558,22 @@ __global__ __launch_bounds__(kBlock) void k_bb_scatter(BatchRef b) {
     int li;
     const BatchSys& d = batch_item(b, kStScatter, it, li);
     const int p = d.parity;
-    scatter_body<true>(d.x[p], d.y[p], d.th[p], d.w, li, d.step_lo, d.step_hi, d.sys_id,
-                       d.seed_lo, d.seed_hi);
+    if (d.w.nbins > 0)
+      coarse_scatter_body<true>(d.x[p], d.y[p], d.th[p], d.w, li);
+    else
+      scatter_body<true>(d.x[p], d.y[p], d.th[p], d.w, li, d.step_lo, d.step_hi, d.sys_id,
+                         d.seed_lo, d.seed_hi);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bb_fine(BatchRef b) {
+  const int ni = b.begin[kStFine + 1] - b.begin[kStFine];
+  for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+    int li;
+    const BatchSys& d = batch_item(b, kStFine, it, li);
+    fine_sort_body<true>(d.w, li, d.step_lo, d.step_hi, d.sys_id, d.seed_lo, d.seed_hi);
+    __syncthreads();
   }
 }
 
@@ -552,7 +589,7 @@ hipError_t launch_ws_init(const DevWs& w, hipStream_t s) {
 hipError_t launch_build(const DevWs& w, const int32_t* x, const int32_t* y, const float* theta,
                         const nm_params* p, uint64_t step, hipStream_t s) {
   const bool fused = theta != nullptr && p != nullptr;
-  if (w.nbins > 0) {  // two-level
+  if (w.nbins > 0 && w.n >= kCoarseMinN) {  // two-level
     hipLaunchKernelGGL(k_coarse_count, dim3(w.nblk), dim3(kBlock), 0, s, x, y, w);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -616,6 +653,7 @@ hipError_t launch_batch_bin(const BatchRef& b, int stage, hipStream_t s) {
     case kStCount: k = reinterpret_cast<const void*>(k_bb_count); break;
     case kStScan: k = reinterpret_cast<const void*>(k_bb_scan); break;
     case kStScatter: k = reinterpret_cast<const void*>(k_bb_scatter); break;
+    case kStFine: k = reinterpret_cast<const void*>(k_bb_fine); break;
     default: return hipErrorInvalidValue;
   }
   const int grid = batch_grid(k, items);
@@ -623,7 +661,8 @@ hipError_t launch_batch_bin(const BatchRef& b, int stage, hipStream_t s) {
     case kStInit: hipLaunchKernelGGL(k_bb_init, dim3(grid), dim3(kBlock), 0, s, b); break;
     case kStCount: hipLaunchKernelGGL(k_bb_count, dim3(grid), dim3(kBlock), 0, s, b); break;
     case kStScan: hipLaunchKernelGGL(k_bb_scan, dim3(grid), dim3(kBlock), 0, s, b); break;
-    default: hipLaunchKernelGGL(k_bb_scatter, dim3(grid), dim3(kBlock), 0, s, b); break;
+    case kStScatter: hipLaunchKernelGGL(k_bb_scatter, dim3(grid), dim3(kBlock), 0, s, b); break;
+    default: hipLaunchKernelGGL(k_bb_fine, dim3(grid), dim3(kBlock), 0, s, b); break;
   }
   return hipGetLastError();
 }

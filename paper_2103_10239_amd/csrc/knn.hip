@@ -237,7 +237,10 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
     rv[t] = 0;
     if (t >= KMAX - k) {
       const int4 e = w.sorted[slot[t]];
-      rv[t] = e.z;
+      if constexpr (kRowVec<KMAX>)
+        rv[t] = e.z;
+      else
+        row[t - (KMAX - k)] = e.z;
       if (!kAlign && d2out) {
         const int ex = wrap_axis(e.x - q.x, sh), ey = wrap_axis(e.y - q.y, sh);
         d2out[static_cast<int64_t>(q.z) * k + t - (KMAX - k)] =
@@ -250,7 +253,7 @@ __device__ __forceinline__ void finish_query(const DevWs& w, int s, const int4& 
       }
     }
   }
-  store_row<KMAX>(row, rv, k);
+  if constexpr (kRowVec<KMAX>) store_row<KMAX>(row, rv, k);
   if (!kAlign) return;
 
   // Eq. (2): average of the neighbours' unit vectors (plus the particle's own),
@@ -688,7 +691,10 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
       rv[t] = 0;
       if (t >= KMAX - k) {
         const int i = nb[t];
-        rv[t] = lidx[i];
+        if constexpr (kRowVec<KMAX>)
+          rv[t] = lidx[i];
+        else
+          row[t - (KMAX - k)] = lidx[i];
         if (!kAlign && d2out)
           d2out[static_cast<int64_t>(qi) * k + t - (KMAX - k)] =
               wide ? staged_d2<true>(lpos, i, pq, pqy) : staged_d2<false>(lpos, i, pq, pqy);
@@ -699,7 +705,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
         }
       }
     }
-    store_row<KMAX>(row, rv, k);
+    if constexpr (kRowVec<KMAX>) store_row<KMAX>(row, rv, k);
     if (kAlign) {
       // Eq. (2) and Eq. (1) as in finish_query, the position from the staged copy
       const double2 own = w.cs[2 * s];
@@ -856,8 +862,14 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   }
 }
 
+// Waves per SIMD asked of the compiler for the larger lists: their insertion
+// networks would otherwise take the kernel to 2 (KMAX 16-20) or 3 (KMAX 12)
+// waves per SIMD, which cost more than the few cold spills the limit adds.
+template <int KMAX>
+constexpr int kKnnWaves = (KMAX >= 16 && KMAX <= 20) ? 3 : (KMAX == 12 ? 4 : 1);
+
 template <int KMAX, bool kAlign, int kMode>
-__global__ __launch_bounds__(kBlock) void k_knn(DevWs w, FastCfg f, TileCfg tc, int k,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kKnnWaves<KMAX>))) void k_knn(DevWs w, FastCfg f, TileCfg tc, int k,
                                                 int32_t* __restrict__ nbr,
                                                 long long* __restrict__ d2out, AlignArgs a) {
   knn_tile_body<KMAX, kAlign, kMode>(w, f, tc, k, nbr, d2out, a, xcd_tile(blockIdx.x, gridDim.x));
@@ -905,7 +917,7 @@ __device__ __forceinline__ AlignArgs uniform_load_align(const BatchSys* d) {
 }
 
 template <int KMAX, int kMode>
-__global__ __launch_bounds__(kBlock) void k_bb_knn(BatchRef b, int k) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kKnnWaves<KMAX>))) void k_bb_knn(BatchRef b, int k) {
   constexpr int kSt = kMode == kOverflowSplit ? kStKnnSplit : kStKnn;
   const int ni = b.begin[kSt + 1] - b.begin[kSt];
   const int per = gridDim.x & ~7;  // whole rounds of the 8 XCDs

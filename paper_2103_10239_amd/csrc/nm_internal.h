@@ -38,7 +38,9 @@ constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kCoarseBins = 1024;
 constexpr int kCoarseP = 4096;
 constexpr int kFineCells = 4096;  // cells per coarse bin the LDS sort takes (else one-level)
-constexpr int kCoarseMinN = 1 << 17;  // smaller systems: one-level binning (fewer launches)
+constexpr int kCoarseMinN = 1 << 17;  // smaller single systems: one-level binning (fewer launches)
+constexpr int kCoarseMinBatch = 1024;  // the batched stages bin systems from this size in two levels
+constexpr int kBinTarget = 1024;      // particles a coarse bin should hold at the mean density
 constexpr uint32_t kMagic = 0x4E4D5753u;  // "NMWS"
 constexpr uint32_t kBuilt = 0x42554C54u;  // "BULT"
 constexpr int kKeyIndexBits = 24;         // particle index field of a search key
@@ -383,6 +385,12 @@ __device__ __forceinline__ uint32_t key32_d(uint32_t kk) { return kk >> 13; }
 typedef int nm_int4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef int nm_int3u __attribute__((ext_vector_type(3), aligned(4)));
 typedef int nm_int2u __attribute__((ext_vector_type(2), aligned(4)));
+// Only short rows are gathered for vector stores: holding a longer row in
+// registers until its last entry raises the register count of the kernels
+// with large KMAX past what the stores save.
+template <int KMAX>
+constexpr bool kRowVec = KMAX <= 8;
+
 template <int KMAX>
 __device__ __forceinline__ void store_row(int32_t* row, const int (&v)[KMAX], int k) {
   if (k == KMAX) {
@@ -555,7 +563,11 @@ struct AlignArgs {
 // ---------------------------------------------------------------------------
 // The k-NN stage is two: systems whose grid uses the sub-strip kernel
 // (NM_BLOCK_SUBSTRIPS) have their tiles in kStKnnSplit, the others in kStKnn.
-enum BatchStage { kStInit = 0, kStCount, kStScan, kStScatter, kStKnn, kStKnnSplit, kStages };
+// Systems binned in two levels (workspace nbins > 0) run the coarse count,
+// the scan of their bin x block table, the coarse scatter and the per-bin
+// sort in kStCount, kStScan, kStScatter and kStFine; the others run the
+// one-level count, scan and scatter and have no kStFine items.
+enum BatchStage { kStInit = 0, kStCount, kStScan, kStScatter, kStFine, kStKnn, kStKnnSplit, kStages };
 
 struct BatchSys {
   DevWs w;

@@ -190,6 +190,43 @@ def test_batch_reports_out_of_range_coordinate():
     b.close()
 
 
+@pytest.mark.parametrize("k", [7, 12])
+def test_batch_two_level_binning_matches_plain_steps(k):
+    # systems from 1024 particles are binned in two levels by the batched
+    # stages, while the plain calls bin them in one level below 2^17: the
+    # order inside a cell differs, every output must not; the smallest and
+    # the largest system take the one-level and two-level paths on both sides
+    sizes = [1023, 1024, 4096, 70000, 140000, 300, 2049]
+    xs, ys, ts = _systems(sizes, clustered_every=2, seed=41)
+    p = nm.make_params(L, v0=64, eta=0.2, seed=99)
+    b = nm.Batch(sizes, np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), k, p)
+    nsteps = 3
+    b.step(nsteps, use_graph=True)
+    torch.cuda.synchronize()
+    assert b.check() == 0
+    for s, n in enumerate(sizes):
+        ps = nm.make_params(L, v0=64, eta=0.2, seed=99, sys_id=s)
+        ex, ey, et, en = _plain_run(xs[s], ys[s], ts[s], k, ps, nsteps)
+        bx, by, bth, bn = (t.cpu().numpy() for t in b.system(s))
+        assert np.array_equal(bx, ex) and np.array_equal(by, ey), f"system {s} (n={n})"
+        assert np.array_equal(bth.view(np.uint32), et.view(np.uint32)), f"system {s} (n={n})"
+        assert np.array_equal(bn, en), f"system {s} (n={n})"
+    b.close()
+
+
+def test_batch_two_level_reports_out_of_range_coordinate():
+    sizes = [1500, 3000, 1200]
+    xs, ys, ts = _systems(sizes)
+    y = np.concatenate(ys)
+    y[2000] = -3  # a coordinate of system 1 outside the box
+    p = nm.make_params(L, v0=64, eta=0.2, seed=1)
+    b = nm.Batch(sizes, np.concatenate(xs), y, np.concatenate(ts), 7, p)
+    b.step(1)
+    assert b.check() == nm.NM_E_RANGE
+    assert b.check() == 0  # cleared
+    b.close()
+
+
 def test_batch_plan_rejects_bad_arguments():
     p = nm.make_params(L)
     with pytest.raises(nm.NMError):
