@@ -375,23 +375,32 @@ __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, 
 #pragma unroll
     for (int t = 0; t < KS; ++t) kl[t] = (t < KS - (k + 1 + (kWithSelf ? 1 : 0))) ? 0u : kKey32Inf;
     const int sh = b.sh;
+    // wide strips: the bound rounded down to fp32 (so that a clamped field
+    // stays below 2^19) and the exact scale 2^-sh
+    float boundf = static_cast<float>(b.bound);
+    if (static_cast<long long>(boundf) > b.bound) boundf = nextafterf(boundf, 0.0f);
+    const float scale = ldexpf(1.0f, -sh);
     const int a = rbase[b.r0], e = rbase[b.r0 + Bq];
     // One round: candidates i .. i + kUnroll - 1.  Only the last round of a
     // block (tail) can pass its end; it masks what lies beyond.
     auto round = [&](int i, bool tail) {
       uint32_t kk[kUnroll];
       if (kWide) {
+        // fp32 squared distances: the offsets are exact (below 2^24), the
+        // square and the sum round twice (relative error below 2^-23, an
+        // eighth of a distance-field unit), so every field is within one of
+        // the exact one; the certificate below widens its margins to match.
         int2 pc[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) pc[u] = lpos2[i + u];  // (buffer padded by kUnroll)
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const long long dx = pc[u].x - pq, dy = pc[u].y - pqy;
-          const unsigned long long d2 = static_cast<unsigned long long>(dx * dx + dy * dy);
-          kk[u] = (static_cast<uint32_t>(min(d2, static_cast<unsigned long long>(b.bound)) >> sh) << 13) |
-                  static_cast<uint32_t>(i + u);
+          const int dxi = pc[u].x - pq, dyi = pc[u].y - pqy;
+          const float dx = static_cast<float>(dxi), dy = static_cast<float>(dyi);
+          const float d2 = fmaf(dy, dy, dx * dx);
+          kk[u] = (static_cast<uint32_t>(fminf(d2, boundf) * scale) << 13) | static_cast<uint32_t>(i + u);
           if constexpr (Filter::kActive)
-            if (!filt.visible(dx, dy)) kk[u] = kKey32Inf;
+            if (!filt.visible(static_cast<long long>(dxi), static_cast<long long>(dyi))) kk[u] = kKey32Inf;
         }
       } else {
         int pc[kUnroll];
@@ -430,8 +439,13 @@ __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, 
 #pragma unroll
       for (int t = 0; t < KT; ++t) key[t] = kl[t];
     }
+    // Certificate (fields exact, or within one of exact on wide strips: M = 2):
+    // the k-th lies inside the block, the (k+1)-th is strictly farther than
+    // the k-th, and fields closer than M + 1 inside the k are re-sorted by
+    // the exact (d^2, index).
+    constexpr uint32_t M = kWide ? 2u : 0u;
     const uint32_t kth = key[KT - 2];
-    const long long dmax = (static_cast<long long>(key32_d(kth) + 1) << sh) - 1;
+    const long long dmax = (static_cast<long long>(key32_d(kth) + 1 + M / 2) << sh) - 1;
     if (kth == kKey32Inf || dmax >= b.bound) {
       if (attempt == 0 && Bq + 2 <= tc.bmax) {
         Bq += 2;
@@ -439,11 +453,11 @@ __device__ __forceinline__ bool strip_search(const DevWs& w, const TileCfg& tc, 
       }
       return false;
     }
-    if (key32_d(kth) >= key32_d(key[KT - 1])) return false;
+    if (key32_d(kth) + M >= key32_d(key[KT - 1])) return false;
     bool tied = false;
 #pragma unroll
     for (int t = 0; t < KT - 2; ++t)
-      if (t >= KT - (k + 1)) tied = tied || (key32_d(key[t]) == key32_d(key[t + 1]));
+      if (t >= KT - (k + 1)) tied = tied || (key32_d(key[t + 1]) - key32_d(key[t]) <= M);
 #pragma unroll
     for (int t = 0; t < KMAX; ++t)
       if (t >= KMAX - k) lds[t] = static_cast<int>(key[t] & 0x1FFFu);
