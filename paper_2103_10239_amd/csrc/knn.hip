@@ -876,11 +876,13 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   }
 }
 
-// Waves per SIMD asked of the compiler for the larger lists: their insertion
-// networks would otherwise take the kernel to 2 (KMAX 16-20) or 3 (KMAX 12)
-// waves per SIMD, which cost more than the few cold spills the limit adds.
+// Waves per SIMD asked of the compiler: five for the short lists (96 VGPRs,
+// which the LDS of a strip also allows), four for KMAX 12 and three for
+// KMAX 16-20, whose insertion networks would otherwise take the kernel to
+// three or two; the few cold spills these limits add cost less than the
+// waves they gain.
 template <int KMAX>
-constexpr int kKnnWaves = (KMAX >= 16 && KMAX <= 20) ? 3 : (KMAX == 12 ? 4 : 1);
+constexpr int kKnnWaves = (KMAX >= 16 && KMAX <= 20) ? 3 : (KMAX == 12 ? 4 : (KMAX <= 8 ? 5 : 1));
 
 template <int KMAX, bool kAlign, int kMode>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kKnnWaves<KMAX>))) void k_knn(DevWs w, FastCfg f, TileCfg tc, int k,
@@ -992,7 +994,7 @@ TileCfg tile_cfg_impl(const DevWs& w, const FastCfg& f, int k, bool narrow_strip
   // sub-strip kernel, whose larger halos overflow LDS more often, and the
   // field-of-view lists, whose blocks span every column of the strip.
   int tw = narrow_strips ? (hx >= 3 ? 2 : 1) : (hx >= 3 ? 4 : (hx >= 2 ? 2 : 1));
-  while (tw < 16 && 2 * tw <= w.G && 256.0 / (tw * rr) > 1.1 * (kStripRows - 2 * hy)) tw *= 2;
+  while (tw < 16 && 2 * tw <= w.G && 256.0 / (tw * rr) > 1.1 * (kTwRows - 2 * hy)) tw *= 2;
   while (hx > 1 && tw + 2 * hx > w.G) --hx;
   while (hy > 1 && 2 * hy + 1 > w.G) --hy;
   if (tw + 2 * hx > w.G || 2 * hy + 1 > w.G) return plain();

@@ -95,7 +95,7 @@ MetricCfg metric_cfg(const DevWs& w, long long rc2) {
   if (h < 1 || 4 * h + 1 > kStripRows || 2 * h + 1 > w.G) return plain();
   // two columns once the halo is two wide (each particle staged fewer times)
   int tw = h >= 2 ? 2 : 1;
-  while (tw < 16 && 2 * tw <= w.G && 256.0 / (tw * rr) > 1.1 * (kStripRows - 2 * h)) tw *= 2;
+  while (tw < 16 && 2 * tw <= w.G && 256.0 / (tw * rr) > 1.1 * (kTwRows - 2 * h)) tw *= 2;
   if (tw + 2 * h > w.G) return plain();
   const int W = tw + 2 * h;
   const bool narrow = (static_cast<long long>(W) << w.log2_w) < 32768 &&

@@ -20,8 +20,9 @@
 namespace nm {
 
 constexpr int kStripPts = 2560;           // staged particles (wide strips: half)
-constexpr int kStripRows = 256;           // R <= kStripRows
+constexpr int kStripRows = 128;           // R <= kStripRows (row tables small enough for 5 strips per CU)
 constexpr int kRowStep = kStripRows / 2;  // binary search over <= kStripRows rows
+constexpr int kTwRows = 256;              // strips widen while ~256 queries need more rows than this
 constexpr int kUnroll = 4;                // candidates read per round of a block loop
 
 // Exclusive prefix sum of v over the workgroup (thread order); *total gets
