@@ -595,13 +595,16 @@ struct FillOp {
     if (!fill_row(w, offsets, nnz, v.lidx[q.self], base, m) || m == 0) return true;
     const long long visits = ((m + kChunk - 1) / kChunk) * static_cast<long long>(q.hi - q.lo);
     if (m <= kWaveKeys && visits > kHeavyWork) return false;
+    // One network width per wavefront: lanes of one wavefront taking the 8- and
+    // the 16-wide network would run both, one after the other.
+    const bool wide16 = __ballot(m > 8) != 0ull;
     bool done;
     if (v.wide)
-      done = m <= 8 ? strip_fill32<8, true>(q, v, rc2, sh, m, idx + base)
-                    : strip_fill32<kChunk, true>(q, v, rc2, sh, m, idx + base);
+      done = !wide16 ? strip_fill32<8, true>(q, v, rc2, sh, m, idx + base)
+                     : strip_fill32<kChunk, true>(q, v, rc2, sh, m, idx + base);
     else
-      done = m <= 8 ? strip_fill32<8, false>(q, v, rc2, sh, m, idx + base)
-                    : strip_fill32<kChunk, false>(q, v, rc2, sh, m, idx + base);
+      done = !wide16 ? strip_fill32<8, false>(q, v, rc2, sh, m, idx + base)
+                     : strip_fill32<kChunk, false>(q, v, rc2, sh, m, idx + base);
     if (!done && !strip_fill(q, v, rc2, m, idx + base)) set_err(w.hdr, NM_E_INVAL);
     return true;
   }
