@@ -30,7 +30,8 @@ Beside it, on the same GPU:
            update against a rebuild every step)
 
 roofline: the fused k-NN + alignment kernel (k_knn<7, align>) bracketed by
-HIP events on the stream it runs on; its algorithmic traffic is 24 + 4k bytes
+HIP events on the stream it runs on, on every 4th timed step (an event pair
+inside every step would add a barrier to each); its algorithmic traffic is 24 + 4k bytes
 per particle-step (read x, y, theta; write the k indices and x', y',
 theta'), priced against the 8 TB/s HBM peak.  `traffic` is the DRAM traffic
 per launch that rocprofv3 counters measured for the same kernel source (null
@@ -52,6 +53,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_EVENT_EVERY = 4  # timed steps per kernel-time sample
 METRIC = "particle-steps/s (k=7 kNN rebuild + align) at N=1M; batched p50/p99 latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_knn_align_uniform_1m_k7.json")
 KERNEL_SOURCES = ("knn.hip", "strip.h", "nm_internal.h")
@@ -227,12 +229,15 @@ def bench_single(args, torch, nm, workloads):
     if nm.check(ws) != 0:
         raise RuntimeError("device error during warmup")
     log("[bench] warmup done")
+    # HIP events around the k-NN + align kernel on every KERNEL_EVENT_EVERY-th
+    # timed step: an event pair between the two calls of a step puts a
+    # barrier between its kernels that costs about 6 us per step (4%).
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
+              for _ in range(0, args.steps, KERNEL_EVENT_EVERY)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        one_step(events[i])
+        one_step(events[i // KERNEL_EVENT_EVERY] if i % KERNEL_EVENT_EVERY == 0 else None)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     status = nm.check(ws)
@@ -244,7 +249,7 @@ def bench_single(args, torch, nm, workloads):
     log(f"[bench] timed {args.steps} steps: {ms_step:.4f} ms/step, k-NN+align kernel {k_ms:.4f} ms")
     log(f"[bench] grids used: {sorted(grids)}")
     return {"x": x, "y": y, "th": th, "ms_step": ms_step, "k_ms": k_ms, "k_p50": pct(kms, 50),
-            "k_p99": pct(kms, 99), "cell_w": cell_w, "block": block, "tuned": tuned,
+            "k_p99": pct(kms, 99), "k_n": len(kms), "cell_w": cell_w, "block": block, "tuned": tuned,
             "grids": sorted(grids)}
 
 
@@ -818,6 +823,8 @@ def main():
             "kernel_ms_avg": r["k_ms"],
             "kernel_ms_p50": r["k_p50"],
             "kernel_ms_p99": r["k_p99"],
+            "kernel_launches_timed": r["k_n"],
+            "kernel_timed_every": KERNEL_EVENT_EVERY,
             # in a kernel trace of this process, the timed launches are this
             # kernel's launches [first, first + steps): the tuner's candidate
             # steps (one untimed and five timed each) and the warm-up come first
