@@ -628,7 +628,29 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   const StripBox tb = strip_box(w, tc, tile);
   const int G = w.G, lw = w.log2_w;
   const int total = min(w.start[w.C], w.n);
-  const int tw = tc.tw, hx = tc.hx, hy = tc.hy;
+  const int tw = tc.tw, hy = tc.hy;
+  // The sub-strip kernel (chosen for clustered systems) takes each strip's
+  // halo width from the strip's own density, never wider than the grid's:
+  // dense strips get narrower blocks (6% less time at k = 20 on the clustered
+  // state; the extra pass over the strip's rows costs the default kernel 7%
+  // on uniform systems, which keep the grid's width).
+  int hx = tc.hx;
+  if (kMode == kOverflowSplit && hx > 1) {
+    int q = 0;
+    if (static_cast<int>(threadIdx.x) < tb.ty) {
+      const int64_t prow = static_cast<int64_t>(tb.y0 + threadIdx.x) * G;
+      q = max(min(w.start[prow + tb.x0 + tw], total) - w.start[prow + tb.x0], 0);
+    }
+    int nqs;
+    (void)block_exclusive_scan(q, s_wsum, &nqs);
+    if (nqs > 0) {
+      const float rho = static_cast<float>(nqs) / static_cast<float>(tw * tb.ty);
+      int hs = static_cast<int>(
+          ceilf(static_cast<float>(kReachX) * sqrtf(static_cast<float>(k) / (3.14159265f * rho))));
+      if (f.bfix > 0) hs = max(hs, f.bfix / 2);
+      hx = max(1, min(hs, tc.hx));
+    }
+  }
   const int W = tw + 2 * hx;
   const int uL = tb.x0 - hx;
   const int lane = threadIdx.x & 63;
@@ -877,12 +899,11 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
 }
 
 // Waves per SIMD asked of the compiler: five for the short lists (96 VGPRs,
-// which the LDS of a strip also allows), four for KMAX 12 and three for
-// KMAX 16-20, whose insertion networks would otherwise take the kernel to
-// three or two; the few cold spills these limits add cost less than the
-// waves they gain.
+// which the LDS of a strip also allows), four for KMAX 12-20, whose insertion
+// networks would otherwise take the kernel to three or two; the spills these
+// limits add (cold for k <= 12) cost less than the waves they gain.
 template <int KMAX>
-constexpr int kKnnWaves = (KMAX >= 16 && KMAX <= 20) ? 3 : (KMAX == 12 ? 4 : (KMAX <= 8 ? 5 : 1));
+constexpr int kKnnWaves = (KMAX >= 12 && KMAX <= 20) ? 4 : (KMAX <= 8 ? 5 : 1);
 
 template <int KMAX, bool kAlign, int kMode>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kKnnWaves<KMAX>))) void k_knn(DevWs w, FastCfg f, TileCfg tc, int k,
