@@ -376,15 +376,31 @@ struct CountOp {
   unsigned long long rc2;
   __device__ bool light(const DevWs&, const StagedQuery& q, const StripView& v) const {
     if (q.hi - q.lo > kHeavyRange) return false;
+    // The query itself (distance 0, inside its own range) is counted with the
+    // others and taken off at the end.  Whole rounds run without an end check;
+    // only the range's last round masks what lies beyond it (staging is
+    // padded by kUnroll entries).
     int cnt = 0;
-    for (int i = q.lo; i < q.hi; i += kUnroll) {
+    const int full = q.lo + ((q.hi - q.lo) & ~(kUnroll - 1));
+    if (v.wide) {
+      auto round = [&](int i, bool tail) {
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const long long d2 = v.d2(i + u, q);  // staging is padded by kUnroll entries
-        cnt += (i + u < q.hi && i + u != q.self && static_cast<unsigned long long>(d2) <= rc2) ? 1 : 0;
-      }
+        for (int u = 0; u < kUnroll; ++u)
+          cnt += ((!tail || i + u < q.hi) && static_cast<unsigned long long>(v.d2(i + u, q)) <= rc2) ? 1 : 0;
+      };
+      for (int i = q.lo; i < full; i += kUnroll) round(i, false);
+      if (full < q.hi) round(full, true);
+    } else {
+      const uint32_t r32 = static_cast<uint32_t>(min(rc2, 0xFFFFFFFFull));
+      auto round = [&](int i, bool tail) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          cnt += ((!tail || i + u < q.hi) && rel_d2_u(v.lpos[i + u], q.pq) <= r32) ? 1 : 0;
+      };
+      for (int i = q.lo; i < full; i += kUnroll) round(i, false);
+      if (full < q.hi) round(full, true);
     }
-    offsets[v.lidx[q.self]] = cnt;
+    offsets[v.lidx[q.self]] = cnt - 1;
     return true;
   }
   // One wave: the same count over the staged range.
@@ -481,7 +497,9 @@ __device__ __forceinline__ bool strip_fill32(const StagedQuery& q, const StripVi
     uint32_t key[KT];
 #pragma unroll
     for (int t = 0; t < KT; ++t) key[t] = (t < KT - need) ? 0u : kKey32Inf;
-    for (int i = q.lo; i < q.hi; i += kUnroll) {
+    // whole rounds without an end check; only the range's last round masks
+    // what lies beyond it
+    auto round = [&](int i, bool tail) {
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         bool in;
@@ -491,14 +509,17 @@ __device__ __forceinline__ bool strip_fill32(const StagedQuery& q, const StripVi
           in = d2 <= rc2;
           dfield = static_cast<uint32_t>(d2 >> sh);
         } else {
-          const uint32_t d2 = static_cast<uint32_t>(rel_d2(v.lpos[i + u], q.pq));
+          const uint32_t d2 = rel_d2_u(v.lpos[i + u], q.pq);
           in = d2 <= static_cast<uint32_t>(rc2);
           dfield = d2 >> sh;
         }
         const uint32_t kk = (dfield << 13) | static_cast<uint32_t>(i + u);
-        net_insert(key, (in && i + u < q.hi && i + u != q.self && kk > last) ? kk : kKey32Inf);
+        net_insert(key, (in && (!tail || i + u < q.hi) && i + u != q.self && kk > last) ? kk : kKey32Inf);
       }
-    }
+    };
+    const int full = q.lo + ((q.hi - q.lo) & ~(kUnroll - 1));
+    for (int i = q.lo; i < full; i += kUnroll) round(i, false);
+    if (full < q.hi) round(full, true);
     if (key[KT - 1] == kKey32Inf) return false;
     bool good = key32_d(key[KT - need]) != prev_d;
 #pragma unroll

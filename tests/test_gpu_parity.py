@@ -466,6 +466,25 @@ def _gpu_knn_block(x, y, k, w, block):
     return nbr.cpu().numpy(), d2.cpu().numpy()
 
 
+@pytest.mark.parametrize("k", [4, 7, 8, 12])
+@pytest.mark.parametrize("block", [0, 4, nm.NM_BLOCK_SUBSTRIPS])
+def test_knn_wide_strips_near_ties(k, block):
+    # A 128 x 128 lattice (spacing 8192) jittered by at most 2 units.  Its
+    # strips are wide (blocks span more than 2^15 units), where the 32-bit
+    # keys take fp32 squared distances; many neighbours lie within a few
+    # distance-field units of each other, which the certificate must defer
+    # or re-sort by the exact (d^2, index).
+    x, y, a = workloads.lattice(128)
+    rng = np.random.default_rng(5)
+    x = ((x.astype(np.int64) + rng.integers(-2, 3, x.size)) % L).astype(np.int32)
+    y = ((y.astype(np.int64) + rng.integers(-2, 3, y.size)) % L).astype(np.int32)
+    lay = nm.knn_layout(len(x), L, a, block, k)
+    assert lay["wide"] == 1 and lay["kernel"] in (1, 2)
+    nbr, d2 = _gpu_knn_block(x, y, k, a, block)
+    rn, rd = oracle.knn(x, y, L, k)
+    assert np.array_equal(nbr, rn) and np.array_equal(d2, rd)
+
+
 @pytest.mark.parametrize("block", [-1, 0, 3, 4, 5, 6, 8, nm.NM_BLOCK_SUBSTRIPS, nm.NM_BLOCK_SUBSTRIPS | 5])
 @pytest.mark.parametrize("kind,n,k,w", [("uniform", 20013, 7, 4096), ("uniform", 20013, 1, 8192),
                                         ("uniform", 20013, 20, 4096), ("clustered", 20013, 12, 2048),
