@@ -780,7 +780,11 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   };
   if constexpr (kMode != kOverflowSplit) {
     int npts, nq;
+    // Staging is a chain of global reads and barriers: its waves issue first
+    // (wave priority), so that other strips' searches fill the gaps.
+    __builtin_amdgcn_s_setprio(3);
     const bool staged = strip_stage<true>(w, geo, strip_lds(), total, npts, nq);
+    __builtin_amdgcn_s_setprio(0);
     if (nq == 0) return;
     for (int qi = threadIdx.x; qi < nq; qi += kBlock) {
       if (staged) {
@@ -798,7 +802,9 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
     int next = -1, nsub = 0;  // the sub-strip to stage next (-1: none planned)
     for (;;) {
       int np_cur, nq_cur;
+      __builtin_amdgcn_s_setprio(3);
       const bool st = strip_stage<true>(w, geo, strip_lds(), total, np_cur, nq_cur);
+      __builtin_amdgcn_s_setprio(0);
       nq_cur = __builtin_amdgcn_readfirstlane(nq_cur);  // block-uniform: keep it scalar
       bool plan = false;
       if (next < 0) {
