@@ -9,8 +9,11 @@
 // staging of strip.h, with particle indices beside the positions): the disk of
 // radius r_c around any query lies inside the W halo columns of the 2h + 1
 // halo rows around its own, one contiguous LDS range, so no search is needed.
-// The fill selects each row in chunks of kChunk: a pass over the range keeps
-// the kChunk smallest exact (d^2, index) keys above the last one written.
+// The fill appends the LDS index of each hit to the lane's column of an LDS
+// buffer in one pass over the range, then orders the column by 32-bit keys
+// in a sorting network; rows too long for the column are selected in chunks
+// of kChunk, a pass over the range keeping the kChunk smallest exact
+// (d^2, index) keys above the last one written.
 // Strips whose halo does not fit LDS walk rings of cells in global memory.
 #include "strip.h"
 
@@ -114,8 +117,7 @@ MetricCfg metric_cfg(const DevWs& w, long long rc2) {
   return m;
 }
 
-constexpr int kHeavyRange = 768;  // count: staged candidates above which a wave takes the query
-constexpr int kHeavyWork = 1024;  // fill: candidate visits (passes x candidates) above which it does
+constexpr int kHeavyRange = 768;  // staged candidates above which a wave takes the query
 constexpr int kWaveKeys = 512;    // longest row a wave sorts in LDS
 constexpr int kWaves = kBlock / 64;
 constexpr int kChunkQ = 512;      // queries per chunk of a split strip
@@ -178,7 +180,7 @@ struct StripShared {
   uint8_t rowid[kStripPts];
   int4 chunk[kMaxChunks];  // this strip's chunks: {tile, r0 | r1 << 16 | unstaged << 30, qa, qb}
   int heavy[kChunkQ];      // queries of the current batch left to the waves
-  int nchunk, nlocal, nheavy;
+  int nchunk, nlocal, nheavy, nlane;
 };
 
 // Strip of tile `tile` as a strip geometry, rows [r0, r1) of it.
@@ -189,9 +191,14 @@ __device__ __forceinline__ StripGeo tile_geo(const DevWs& w, const MetricCfg& mc
   return StripGeo{txi * mc.tw, y0 + r0, r1 - r0, mc.tw, stage ? mc.h : 0, mc.h, mc.wide != 0};
 }
 
+// Where Op::light leaves a row: done, to one wave (Op::heavy) or to one lane
+// of a second sweep (Op::lane), so that rows of one kind share wavefronts.
+enum RowPath { kRowDone = 0, kRowWave = 1, kRowLane = 2 };
+
 // Queries [qa, qb) of the strip g just staged, in batches of kChunkQ: one
-// lane each runs Op::light; the rows it declines are then taken by one wave
-// each, Op::heavy, from the same staged data.  Without staging (`staged`
+// lane each runs Op::light; the rows it passes on are then taken, from the
+// same staged data, one lane each (Op::lane) or one wave each (Op::heavy);
+// both lists share S.heavy, from either end.  Without staging (`staged`
 // false) every query goes to the deferred list for the wave kernels.
 template <class Op>
 __device__ __forceinline__ void run_queries(const DevWs& w, const MetricCfg& mc, StripShared& S,
@@ -226,11 +233,19 @@ __device__ __forceinline__ void run_queries(const DevWs& w, const MetricCfg& mc,
   };
   for (int b0 = qa; b0 < qb; b0 += kChunkQ) {
     const int b1 = min(qb, b0 + kChunkQ);
-    if (threadIdx.x == 0) S.nheavy = 0;
+    if (threadIdx.x == 0) {
+      S.nheavy = 0;
+      S.nlane = 0;
+    }
     __syncthreads();
-    for (int qi = b0 + threadIdx.x; qi < b1; qi += kBlock)
-      if (!op.light(w, query(qi), view)) S.heavy[atomicAdd(&S.nheavy, 1)] = qi;
+    for (int qi = b0 + threadIdx.x; qi < b1; qi += kBlock) {
+      const int path = op.light(w, query(qi), view);
+      if (path == kRowWave) S.heavy[atomicAdd(&S.nheavy, 1)] = qi;
+      if (path == kRowLane) S.heavy[kChunkQ - 1 - atomicAdd(&S.nlane, 1)] = qi;
+    }
     __syncthreads();
+    const int nl = S.nlane;
+    for (int d = threadIdx.x; d < nl; d += kBlock) op.lane(w, query(S.heavy[kChunkQ - 1 - d]), view);
     const int nh = S.nheavy;
     for (int d = threadIdx.x >> 6; d < nh; d += kWaves) op.heavy(w, query(S.heavy[d]), view);
     __syncthreads();
@@ -249,7 +264,11 @@ __device__ __forceinline__ void run_chunk(const DevWs& w, const MetricCfg& mc, S
   const int r0 = c.y & 0x1FF, r1 = (c.y >> 16) & 0x1FF;
   const StripGeo g = tile_geo(w, mc, c.x, r0, r1, !unstaged);
   int npts, nq;
+  // Staging (global reads and barriers) issues first; other strips' searches
+  // fill its gaps.
+  __builtin_amdgcn_s_setprio(3);
   const bool staged = strip_stage<true>(w, g, strip_lds(S), total, npts, nq);
+  __builtin_amdgcn_s_setprio(0);
   run_queries(w, mc, S, g, staged, min(c.z, nq), min(c.w, nq), op);
   __syncthreads();  // LDS is restaged by the next chunk
 }
@@ -297,7 +316,9 @@ __device__ __forceinline__ void strip_tile(const DevWs& w, const MetricCfg& mc, 
   const int ty = min(mc.th, w.G - tyi * mc.th);
   const StripGeo geo = tile_geo(w, mc, tile, 0, ty, mc.stage != 0);
   int npts, nq;
+  __builtin_amdgcn_s_setprio(3);
   const bool staged = strip_stage<true>(w, geo, strip_lds(S), total, npts, nq);
+  __builtin_amdgcn_s_setprio(0);
   if (nq == 0) return;
   if (!mc.stage || (staged && nq <= kChunkQ)) {
     run_queries(w, mc, S, geo, staged, 0, nq, op);
@@ -374,8 +395,8 @@ struct CountOp {
   static constexpr int kPass = 0;
   int32_t* offsets;
   unsigned long long rc2;
-  __device__ bool light(const DevWs&, const StagedQuery& q, const StripView& v) const {
-    if (q.hi - q.lo > kHeavyRange) return false;
+  __device__ __forceinline__ int light(const DevWs&, const StagedQuery& q, const StripView& v) const {
+    if (q.hi - q.lo > kHeavyRange) return kRowWave;
     // The query itself (distance 0, inside its own range) is counted with the
     // others and taken off at the end.  Whole rounds run without an end check;
     // only the range's last round masks what lies beyond it (staging is
@@ -401,10 +422,11 @@ struct CountOp {
       if (full < q.hi) round(full, true);
     }
     offsets[v.lidx[q.self]] = cnt - 1;
-    return true;
+    return kRowDone;
   }
+  __device__ __forceinline__ void lane(const DevWs&, const StagedQuery&, const StripView&) const {}
   // One wave: the same count over the staged range.
-  __device__ void heavy(const DevWs&, const StagedQuery& q, const StripView& v) const {
+  __device__ __forceinline__ void heavy(const DevWs&, const StagedQuery& q, const StripView& v) const {
     int cnt = 0;
     for (int i0 = q.lo; i0 < q.hi; i0 += 64) {
       const int i = i0 + static_cast<int>(threadIdx.x & 63);
@@ -443,8 +465,9 @@ __global__ __launch_bounds__(kBlock) void k_metric_count_waves(DevWs w, long lon
 // Rows of the fill: offset and length of row j, checked against nnz.
 __device__ __forceinline__ bool fill_row(const DevWs& w, const int32_t* offsets, long long nnz, int j,
                                          long long& base, long long& m) {
-  base = offsets[j];
-  m = static_cast<long long>(offsets[j + 1]) - base;
+  const nm_int2u o = *reinterpret_cast<const nm_int2u*>(offsets + j);  // one 8-byte load
+  base = o.x;
+  m = static_cast<long long>(o.y) - base;
   if (base < 0 || m < 0 || base + m > nnz) {
     set_err(w.hdr, NM_E_INVAL);
     return false;
@@ -562,9 +585,24 @@ __device__ __forceinline__ bool global_fill(const DevWs& w, int s, long long rc2
 
 // This wave's key buffer in LDS (kernels of the fill pass); two spare
 // entries keep each wave's buffer 16-byte aligned and pad odd rows.
-__device__ __forceinline__ unsigned long long* wave_keys() {
+__device__ __forceinline__ unsigned long long (&key_lds())[kWaves][kWaveKeys + 2] {
   __shared__ unsigned long long s_keys[kWaves][kWaveKeys + 2];
-  return s_keys[threadIdx.x >> 6];
+  return s_keys;
+}
+__device__ __forceinline__ unsigned long long* wave_keys() { return key_lds()[threadIdx.x >> 6]; }
+
+// The same LDS as kSlots 16-bit slots per lane (LDS indices of a row's hits),
+// column-major: slot c of lane t at c * kBlock + p(t), where p interleaves
+// lanes t and t + 32 of a wavefront in one dword, so that a wavefront's
+// appends touch each bank once per half.  The light rows of a batch use it,
+// the waves' rows only after a barrier.
+constexpr int kSlots = 32;
+static_assert(kSlots * kBlock * 2 <= kWaves * (kWaveKeys + 2) * 8, "slot columns exceed the key buffer");
+static_assert(kStripPts + kUnroll <= 0x2000, "LDS indices exceed the slots and the keys' index field");
+__device__ __forceinline__ uint16_t* lane_slots() {
+  const int t = threadIdx.x;
+  const int p = (t & ~63) | ((t & 31) << 1) | ((t >> 5) & 1);
+  return reinterpret_cast<uint16_t*>(&key_lds()[0][0]) + p;
 }
 
 // One wave: the m unique keys in buf written to out in ascending order.
@@ -604,6 +642,98 @@ __device__ __forceinline__ void wave_sort_write(unsigned long long* buf, int m, 
     rank_write_e<8>(buf, m, out);
 }
 
+// Ascending sort of NS keys in registers (bitonic network).
+template <int NS>
+__device__ __forceinline__ void bitonic_sort(uint32_t (&key)[NS]) {
+#pragma unroll
+  for (int size = 2; size <= NS; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const uint32_t a = key[i], b = key[j];
+          const bool up = (i & size) == 0;
+          key[i] = up ? min(a, b) : max(a, b);
+          key[j] = up ? max(a, b) : min(a, b);
+        }
+      }
+    }
+  }
+}
+
+// The c LDS indices of a slot column as 32-bit keys (d^2 >> sh) << 13 | index,
+// sorted; the first must be the query itself (distance 0) and no two may share
+// a distance field (then the order by index is the exact one).  The others go
+// out as particle indices.  False otherwise: the caller runs the exact
+// selection.
+template <int NS>
+__device__ __forceinline__ bool slots_sort_write(const StagedQuery& q, const StripView& v, const uint16_t* col,
+                                                 int c, int sh, int32_t* __restrict__ out) {
+  uint32_t key[NS];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    key[t] = kKey32Inf;
+    if (t < c) {
+      const int j = col[t * kBlock];
+      const uint32_t d2 = v.wide ? static_cast<uint32_t>(v.d2(j, q) >> sh) : rel_d2_u(v.lpos[j], q.pq) >> sh;
+      key[t] = (d2 << 13) | static_cast<uint32_t>(j);
+    }
+  }
+  bitonic_sort(key);
+  bool good = key[0] == static_cast<uint32_t>(q.self);
+#pragma unroll
+  for (int t = 0; t + 1 < NS; ++t)
+    if (t + 1 < c) good = good && key32_d(key[t]) != key32_d(key[t + 1]);
+  if (!good) return false;
+  // keys 1 .. c - 1 as 16-byte stores where four are left, the rest one by one
+  auto at = [&](int t) { return v.lidx[key[t] & 0x1FFFu]; };
+#pragma unroll
+  for (int t = 1; t < NS; t += 4) {
+    if (t + 3 < NS && t + 3 < c) {
+      *reinterpret_cast<nm_int4u*>(out + t - 1) = nm_int4u{at(t), at(t + 1), at(t + 2), at(t + 3)};
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (t + u < NS && t + u < c) out[t - 1 + u] = at(t + u);
+    }
+  }
+  return true;
+}
+
+// One thread, a row of m entries with m + 2 <= kSlots: one pass over the
+// range appends the LDS index of every hit (the query itself among them, at
+// distance 0) to the lane's slot column, whose spare slot takes the
+// candidates after the last hit; then the column is sorted and written.
+// False when the hits are not m + 1 or on a tie of distance fields.
+template <bool kWide>
+__device__ __forceinline__ bool strip_fill_slots(const StagedQuery& q, const StripView& v, long long rc2,
+                                                 int sh, long long m, int32_t* __restrict__ out) {
+  uint16_t* col = lane_slots();
+  const uint32_t r32 = static_cast<uint32_t>(min(rc2, 0xFFFFFFFFll));
+  int c = 0;
+  // whole rounds without an end check; only the range's last round masks
+  // what lies beyond it
+  auto round = [&](int i, bool tail) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const bool in = kWide ? v.d2(i + u, q) <= rc2 : rel_d2_u(v.lpos[i + u], q.pq) <= r32;
+      col[min(c, kSlots - 1) * kBlock] = static_cast<uint16_t>(i + u);
+      c += (in && (!tail || i + u < q.hi)) ? 1 : 0;
+    }
+  };
+  const int full = q.lo + ((q.hi - q.lo) & ~(kUnroll - 1));
+  for (int i = q.lo; i < full; i += kUnroll) round(i, false);
+  if (full < q.hi) round(full, true);
+  if (c != m + 1) return false;
+  // one network width per wavefront (lanes taking two would run both)
+  const unsigned long long w8 = __ballot(c > 8), w16 = __ballot(c > 16);
+  if (w16) return slots_sort_write<kSlots>(q, v, col, c, sh, out);
+  if (w8) return slots_sort_write<16>(q, v, col, c, sh, out);
+  return slots_sort_write<8>(q, v, col, c, sh, out);
+}
+
 // Fill pass: row i of the CSR lists, ascending by (d^2, index).
 struct FillOp {
   static constexpr int kPass = 1;
@@ -611,27 +741,33 @@ struct FillOp {
   int32_t* idx;
   long long rc2, nnz;
   int sh;  // distance field of the 32-bit keys: d^2 >> sh < 2^kDBits for d^2 <= rc2
-  __device__ bool light(const DevWs& w, const StagedQuery& q, const StripView& v) const {
+  // Rows of up to kSlots - 2 entries: one pass into the lane's slot column.
+  // Longer rows go to a wave (one lane would take several passes of the
+  // kChunk-wide network, while the rest of the workgroup waits at the next
+  // barrier); rows longer than a wave sorts, to the second sweep of lanes.
+  __device__ __forceinline__ int light(const DevWs& w, const StagedQuery& q, const StripView& v) const {
     long long base, m;
-    if (!fill_row(w, offsets, nnz, v.lidx[q.self], base, m) || m == 0) return true;
-    const long long visits = ((m + kChunk - 1) / kChunk) * static_cast<long long>(q.hi - q.lo);
-    if (m <= kWaveKeys && visits > kHeavyWork) return false;
-    // One network width per wavefront: lanes of one wavefront taking the 8- and
-    // the 16-wide network would run both, one after the other.
-    const bool wide16 = __ballot(m > 8) != 0ull;
-    bool done;
-    if (v.wide)
-      done = !wide16 ? strip_fill32<8, true>(q, v, rc2, sh, m, idx + base)
-                     : strip_fill32<kChunk, true>(q, v, rc2, sh, m, idx + base);
-    else
-      done = !wide16 ? strip_fill32<8, false>(q, v, rc2, sh, m, idx + base)
-                     : strip_fill32<kChunk, false>(q, v, rc2, sh, m, idx + base);
+    if (!fill_row(w, offsets, nnz, v.lidx[q.self], base, m) || m == 0) return kRowDone;
+    const int range = q.hi - q.lo;
+    if (m <= kWaveKeys && range > kHeavyRange) return kRowWave;
+    if (m + 2 <= kSlots) {
+      const bool done = v.wide ? strip_fill_slots<true>(q, v, rc2, sh, m, idx + base)
+                               : strip_fill_slots<false>(q, v, rc2, sh, m, idx + base);
+      if (!done && !strip_fill(q, v, rc2, m, idx + base)) set_err(w.hdr, NM_E_INVAL);
+      return kRowDone;
+    }
+    return m <= kWaveKeys ? kRowWave : kRowLane;
+  }
+  __device__ __forceinline__ void lane(const DevWs& w, const StagedQuery& q, const StripView& v) const {
+    long long base, m;
+    if (!fill_row(w, offsets, nnz, v.lidx[q.self], base, m)) return;
+    const bool done = v.wide ? strip_fill32<kChunk, true>(q, v, rc2, sh, m, idx + base)
+                             : strip_fill32<kChunk, false>(q, v, rc2, sh, m, idx + base);
     if (!done && !strip_fill(q, v, rc2, m, idx + base)) set_err(w.hdr, NM_E_INVAL);
-    return true;
   }
   // One wave: the row's exact keys gathered from the staged range into LDS
   // (ballot compaction), placed by rank and written out (m <= kWaveKeys).
-  __device__ void heavy(const DevWs& w, const StagedQuery& q, const StripView& v) const {
+  __device__ __forceinline__ void heavy(const DevWs& w, const StagedQuery& q, const StripView& v) const {
     long long base, m;
     if (!fill_row(w, offsets, nnz, v.lidx[q.self], base, m) || m == 0) return;
     const int lane = threadIdx.x & 63;

@@ -599,6 +599,32 @@ def test_metric_strip_layouts(case):
     assert np.array_equal(offs, ro) and np.array_equal(idx, ri)
 
 
+def test_metric_rows_across_slot_widths():
+    # Isolated groups of 5 .. 48 points in disks of radius 40 (r_c = 100): rows of
+    # 4 .. 47 entries take the 8-, 16- and 32-wide sorts of the one-pass fill and,
+    # past its slot column, the chunked selection; sparse points elsewhere keep
+    # short rows in the same launch.  Cells of 8192 make the strips wide.
+    rng = np.random.default_rng(33)
+    sizes = [5, 9, 10, 16, 17, 18, 25, 30, 31, 32, 33, 40, 48]
+    xs, ys = [], []
+    for g, size in enumerate(sizes):
+        r = 40 * np.sqrt(rng.uniform(0, 1, size))
+        a = rng.uniform(0, 2 * np.pi, size)
+        xs.append(40000 + 60000 * g + np.round(r * np.cos(a)))
+        ys.append(300000 + 5000 * g + np.round(r * np.sin(a)))
+    xs.append(rng.integers(0, L, 3000))
+    ys.append(rng.integers(0, L, 3000))
+    x = np.concatenate(xs).astype(np.int32)
+    y = np.concatenate(ys).astype(np.int32)
+    rc2 = 100 ** 2
+    ro, ri, _ = oracle.metric_list(x, y, L, rc2)
+    lengths = set(np.diff(ro).tolist())
+    assert {4, 8, 9, 15, 16, 17, 29, 30, 31, 47} <= lengths
+    for w in (1024, 8192):
+        offs, idx = _gpu_metric(x, y, rc2, w)
+        assert np.array_equal(offs, ro) and np.array_equal(idx, ri)
+
+
 def test_metric_rows_longer_than_a_wave_sort():
     # 700 coincident points: rows of 699 entries, beyond what one wave sorts in LDS,
     # take the chunked selection; 300 more points in a ring keep other rows mid-sized.
