@@ -1,5 +1,5 @@
 // batch.hip -- the batched form: many independent systems of uneven size
-// advanced together, one persistent launch per stage of the step (Alg. 1:
+// advanced together, one launch per stage of the step (Alg. 1:
 // cell binning, k-NN lists, Eq. (2) alignment and Eq. (1) move), with the
 // whole step captured once into a HIP graph and replayed.
 //

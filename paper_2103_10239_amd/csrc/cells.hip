@@ -506,8 +506,12 @@ __global__ __launch_bounds__(kBlock) void k_fine_sort(DevWs w, uint32_t step_lo,
 }
 
 // ---------------------------------------------------------------------------
-// Batched stages.  Workgroup g of a persistent launch takes the stage's items
-// g, g + gridDim.x, ...; an item is one workgroup's share of one system.
+// Batched stages.  Workgroup g takes the stage's items g, g + gridDim.x, ...;
+// an item is one workgroup's share of one system.  The scan runs on a
+// persistent grid (its tiles wait on tiles of running workgroups only); the
+// other stages, whose items never wait on one another, launch one workgroup
+// per item, so that the hardware hands items of uneven cost to whichever CU
+// is free.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ const BatchSys& batch_item(const BatchRef& b, int stage, int it, int& li) {
   const BatchSys& d = b.sys[b.items[b.begin[stage] + it]];
@@ -656,7 +660,7 @@ hipError_t launch_batch_bin(const BatchRef& b, int stage, hipStream_t s) {
     case kStFine: k = reinterpret_cast<const void*>(k_bb_fine); break;
     default: return hipErrorInvalidValue;
   }
-  const int grid = batch_grid(k, items);
+  const int grid = stage == kStScan ? batch_grid(k, items) : items;
   switch (stage) {
     case kStInit: hipLaunchKernelGGL(k_bb_init, dim3(grid), dim3(kBlock), 0, s, b); break;
     case kStCount: hipLaunchKernelGGL(k_bb_count, dim3(grid), dim3(kBlock), 0, s, b); break;

@@ -907,9 +907,13 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
 // Waves per SIMD asked of the compiler: five for the short lists (96 VGPRs,
 // which the LDS of a strip also allows), four for KMAX 12-20, whose insertion
 // networks would otherwise take the kernel to three or two; the spills these
-// limits add (cold for k <= 12) cost less than the waves they gain.
+// limits add (cold for k <= 12) cost less than the waves they gain.  The
+// batched kernel, which also holds its system's descriptors, spills at five
+// and takes four.
 template <int KMAX>
 constexpr int kKnnWaves = (KMAX >= 12 && KMAX <= 20) ? 4 : (KMAX <= 8 ? 5 : 1);
+template <int KMAX>
+constexpr int kBatchKnnWaves = KMAX <= 8 ? 4 : kKnnWaves<KMAX>;
 
 template <int KMAX, bool kAlign, int kMode>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kKnnWaves<KMAX>))) void k_knn(DevWs w, FastCfg f, TileCfg tc, int k,
@@ -960,15 +964,19 @@ __device__ __forceinline__ AlignArgs uniform_load_align(const BatchSys* d) {
 }
 
 template <int KMAX, int kMode>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kKnnWaves<KMAX>))) void k_bb_knn(BatchRef b, int k) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBatchKnnWaves<KMAX>))) void k_bb_knn(BatchRef b, int k) {
   constexpr int kSt = kMode == kOverflowSplit ? kStKnnSplit : kStKnn;
   const int ni = b.begin[kSt + 1] - b.begin[kSt];
   const int per = gridDim.x & ~7;  // whole rounds of the 8 XCDs
   for (int hw = blockIdx.x; hw < ni; hw += gridDim.x) {
-    // Remap within the rounds that every workgroup of a multiple-of-8 grid takes.
+    // Neighbouring strips on one XCD (one L2): over all items when each
+    // workgroup takes one, else within the rounds that every workgroup of a
+    // multiple-of-8 grid takes.
     int it = hw;
     const int round_base = (hw / gridDim.x) * gridDim.x;
-    if (per == static_cast<int>(gridDim.x) && round_base + per <= ni)
+    if (static_cast<int>(gridDim.x) == ni)
+      it = xcd_tile(hw, ni);
+    else if (per == static_cast<int>(gridDim.x) && round_base + per <= ni)
       it = round_base + xcd_tile(hw - round_base, per);
     const BatchSys* g = b.sys + b.items[b.begin[kSt] + it];
     const DevWs w = uniform_load(&g->w);
@@ -1086,13 +1094,13 @@ hipError_t launch_batch_knn(const BatchRef& b, int k, hipStream_t s) {
   return dispatch_k(k, [&](auto km) {
     constexpr int KM = decltype(km)::value;
     if (nt > 0) {
-      const int g = batch_grid(reinterpret_cast<const void*>(k_bb_knn<KM, kOverflowGlobal>), nt);
+      const int g = nt;  // one workgroup per strip: uneven strips balance over the CUs
       hipLaunchKernelGGL((k_bb_knn<KM, kOverflowGlobal>), dim3(g), dim3(kBlock), 0, s, b, k);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
     if (ns > 0) {
-      const int g = batch_grid(reinterpret_cast<const void*>(k_bb_knn<KM, kOverflowSplit>), ns);
+      const int g = ns;
       hipLaunchKernelGGL((k_bb_knn<KM, kOverflowSplit>), dim3(g), dim3(kBlock), 0, s, b, k);
       return hipGetLastError();
     }
