@@ -691,6 +691,20 @@ def run_stream(reqs, pools, submit, collect, t_limit):
     return out, time.perf_counter() - t0
 
 
+def served_tail(out):
+    """Where the job latency comes from: latency per requested step, and the
+    p99 of short and long jobs and of the largest tenth by N."""
+    per_step = [o[0] / o[5] for o in out]
+    short = [o[0] for o in out if o[5] <= 10]
+    long_ = [o[0] for o in out if o[5] >= 90]
+    n_cut = sorted(o[4] for o in out)[int(0.9 * (len(out) - 1))]
+    big = [o[0] for o in out if o[4] >= n_cut]
+    return {"ms_per_step_p50": 1e3 * pct(per_step, 50), "ms_per_step_p99": 1e3 * pct(per_step, 99),
+            "latency_ms_p99_jobs_le_10_steps": 1e3 * pct(short, 99) if short else None,
+            "latency_ms_p99_jobs_ge_90_steps": 1e3 * pct(long_, 99) if long_ else None,
+            "latency_ms_p99_largest_tenth_n": 1e3 * pct(big, 99) if big else None}
+
+
 def bench_served(args, torch, nm, workloads):
     box = workloads.BOX
     reqs = workloads.request_stream(200.0, args.served_seconds)
@@ -713,7 +727,7 @@ def bench_served(args, torch, nm, workloads):
             o = srv.wait(jid)
             if o["status"] != 0:
                 raise RuntimeError(f"served job failed: {nm.nm.status_str(o['status'])}")
-            return (o["done_s"] - o["submit_s"], r.n * r.nsteps, o["submit_s"], o["done_s"])
+            return (o["done_s"] - o["submit_s"], r.n * r.nsteps, o["submit_s"], o["done_s"], r.n, r.nsteps)
 
         out, wall = run_stream(reqs_run, pools, submit, collect, args.served_seconds + 1.0)
         st = srv.stats()
@@ -724,7 +738,8 @@ def bench_served(args, torch, nm, workloads):
         res[label] = {"jobs": len(out), "latency_ms_p50": 1e3 * pct(lat, 50),
                       "latency_ms_p99": 1e3 * pct(lat, 99), "particle_steps_per_s": work / span,
                       "peak_active": st["peak_active"], "peak_ledger_bytes": st["peak_used_bytes"],
-                      "device_slab_bytes": st["reserved_bytes"], "iterations": st["iterations"]}
+                      "device_slab_bytes": st["reserved_bytes"], "iterations": st["iterations"],
+                      "tail": served_tail(out)}
         log(f"[bench] served {label}: {len(out)} jobs, p50 {res[label]['latency_ms_p50']:.1f} ms, "
             f"p99 {res[label]['latency_ms_p99']:.1f} ms, {work / span:.3g} particle-steps/s, "
             f"peak active {st['peak_active']}")
