@@ -1021,14 +1021,17 @@ TileCfg tile_cfg_impl(const DevWs& w, const FastCfg& f, int k, bool narrow_strip
   // neighbour distance, not only its mean.
   int hx = min(max(1, static_cast<int>(ceil(kReachX * rk))), 15);
   if (f.bfix > 0) hx = min(max(hx, f.bfix / 2), 15);
-  // Strip width: wider as the halo widens (hx 2: two columns, hx >= 3: four),
-  // and at least the narrowest power of two whose strips reach ~256 queries
-  // within the row limit.  Wider strips stage each particle fewer times and
-  // leave fewer queries near a strip's side.  `narrow_strips` (two columns
+  // Strip width: wider as the halo widens (hx 2: two columns, hx >= 3: four,
+  // or two for lists of up to 8, where a block's candidates (its rows times
+  // W = tw + 2 hx) cost more than the extra staging: 93 -> 88 us for k = 7 at
+  // w = 1024, block 6, while k = 12 loses 4%), and at least the narrowest
+  // power of two whose strips reach ~256 queries within the row limit.  Wider
+  // strips stage each particle fewer times and leave fewer queries near a
+  // strip's side.  `narrow_strips` (two columns
   // only from hx 3, and halo rows for the expected block height) serves the
   // sub-strip kernel, whose larger halos overflow LDS more often, and the
   // field-of-view lists, whose blocks span every column of the strip.
-  int tw = narrow_strips ? (hx >= 3 ? 2 : 1) : (hx >= 3 ? 4 : (hx >= 2 ? 2 : 1));
+  int tw = narrow_strips ? (hx >= 3 ? 2 : 1) : (hx >= 3 ? (k <= 8 ? 2 : 4) : (hx >= 2 ? 2 : 1));
   while (tw < 16 && 2 * tw <= w.G && 256.0 / (tw * rr) > 1.1 * (kTwRows - 2 * hy)) tw *= 2;
   while (hx > 1 && tw + 2 * hx > w.G) --hx;
   while (hy > 1 && 2 * hy + 1 > w.G) --hy;
