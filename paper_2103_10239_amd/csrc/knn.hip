@@ -483,8 +483,8 @@ __device__ __forceinline__ void ring_cell(int r, int q, int& dx, int& dy) {
 // lanes take up to 64 cells at a time, skip cells whose nearest point is
 // farther than the current k-th neighbour, flatten the candidates of the rest
 // across the lanes and evaluate 64 per round; candidates that beat the
-// current k-th are merged one by one (their keys broadcast to every lane,
-// which all hold the same list).  Same stop rule as the lane search.
+// current k-th are merged one by one (each broadcast to every lane; the list
+// itself is spread over the lanes).  Same stop rule as the lane search.
 // Candidates that fail `filt` are skipped.
 template <int KMAX, class Filter = NoFilter>
 __device__ __forceinline__ bool knn_wave(const DevWs& w, int s, const int4& q, int k, int total,
@@ -494,8 +494,12 @@ __device__ __forceinline__ bool knn_wave(const DevWs& w, int s, const int4& q, i
   const int cw = 1 << w.log2_w;
   const int gm = w.G - 1;
   const QueryGeom g(q.x, q.y, w);
-  TopK<KMAX, true> top;
-  top.init(k);
+  // The list is spread over the wave: lane t < k holds the t-th nearest so
+  // far (key and slot), so an insertion costs each lane one compare with its
+  // own entry and its left neighbour's instead of a pass over a whole list.
+  unsigned long long mine = ~0ull;
+  int mslot = -1;
+  unsigned long long worst = ~0ull;  // the k-th entry, in every lane
   for (int r = 0; r <= g.rmax; ++r) {
     const int ncell = r == 0 ? 1 : 8 * r;
     for (int c0 = 0; c0 < ncell; c0 += 64) {
@@ -505,7 +509,7 @@ __device__ __forceinline__ bool knn_wave(const DevWs& w, int s, const int4& q, i
         ring_cell(r, c0 + lane, dx, dy);
         if (dx >= g.lo && dx <= g.hi && dy >= g.lo && dy <= g.hi) {
           const long long gx = axis_gap(dx, g.ox, cw, sh), gy = axis_gap(dy, g.oy, cw, sh);
-          if (gx * gx + gy * gy <= key_bound_d2(top.worst())) {
+          if (gx * gx + gy * gy <= key_bound_d2(worst)) {
             const int64_t c = static_cast<int64_t>((g.hy + dy) & gm) * w.G + ((g.hx + dx) & gm);
             beg = w.start[c];
             cnt = max(min(w.start[c + 1], total) - beg, 0);
@@ -542,21 +546,36 @@ __device__ __forceinline__ bool knn_wave(const DevWs& w, int s, const int4& q, i
             if (keep) kk = pack_key(static_cast<long long>(ex) * ex + static_cast<long long>(ey) * ey, e.z);
           }
         }
-        unsigned long long better = __ballot(kk < top.worst());
+        unsigned long long better = __ballot(kk < worst);
         while (better) {
           const int l = __ffsll(static_cast<long long>(better)) - 1;
           better &= better - 1;
           const unsigned long long bk = __shfl(kk, l, 64);
           const int bt = __shfl(t, l, 64);
-          if (bk < top.worst()) top.push(bk, bt);
+          if (bk < worst) {
+            const unsigned long long left = __shfl_up(mine, 1, 64);
+            const int lslot = __shfl_up(mslot, 1, 64);
+            if (lane < k && bk < mine) {
+              const bool shift = lane > 0 && bk < left;  // the new key lands before this entry
+              mine = shift ? left : bk;
+              mslot = shift ? lslot : bt;
+            }
+            worst = __shfl(mine, k - 1, 64);
+          }
         }
       }
     }
-    if (key_bound_d2(top.worst()) < g.ring_bound(r, cw)) break;
+    if (key_bound_d2(worst) < g.ring_bound(r, cw)) break;
   }
+  // the list in every lane, in the lane search's layout (nearest first at
+  // KMAX - k)
 #pragma unroll
-  for (int t = 0; t < KMAX; ++t) slot[t] = top.slot[t];
-  return top.worst() != ~0ull;
+  for (int t = 0; t < KMAX; ++t) {
+    const int src = t - (KMAX - k);
+    const int v = __shfl(mslot, src < 0 ? 0 : src, 64);
+    slot[t] = src < 0 ? -1 : v;
+  }
+  return worst != ~0ull;
 }
 
 // One uncertified query searched by its own lane (exact ring search).
@@ -854,9 +873,10 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
   const int nd = s_defer;
   if (nd == 0) return;
 
-  // The strip's uncertified queries, by the exact ring search.  With many,
-  // each lane searches its own; with a few, a wavefront searches one at a
-  // time, so that a single long search is not one lane's serial chain.
+  // The strip's uncertified queries, by the exact ring search.  With many
+  // (over 48), each lane searches its own; otherwise a wavefront searches one
+  // at a time, so that a single long search is not one lane's serial chain
+  // (on the clustered 2^22 state, from 16 to 48: 3-8% faster).
   const int nl = min(nd, kDeferCap);
   if (kMode == kFieldOfView && nl > 16) {
     for (int j = threadIdx.x; j < nl; j += kBlock) {
@@ -864,7 +884,7 @@ __device__ __forceinline__ void knn_tile_body(const DevWs& w, const FastCfg& f, 
       const int4 q = w.sorted[sq];
       fov_exact<KMAX>(w, sq, q, fov_heading(a.theta[q.z], a.cone), k, total, nbr);
     }
-  } else if (kMode != kFieldOfView && nl > 16) {
+  } else if (kMode != kFieldOfView && nl > 48) {
     for (int j = threadIdx.x; j < nl; j += kBlock) exact_lane<KMAX, kAlign>(w, s_dq[j], k, total, nbr, d2out, a);
   } else {
     for (int j = threadIdx.x >> 6; j < nl; j += kBlock / 64) {
