@@ -246,8 +246,26 @@ __device__ __forceinline__ void run_queries(const DevWs& w, const MetricCfg& mc,
     __syncthreads();
     const int nl = S.nlane;
     for (int d = threadIdx.x; d < nl; d += kBlock) op.lane(w, query(S.heavy[kChunkQ - 1 - d]), view);
+    // Wave rows: wave v takes rows v, v + kWaves, ...; lane j first finds the
+    // query and loads the row data of the wave's j-th next row, so that the
+    // rows' latencies overlap, and the wave then takes them one by one.
     const int nh = S.nheavy;
-    for (int d = threadIdx.x >> 6; d < nh; d += kWaves) op.heavy(w, query(S.heavy[d]), view);
+    const int lane = threadIdx.x & 63;
+    for (int d0 = threadIdx.x >> 6; d0 < nh; d0 += 64 * kWaves) {
+      const int dj = d0 + kWaves * lane;
+      StagedQuery qj{0, 0, 0, 0, 0};
+      typename Op::Row rj{};
+      if (dj < nh) {
+        qj = query(S.heavy[dj]);
+        rj = op.row(view, qj);
+      }
+      const int cnt = min(64, (nh - d0 + kWaves - 1) / kWaves);
+      for (int j = 0; j < cnt; ++j) {
+        const StagedQuery q{__shfl(qj.self, j, 64), __shfl(qj.lo, j, 64), __shfl(qj.hi, j, 64),
+                            __shfl(qj.pq, j, 64), __shfl(qj.pqy, j, 64)};
+        op.heavy(w, q, view, Op::row_at(rj, j));
+      }
+    }
     __syncthreads();
   }
 }
@@ -425,8 +443,11 @@ struct CountOp {
     return kRowDone;
   }
   __device__ __forceinline__ void lane(const DevWs&, const StagedQuery&, const StripView&) const {}
+  using Row = int;  // no row data
+  __device__ __forceinline__ Row row(const StripView&, const StagedQuery&) const { return 0; }
+  __device__ static __forceinline__ Row row_at(Row, int) { return 0; }
   // One wave: the same count over the staged range.
-  __device__ __forceinline__ void heavy(const DevWs&, const StagedQuery& q, const StripView& v) const {
+  __device__ __forceinline__ void heavy(const DevWs&, const StagedQuery& q, const StripView& v, Row) const {
     int cnt = 0;
     for (int i0 = q.lo; i0 < q.hi; i0 += 64) {
       const int i = i0 + static_cast<int>(threadIdx.x & 63);
@@ -462,10 +483,10 @@ __global__ __launch_bounds__(kBlock) void k_metric_count_waves(DevWs w, long lon
   });
 }
 
-// Rows of the fill: offset and length of row j, checked against nnz.
-__device__ __forceinline__ bool fill_row(const DevWs& w, const int32_t* offsets, long long nnz, int j,
-                                         long long& base, long long& m) {
-  const nm_int2u o = *reinterpret_cast<const nm_int2u*>(offsets + j);  // one 8-byte load
+// Rows of the fill: offset and length of a row from its two offsets, checked
+// against nnz.
+__device__ __forceinline__ bool row_bounds(const DevWs& w, const nm_int2u& o, long long nnz, long long& base,
+                                           long long& m) {
   base = o.x;
   m = static_cast<long long>(o.y) - base;
   if (base < 0 || m < 0 || base + m > nnz) {
@@ -473,6 +494,12 @@ __device__ __forceinline__ bool fill_row(const DevWs& w, const int32_t* offsets,
     return false;
   }
   return true;
+}
+
+// The same for row j, read from `offsets` (one 8-byte load).
+__device__ __forceinline__ bool fill_row(const DevWs& w, const int32_t* offsets, long long nnz, int j,
+                                         long long& base, long long& m) {
+  return row_bounds(w, *reinterpret_cast<const nm_int2u*>(offsets + j), nnz, base, m);
 }
 
 // One thread: the m smallest exact (d^2, index) keys of a staged query, in
@@ -621,6 +648,9 @@ __device__ __forceinline__ void rank_write_e(unsigned long long* buf, int m, int
     mine[r] = e < m ? buf[e] : ~0ull;
     rank[r] = 0;
   }
+  // four pairs a round: their LDS reads are in flight together (a wave sorts
+  // its rows one after another, so their latency is not hidden by others)
+#pragma unroll 4
   for (int t = 0; t < m; t += 2) {
     const unsigned long long a = buf[t], b = buf[t + 1];
 #pragma unroll
@@ -767,9 +797,16 @@ struct FillOp {
   }
   // One wave: the row's exact keys gathered from the staged range into LDS
   // (ballot compaction), placed by rank and written out (m <= kWaveKeys).
-  __device__ __forceinline__ void heavy(const DevWs& w, const StagedQuery& q, const StripView& v) const {
+  using Row = nm_int2u;  // the row's offset and the next one
+  __device__ __forceinline__ Row row(const StripView& v, const StagedQuery& q) const {
+    return *reinterpret_cast<const nm_int2u*>(offsets + v.lidx[q.self]);
+  }
+  __device__ static __forceinline__ Row row_at(const Row& r, int j) {
+    return Row{__shfl(r.x, j, 64), __shfl(r.y, j, 64)};
+  }
+  __device__ __forceinline__ void heavy(const DevWs& w, const StagedQuery& q, const StripView& v, Row o) const {
     long long base, m;
-    if (!fill_row(w, offsets, nnz, v.lidx[q.self], base, m) || m == 0) return;
+    if (!row_bounds(w, o, nnz, base, m) || m == 0) return;
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
     unsigned long long* buf = wave_keys();
