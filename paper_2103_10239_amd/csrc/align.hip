@@ -45,18 +45,42 @@ __global__ __launch_bounds__(kBlock) void k_align(const int32_t* __restrict__ x,
   }
   double sx = 0.0, sy = 0.0;
   long long m = 0;
-  for (long long t = begin; t < end; ++t) {
-    const int j = nbr[t];
-    if (j == -1 && !offsets) break;  // a fixed-k row padded after its last neighbour
+  bool stop = false;
+  // Neighbour j's unit vector, added in list order; a fixed-k row padded
+  // after its last neighbour ends at the first -1.
+  auto add = [&](int j, float thj) {
+    if (stop) return;
+    if (j == -1 && !offsets) {
+      stop = true;
+      return;
+    }
     if (static_cast<uint32_t>(j) >= static_cast<uint32_t>(n)) {
       set_err(err, NM_E_INVAL);
-      continue;
+      return;
     }
     double sn, cs;
-    sincos(static_cast<double>(theta[j]), &sn, &cs);
+    sincos(static_cast<double>(thj), &sn, &cs);
     sx += cs;
     sy += sn;
     ++m;
+  };
+  // Four neighbours a round: their index and heading reads are in flight
+  // together instead of one chain of two dependent reads per neighbour.
+  long long t = begin;
+  for (; t + 4 <= end && !stop; t += 4) {
+    int j4[4];
+    float th4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) j4[u] = nbr[t + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      th4[u] = static_cast<uint32_t>(j4[u]) < static_cast<uint32_t>(n) ? theta[j4[u]] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) add(j4[u], th4[u]);
+  }
+  for (; t < end && !stop; ++t) {
+    const int j = nbr[t];
+    add(j, static_cast<uint32_t>(j) < static_cast<uint32_t>(n) ? theta[j] : 0.0f);
   }
   const float th0 = theta[i];
   double own_s, own_c;
