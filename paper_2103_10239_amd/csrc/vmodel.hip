@@ -152,6 +152,9 @@ __global__ __launch_bounds__(kBlock) void k_vm_cells(const int32_t* __restrict__
   perim[i] = per;
 }
 
+// Rows of up to this many entries are read whole when searched.
+constexpr int kRowRead = 8;
+
 // Pass 2: the force on every particle, and the vertex forces if asked.
 __global__ __launch_bounds__(kBlock) void k_vm_forces(const int32_t* __restrict__ x,
                                                       const int32_t* __restrict__ y, int n, int log2_box,
@@ -188,19 +191,37 @@ __global__ __launch_bounds__(kBlock) void k_vm_forces(const int32_t* __restrict_
       // (j, mm, k), mm the particle just before k in j's row (i follows k)
       const int mj = deg[j];
       const int32_t* rowj = ring + static_cast<long long>(j) * dmax;
-      int sk = -1;
-      if (mj >= 3 && mj <= dmax)
+      int sk = -1, after = -1, mm = -1;
+      if (mj >= 3 && mj <= kRowRead && dmax >= kRowRead) {
+        // the usual short row: its first kRowRead entries read together
+        // (rows are dmax long), instead of one read per step of the search
+        int rj8[kRowRead];
+#pragma unroll
+        for (int u = 0; u < kRowRead; ++u) rj8[u] = rowj[u];
+#pragma unroll
+        for (int u = 0; u < kRowRead; ++u)
+          if (sk < 0 && u < mj && rj8[u] == k) sk = u;
+#pragma unroll
+        for (int u = 0; u < kRowRead; ++u) {
+          if (u == (sk + 1 < mj ? sk + 1 : 0)) after = rj8[u];
+          if (u == (sk > 0 ? sk - 1 : mj - 1)) mm = rj8[u];
+        }
+      } else if (mj >= 3 && mj <= dmax) {
         for (int u = 0; u < mj; ++u)
           if (rowj[u] == k) {
             sk = u;
             break;
           }
-      if (sk < 0 || rowj[sk + 1 < mj ? sk + 1 : 0] != i) {
+        if (sk >= 0) {
+          after = rowj[sk + 1 < mj ? sk + 1 : 0];
+          mm = rowj[sk > 0 ? sk - 1 : mj - 1];
+        }
+      }
+      if (sk < 0 || after != i) {
         set_err(err, NM_E_INVAL);  // the rows are not one triangulation
         ok = false;
         break;
       }
-      const int mm = rowj[sk > 0 ? sk - 1 : mj - 1];
       if (static_cast<unsigned>(mm) >= static_cast<unsigned>(n)) {
         set_err(err, NM_E_INVAL);
         ok = false;
