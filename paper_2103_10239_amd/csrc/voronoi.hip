@@ -509,6 +509,9 @@ __global__ __launch_bounds__(kBlock) void k_vor_clear(WsHeader* hdr, uint8_t* __
   }
 }
 
+// Rows of up to this many entries are read whole when searched.
+constexpr int kRowRead = 8;
+
 // Rows hold sites: a prefix of particles at the row's own position, then
 // runs of particles sharing a position.  These helpers walk a row site by
 // site; entries are valid indices (checked before).
@@ -642,10 +645,26 @@ __global__ __launch_bounds__(kBlock) void k_vor_check(const int32_t* __restrict_
           const int32_t* rowa = ring + static_cast<long long>(a) * dmax;
           const int b = row[tb];
           bool okidx = true, adjacent = false;
-          for (int u = 0; u < ma; ++u) {
-            const int q = rowa[u];
-            okidx = okidx && static_cast<unsigned>(q) < static_cast<unsigned>(n);
-            adjacent = adjacent || (q == b && rowa[u + 1 < ma ? u + 1 : 0] == i);
+          if (ma <= kRowRead && dmax >= kRowRead) {
+            // the usual short row: its first kRowRead entries read together
+            // (rows are dmax long), instead of one read per step
+            int ra[kRowRead];
+#pragma unroll
+            for (int u = 0; u < kRowRead; ++u) ra[u] = rowa[u];
+#pragma unroll
+            for (int u = 0; u < kRowRead; ++u) {
+              if (u < ma) {
+                const int nx = u + 1 < ma ? ra[u + 1 < kRowRead ? u + 1 : 0] : ra[0];
+                okidx = okidx && static_cast<unsigned>(ra[u]) < static_cast<unsigned>(n);
+                adjacent = adjacent || (ra[u] == b && nx == i);
+              }
+            }
+          } else {
+            for (int u = 0; u < ma; ++u) {
+              const int q = rowa[u];
+              okidx = okidx && static_cast<unsigned>(q) < static_cast<unsigned>(n);
+              adjacent = adjacent || (q == b && rowa[u + 1 < ma ? u + 1 : 0] == i);
+            }
           }
           if (!okidx || (!adjacent && !row_holds_then(row_view(rowa, ma, a, x, y), x[b], y[b], xi, yi)))
             fail = true;
