@@ -95,6 +95,38 @@ __device__ __forceinline__ V2 cell_vertex_grad(V2 hp, V2 h, V2 hn, double A, dou
   return dA * (2.0 * a.ka * (A - a.a0)) + dP * (2.0 * a.kp * (P - a.p0));
 }
 
+// Rows of up to this many entries are read whole when checked or searched
+// (one read of each kind in flight for the row, not one chain per entry).
+constexpr int kRowRead = 8;
+
+// Row i's m entries: bad (an index outside [0, n)) or coincident (a
+// particle at i's own position).  Returns whether the row was read whole,
+// with its entries' positions in px, py.
+__device__ __forceinline__ bool row_faults(const int32_t* __restrict__ x, const int32_t* __restrict__ y, int n,
+                                           int dmax, const int32_t* row, int m, int i, bool& bad,
+                                           bool& coincident, int (&px)[kRowRead], int (&py)[kRowRead]) {
+  bad = coincident = false;
+  const int xi = x[i], yi = y[i];
+  if (m <= kRowRead && dmax >= kRowRead) {
+    int rw[kRowRead];
+#pragma unroll
+    for (int u = 0; u < kRowRead; ++u) rw[u] = row[u];  // (rows are dmax long)
+#pragma unroll
+    for (int u = 0; u < kRowRead; ++u) {
+      const bool in = u < m && static_cast<unsigned>(rw[u]) < static_cast<unsigned>(n);
+      bad = bad || (u < m && !in);
+      px[u] = in ? x[rw[u]] : xi + 1;
+      py[u] = in ? y[rw[u]] : yi;
+    }
+#pragma unroll
+    for (int u = 0; u < kRowRead; ++u) coincident = coincident || (px[u] == xi && py[u] == yi);
+    return true;
+  }
+  for (int t = 0; t < m && !bad; ++t) bad = static_cast<unsigned>(row[t]) >= static_cast<unsigned>(n);
+  for (int t = 0; t < m && !bad && !coincident; ++t) coincident = x[row[t]] == xi && y[row[t]] == yi;
+  return false;
+}
+
 // Pass 1: area and perimeter of every cell (and its vertices, if asked).
 __global__ __launch_bounds__(kBlock) void k_vm_cells(const int32_t* __restrict__ x,
                                                      const int32_t* __restrict__ y, int n, int log2_box,
@@ -112,25 +144,41 @@ __global__ __launch_bounds__(kBlock) void k_vm_cells(const int32_t* __restrict__
     area[i] = perim[i] = 0.0;
     return;
   }
-  for (int t = 0; t < m; ++t)
-    if (static_cast<unsigned>(row[t]) >= static_cast<unsigned>(n)) {
-      set_err(err, NM_E_INVAL);
-      area[i] = perim[i] = 0.0;
-      return;
-    }
+  bool bad, coincident;
+  int px[kRowRead], py[kRowRead];
+  const bool whole = row_faults(x, y, n, dmax, row, m, i, bad, coincident, px, py);
+  if (bad) {
+    set_err(err, NM_E_INVAL);
+    area[i] = perim[i] = 0.0;
+    return;
+  }
   // the model gives each particle its own cell: coincident particles have none
-  for (int t = 0; t < m; ++t)
-    if (x[row[t]] == x[i] && y[row[t]] == y[i]) {
-      set_err(err, NM_E_RANGE);
-      area[i] = perim[i] = 0.0;
-      return;
+  if (coincident) {
+    set_err(err, NM_E_RANGE);
+    area[i] = perim[i] = 0.0;
+    return;
+  }
+  const int xi = x[i], yi = y[i];
+  // entry t's offset, from the positions read with the row when it was read whole
+  auto off_t = [&](int t) -> V2 {
+    if (whole) {
+      int ox = 0, oy = 0;
+#pragma unroll
+      for (int u = 0; u < kRowRead; ++u)
+        if (u == t) {
+          ox = px[u];
+          oy = py[u];
+        }
+      return {static_cast<double>(wrap_axis(ox - xi, sh)), static_cast<double>(wrap_axis(oy - yi, sh))};
     }
-  const V2 r0 = offset(x, y, sh, i, row[0]);
+    return offset(x, y, sh, i, row[t]);
+  };
+  const V2 r0 = off_t(0);
   V2 ra = r0;
   V2 h0 = {0.0, 0.0}, hprev = {0.0, 0.0};
   double a2 = 0.0, per = 0.0;
   for (int t = 0; t < m; ++t) {
-    const V2 rb = t + 1 < m ? offset(x, y, sh, i, row[t + 1]) : r0;
+    const V2 rb = t + 1 < m ? off_t(t + 1) : r0;
     const V2 h = circumcentre(ra, rb);
     if (vert) {
       double* v = vert + (static_cast<long long>(i) * dmax + t) * 4;
@@ -152,9 +200,6 @@ __global__ __launch_bounds__(kBlock) void k_vm_cells(const int32_t* __restrict__
   perim[i] = per;
 }
 
-// Rows of up to this many entries are read whole when searched.
-constexpr int kRowRead = 8;
-
 // Pass 2: the force on every particle, and the vertex forces if asked.
 __global__ __launch_bounds__(kBlock) void k_vm_forces(const int32_t* __restrict__ x,
                                                       const int32_t* __restrict__ y, int n, int log2_box,
@@ -171,13 +216,33 @@ __global__ __launch_bounds__(kBlock) void k_vm_forces(const int32_t* __restrict_
   const int32_t* row = ring + static_cast<long long>(i) * dmax;
   V2 F = {0.0, 0.0};
   bool ok = m >= 3 && m <= dmax;
-  for (int t = 0; t < m && ok; ++t)
-    ok = static_cast<unsigned>(row[t]) < static_cast<unsigned>(n) && (x[row[t]] != x[i] || y[row[t]] != y[i]);
+  int px[kRowRead], py[kRowRead];
+  bool whole = false;
   if (ok) {
+    bool bad, coincident;
+    whole = row_faults(x, y, n, dmax, row, m, i, bad, coincident, px, py);
+    ok = !bad && !coincident;
+  }
+  if (ok) {
+    const int xi = x[i], yi = y[i];
+    // entry t's offset, from the positions read with the row when it was read whole
+    auto off_t = [&](int t) -> V2 {
+      if (whole) {
+        int ox = 0, oy = 0;
+#pragma unroll
+        for (int u = 0; u < kRowRead; ++u)
+          if (u == t) {
+            ox = px[u];
+            oy = py[u];
+          }
+        return {static_cast<double>(wrap_axis(ox - xi, sh)), static_cast<double>(wrap_axis(oy - yi, sh))};
+      }
+      return offset(x, y, sh, i, row[t]);
+    };
     // h_{t-1}, h_t, h_{t+1} rolled along the ring
-    const V2 r0 = offset(x, y, sh, i, row[0]);
-    const V2 r1 = offset(x, y, sh, i, row[1 % m]);
-    const V2 rl = offset(x, y, sh, i, row[m - 1]);
+    const V2 r0 = off_t(0);
+    const V2 r1 = off_t(1 % m);
+    const V2 rl = off_t(m - 1);
     const V2 h0 = circumcentre(r0, r1);
     V2 hprev = circumcentre(rl, r0);
     V2 h = h0;
@@ -185,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_vm_forces(const int32_t* __restrict_
     const double Ai = area[i], Pi = perim[i];
     for (int t = 0; t < m; ++t) {
       const int j = row[t], k = row[t + 1 < m ? t + 1 : 0];
-      const V2 rnext = offset(x, y, sh, i, row[t + 2 < m ? t + 2 : t + 2 - m]);
+      const V2 rnext = off_t(t + 2 < m ? t + 2 : t + 2 - m);
       const V2 hnext = t + 1 < m ? circumcentre(rk, rnext) : h0;
       // the vertex across the edge between cells j and k: circumcentre of
       // (j, mm, k), mm the particle just before k in j's row (i follows k)
