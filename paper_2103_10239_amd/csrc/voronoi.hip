@@ -514,17 +514,28 @@ constexpr int kRowRead = 8;
 
 // Rows hold sites: a prefix of particles at the row's own position, then
 // runs of particles sharing a position.  These helpers walk a row site by
-// site; entries are valid indices (checked before).
+// site; entries are valid indices (checked before).  A row of up to
+// kRowRead entries is held in registers with its entries' positions (read
+// together, not as a chain of index and position reads per step).
 struct RowView {
   const int32_t* row;
   int m;
   int own;  // length of the own-site prefix
   const int32_t* x;
   const int32_t* y;
-  __device__ __forceinline__ bool same(int t, int u) const {
-    const int a = row[t], b = row[u];
-    return x[a] == x[b] && y[a] == y[b];
+  bool whole;
+  int rw[kRowRead], px[kRowRead], py[kRowRead];
+  __device__ static __forceinline__ int sel(const int (&a)[kRowRead], int t) {
+    int v = 0;
+#pragma unroll
+    for (int u = 0; u < kRowRead; ++u)
+      if (u == t) v = a[u];
+    return v;
   }
+  __device__ __forceinline__ int idx(int t) const { return whole ? sel(rw, t) : row[t]; }
+  __device__ __forceinline__ int xat(int t) const { return whole ? sel(px, t) : x[row[t]]; }
+  __device__ __forceinline__ int yat(int t) const { return whole ? sel(py, t) : y[row[t]]; }
+  __device__ __forceinline__ bool same(int t, int u) const { return xat(t) == xat(u) && yat(t) == yat(u); }
   // the first entry of the site after the one entry t belongs to (cyclic over
   // the site part of the row)
   __device__ __forceinline__ int next_site(int t) const {
@@ -547,10 +558,27 @@ struct RowView {
   }
 };
 
+// `dmax`: the rows' stride (a row is read whole only within it).
 __device__ __forceinline__ RowView row_view(const int32_t* row, int m, int self, const int32_t* x,
-                                            const int32_t* y) {
-  RowView r{row, m, 0, x, y};
-  while (r.own < m && x[row[r.own]] == x[self] && y[row[r.own]] == y[self]) ++r.own;
+                                            const int32_t* y, int dmax) {
+  RowView r;
+  r.row = row;
+  r.m = m;
+  r.own = 0;
+  r.x = x;
+  r.y = y;
+  r.whole = m <= kRowRead && dmax >= kRowRead;
+  if (r.whole) {
+#pragma unroll
+    for (int u = 0; u < kRowRead; ++u) r.rw[u] = row[u];
+#pragma unroll
+    for (int u = 0; u < kRowRead; ++u) {
+      r.px[u] = u < m ? x[r.rw[u]] : 0;
+      r.py[u] = u < m ? y[r.rw[u]] : 0;
+    }
+  }
+  const int sx = x[self], sy = y[self];
+  while (r.own < m && r.xat(r.own) == sx && r.yat(r.own) == sy) ++r.own;
   return r;
 }
 
@@ -558,11 +586,9 @@ __device__ __forceinline__ RowView row_view(const int32_t* row, int m, int self,
 // the site at (ixp, iyp).
 __device__ __forceinline__ bool row_holds_then(const RowView& rv, int bxp, int byp, int ixp, int iyp) {
   for (int t = rv.own; t < rv.m; ++t) {
-    const int j = rv.row[t];
-    if (rv.x[j] == bxp && rv.y[j] == byp) {
+    if (rv.xat(t) == bxp && rv.yat(t) == byp) {
       const int u = rv.next_site(t);
-      const int k = rv.row[u];
-      return rv.x[k] == ixp && rv.y[k] == iyp;
+      return rv.xat(u) == ixp && rv.yat(u) == iyp;
     }
   }
   return false;
@@ -588,7 +614,7 @@ __global__ __launch_bounds__(kBlock) void k_vor_check(const int32_t* __restrict_
     }
     if (!fail) {
       const int xi = x[i], yi = y[i];
-      const RowView rv = row_view(row, m, i, x, y);
+      const RowView rv = row_view(row, m, i, x, y, dmax);
       // the own site counts once in the area total: from its lowest index;
       // and every particle listed at the own site lists this one back
       bool lowest = true;
@@ -608,22 +634,22 @@ __global__ __launch_bounds__(kBlock) void k_vor_check(const int32_t* __restrict_
         if (!back) fail = true;
       }
       if (m - rv.own < 3) fail = true;
-      auto off = [&](int j, int& ox, int& oy) {
-        ox = wrap_axis(x[j] - xi, sh);
-        oy = wrap_axis(y[j] - yi, sh);
+      auto off = [&](int t, int& ox, int& oy) {  // entry t's offset
+        ox = wrap_axis(rv.xat(t) - xi, sh);
+        oy = wrap_axis(rv.yat(t) - yi, sh);
       };
       const int t0 = fail ? 0 : rv.site_start(rv.own);
       int ta = t0, tb = fail ? 0 : rv.next_site(t0);
       int ax, ay, bx, by;
       if (!fail) {
-        off(row[ta], ax, ay);
-        off(row[tb], bx, by);
+        off(ta, ax, ay);
+        off(tb, bx, by);
       }
       int wraps = 0, nsites = 0;
       for (int guard = 0; guard < m && !fail; ++guard) {
         const int tc = rv.next_site(tb);
         int cx, cy;
-        off(row[tc], cx, cy);
+        off(tc, cx, cy);
         if (abs(ax) >= quarter || abs(ay) >= quarter || (ax == 0 && ay == 0)) {
           fail = true;
           break;
@@ -633,7 +659,7 @@ __global__ __launch_bounds__(kBlock) void k_vor_check(const int32_t* __restrict_
         area2 += cr;
         if (!ccw_before(ax, ay, bx, by)) ++wraps;
         if (inc_sign_w(ax, ay, bx, by, cx, cy) <= 0) fail = true;
-        const int a = row[ta];
+        const int a = rv.idx(ta);
         const int ma = deg[a];
         if (ma < 3 || ma > dmax) {
           fail = true;
@@ -643,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void k_vor_check(const int32_t* __restrict_
           // at different positions) and no position is needed; otherwise the
           // row is walked site by site.
           const int32_t* rowa = ring + static_cast<long long>(a) * dmax;
-          const int b = row[tb];
+          const int b = rv.idx(tb);
           bool okidx = true, adjacent = false;
           if (ma <= kRowRead && dmax >= kRowRead) {
             // the usual short row: its first kRowRead entries read together
@@ -666,7 +692,7 @@ __global__ __launch_bounds__(kBlock) void k_vor_check(const int32_t* __restrict_
               adjacent = adjacent || (q == b && rowa[u + 1 < ma ? u + 1 : 0] == i);
             }
           }
-          if (!okidx || (!adjacent && !row_holds_then(row_view(rowa, ma, a, x, y), x[b], y[b], xi, yi)))
+          if (!okidx || (!adjacent && !row_holds_then(row_view(rowa, ma, a, x, y, dmax), rv.xat(tb), rv.yat(tb), xi, yi)))
             fail = true;
         }
         ++nsites;
@@ -717,14 +743,13 @@ __global__ __launch_bounds__(kBlock) void k_vor_sweep(DevWs w, const int32_t* __
       const int sh = 32 - w.log2_box;
       const int m = deg[i];
       int32_t* row = ring + static_cast<long long>(i) * dmax;
-      const RowView rv = row_view(row, m, i, x, y);
+      const RowView rv = row_view(row, m, i, x, y, dmax);
       const int xi = x[i], yi = y[i];
       // the first entry of the site with the smallest angle
       int t0 = rv.own;
-      int bx = wrap_axis(x[row[t0]] - xi, sh), by = wrap_axis(y[row[t0]] - yi, sh);
+      int bx = wrap_axis(rv.xat(t0) - xi, sh), by = wrap_axis(rv.yat(t0) - yi, sh);
       for (int t = rv.own + 1; t < m; ++t) {
-        const int j = row[t];
-        const int ox = wrap_axis(x[j] - xi, sh), oy = wrap_axis(y[j] - yi, sh);
+        const int ox = wrap_axis(rv.xat(t) - xi, sh), oy = wrap_axis(rv.yat(t) - yi, sh);
         if (ccw_before(ox, oy, bx, by)) {
           t0 = t;
           bx = ox;
