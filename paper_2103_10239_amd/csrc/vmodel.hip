@@ -314,41 +314,41 @@ __global__ __launch_bounds__(kBlock) void k_vm_forces(const int32_t* __restrict_
   fy[i] = ok ? F.y : 0.0;
 }
 
-// Eq. (3) over all cells, one workgroup (a fixed summation order, so the
-// same inputs give the same bits).
-constexpr int kEBlock = 1024;
-__global__ __launch_bounds__(kEBlock) void k_vm_energy(const double* __restrict__ area,
-                                                       const double* __restrict__ perim, int n, VmArgs va,
-                                                       double* __restrict__ energy) {
-  __shared__ double part[kEBlock];
-  // eight independent partial sums per lane (eight loads in flight), then
-  // combined in a fixed order
-  constexpr int kU = 8;
-  double acc[kU];
-#pragma unroll
-  for (int u = 0; u < kU; ++u) acc[u] = 0.0;
-  int i = threadIdx.x;
-  for (; i + (kU - 1) * kEBlock < n; i += kU * kEBlock) {
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const double da = area[i + u * kEBlock] - va.a0, dp = perim[i + u * kEBlock] - va.p0;
-      acc[u] += va.ka * da * da + va.kp * dp * dp;
-    }
-  }
-  for (; i < n; i += kEBlock) {
+// Eq. (3) over many workgroups, still in a fixed order: workgroup g sums
+// the cells of its contiguous share (lanes, then a fixed tree) into part[g];
+// one workgroup then sums the parts in a fixed tree.  The parts go into the
+// force array before the force pass overwrites it.
+constexpr int kEParts = 256;
+__global__ __launch_bounds__(kBlock) void k_vm_energy_part(const double* __restrict__ area,
+                                                           const double* __restrict__ perim, int n, VmArgs va,
+                                                           double* __restrict__ part) {
+  __shared__ double red[kBlock];
+  const int chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int b = blockIdx.x * chunk, e = min(n, b + chunk);
+  double acc = 0.0;
+  for (int i = b + threadIdx.x; i < e; i += kBlock) {
     const double da = area[i] - va.a0, dp = perim[i] - va.p0;
-    acc[0] += va.ka * da * da + va.kp * dp * dp;
+    acc += va.ka * da * da + va.kp * dp * dp;
   }
-  double e = 0.0;
-#pragma unroll
-  for (int u = 0; u < kU; ++u) e += acc[u];
-  part[threadIdx.x] = e;
+  red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = kEBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *energy = part[0];
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kEParts) void k_vm_energy_sum(const double* __restrict__ part, int np,
+                                                           double* __restrict__ energy) {
+  __shared__ double red[kEParts];
+  red[threadIdx.x] = static_cast<int>(threadIdx.x) < np ? part[threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int h = kEParts / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *energy = red[0];
 }
 
 }  // namespace
@@ -361,9 +361,14 @@ hipError_t launch_voronoi_forces(const int32_t* x, const int32_t* y, int32_t n, 
   const int nb = (n + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_vm_cells, dim3(nb), dim3(kBlock), 0, s, x, y, n, log2_box, dmax, ring, deg, area,
                      perim, vert, err);
+  if (energy) {
+    // (one workgroup alone read the cells at one CU's bandwidth: 0.25 ms at 2^20)
+    const int np = n < kEParts ? n : kEParts;
+    hipLaunchKernelGGL(k_vm_energy_part, dim3(np), dim3(kBlock), 0, s, area, perim, n, va, fx);
+    hipLaunchKernelGGL(k_vm_energy_sum, dim3(1), dim3(kEParts), 0, s, fx, np, energy);
+  }
   hipLaunchKernelGGL(k_vm_forces, dim3(nb), dim3(kBlock), 0, s, x, y, n, log2_box, dmax, ring, deg, area,
                      perim, va, fx, fy, vert, err);
-  if (energy) hipLaunchKernelGGL(k_vm_energy, dim3(1), dim3(kEBlock), 0, s, area, perim, n, va, energy);
   return hipGetLastError();
 }
 
