@@ -366,13 +366,19 @@ __global__ __launch_bounds__(kBlock) void k_coarse_scatter(const int32_t* __rest
 // Per bin: counting sort of its particles by cell in LDS.  The first
 // kFineU entries of each lane stay in registers between the count and the
 // scatter (a bin holds about kFineU * kBlock particles at the mean density
-// the cell width is tuned for); entries beyond are read twice.
+// the cell width is tuned for); entries beyond are read twice.  A bin of at
+// most kFineStage particles is sorted into LDS first and written out in
+// order, lane t taking ranks t, t + kBlock, ...: the outputs then leave in
+// whole lines instead of one scattered 16- and 32-byte piece per particle.
+// Larger bins write each particle where it lands.
 constexpr int kFineU = 8;
+constexpr int kFineStage = 1280;
 
 template <bool kFused>
 __device__ __forceinline__ void fine_sort_body(const DevWs& w, int bin, uint32_t step_lo, uint32_t step_hi,
                                                uint32_t sys_id, uint32_t seed_lo, uint32_t seed_hi) {
   __shared__ __align__(16) int h[kFineCells];
+  __shared__ __align__(16) int4 stage[kFineStage];
   __shared__ int s_wsum[kBlock / 64];
   if (!ws_header_ok(w)) return;
   const int64_t m = static_cast<int64_t>(w.nbins) * w.nblk;
@@ -473,10 +479,9 @@ __device__ __forceinline__ void fine_sort_body(const DevWs& w, int bin, uint32_t
   }
   if (bin == w.nbins - 1 && threadIdx.x == 0) w.start[w.C] = b1;
   __syncthreads();
-  auto place = [&](const int4& e, int p) {
-    const int cl = cell_of(e);
-    if (static_cast<uint32_t>(cl) >= static_cast<uint32_t>(S)) return;
-    const int pos = b0 + atomicAdd(&h[cl], 1);
+  // Particle e at sorted position pos: its entry, and with kFused the unit
+  // vectors of its heading and of its noise draw.
+  auto emit = [&](const int4& e, int pos) {
     uint32_t word = 0u;
     if (kFused) {
       const uint4 blk = Philox::block(make_uint4(static_cast<uint32_t>(e.z) >> 2, step_lo, step_hi, sys_id),
@@ -489,12 +494,25 @@ __device__ __forceinline__ void fine_sort_body(const DevWs& w, int bin, uint32_t
       w.cs[2 * pos + 1] = make_double2(xc, xs);  // the random unit vector xi of Eq. (2)
     }
     w.sorted[pos] = make_int4(e.x, e.y, e.z, static_cast<int>(word));
-    (void)p;
+  };
+  const bool staged = b1 - b0 <= kFineStage;
+  auto place = [&](const int4& e) {
+    const int cl = cell_of(e);
+    if (static_cast<uint32_t>(cl) >= static_cast<uint32_t>(S)) return;
+    const int r = atomicAdd(&h[cl], 1);
+    if (!staged)
+      emit(e, b0 + r);
+    else if (r < kFineStage)  // r < b1 - b0 unless the table is inconsistent
+      stage[r] = e;
   };
 #pragma unroll
   for (int u = 0; u < kFineU; ++u)
-    if (p0 + u * kBlock < b1) place(ev[u], p0 + u * kBlock);
-  for (int p = p0 + kFineU * kBlock; p < b1; p += kBlock) place(w.coarse[p], p);
+    if (p0 + u * kBlock < b1) place(ev[u]);
+  for (int p = p0 + kFineU * kBlock; p < b1; p += kBlock) place(w.coarse[p]);
+  if (staged) {
+    __syncthreads();
+    for (int r = threadIdx.x; r < b1 - b0; r += kBlock) emit(stage[r], b0 + r);
+  }
   if (bin == 0 && threadIdx.x == 0) w.hdr->built = kBuilt;
 }
 
