@@ -280,7 +280,10 @@ __device__ __forceinline__ bool in_box(int xi, int yi, const DevWs& w) {
 
 // The two-level kernels take kCoarseP particles per workgroup, kCoarseU per
 // lane: every lane issues all its loads before its first LDS atomic, so that
-// a workgroup has its whole share in flight at once.
+// a workgroup has its whole share in flight at once.  Consecutive blocks run
+// on one XCD: the pieces that blocks b, b + 1, ... write into a bin's range
+// (and into a row of the histogram) are adjacent, and meet in that XCD's L2
+// as whole lines.
 constexpr int kCoarseU = kCoarseP / kBlock;
 
 __device__ __forceinline__ void coarse_count_body(const int32_t* __restrict__ x,
@@ -320,7 +323,7 @@ __device__ __forceinline__ void coarse_count_body(const int32_t* __restrict__ x,
 
 __global__ __launch_bounds__(kBlock) void k_coarse_count(const int32_t* __restrict__ x,
                                                          const int32_t* __restrict__ y, DevWs w) {
-  coarse_count_body(x, y, w, blockIdx.x);
+  coarse_count_body(x, y, w, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 template <bool kFused>
@@ -360,7 +363,7 @@ template <bool kFused>
 __global__ __launch_bounds__(kBlock) void k_coarse_scatter(const int32_t* __restrict__ x,
                                                            const int32_t* __restrict__ y,
                                                            const float* __restrict__ theta, DevWs w) {
-  coarse_scatter_body<kFused>(x, y, theta, w, blockIdx.x);
+  coarse_scatter_body<kFused>(x, y, theta, w, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Per bin: counting sort of its particles by cell in LDS.  The first
