@@ -369,11 +369,11 @@ __global__ __launch_bounds__(kBlock) void k_coarse_scatter(const int32_t* __rest
 // Per bin: counting sort of its particles by cell in LDS.  The first
 // kFineU entries of each lane stay in registers between the count and the
 // scatter (a bin holds about kFineU * kBlock particles at the mean density
-// the cell width is tuned for); entries beyond are read twice.  A bin of at
-// most kFineStage particles is sorted into LDS first and written out in
-// order, lane t taking ranks t, t + kBlock, ...: the outputs then leave in
-// whole lines instead of one scattered 16- and 32-byte piece per particle.
-// Larger bins write each particle where it lands.
+// the cell width is tuned for); entries beyond are read twice.  The sorted
+// entries pass through an LDS stage of kFineStage ranks and are written out
+// in order, lane t taking ranks t, t + kBlock, ...: the outputs then leave
+// in whole lines instead of one scattered 16- and 32-byte piece per
+// particle.
 constexpr int kFineU = 8;
 constexpr int kFineStage = 1280;
 
@@ -498,23 +498,38 @@ __device__ __forceinline__ void fine_sort_body(const DevWs& w, int bin, uint32_t
     }
     w.sorted[pos] = make_int4(e.x, e.y, e.z, static_cast<int>(word));
   };
-  const bool staged = b1 - b0 <= kFineStage;
-  auto place = [&](const int4& e) {
-    const int cl = cell_of(e);
-    if (static_cast<uint32_t>(cl) >= static_cast<uint32_t>(S)) return;
-    const int r = atomicAdd(&h[cl], 1);
-    if (!staged)
-      emit(e, b0 + r);
-    else if (r < kFineStage)  // r < b1 - b0 unless the table is inconsistent
-      stage[r] = e;
-  };
+  // A bin whose entries all sit in registers is written in rounds of
+  // kFineStage ranks: each round stages its ranks' entries in LDS and writes
+  // them out in order.  Larger bins write each particle where it lands.
+  const int nbin = b1 - b0;
+  const bool staged = nbin <= kFineU * kBlock;
+  int rv[kFineU];
 #pragma unroll
-  for (int u = 0; u < kFineU; ++u)
-    if (p0 + u * kBlock < b1) place(ev[u]);
-  for (int p = p0 + kFineU * kBlock; p < b1; p += kBlock) place(w.coarse[p]);
+  for (int u = 0; u < kFineU; ++u) {
+    rv[u] = -1;
+    if (p0 + u * kBlock < b1) {
+      const int cl = cell_of(ev[u]);
+      if (static_cast<uint32_t>(cl) < static_cast<uint32_t>(S)) {
+        rv[u] = atomicAdd(&h[cl], 1);
+        if (!staged) emit(ev[u], b0 + rv[u]);
+      }
+    }
+  }
+  for (int p = p0 + kFineU * kBlock; p < b1; p += kBlock) {  // only when !staged
+    const int4 e = w.coarse[p];
+    const int cl = cell_of(e);
+    if (static_cast<uint32_t>(cl) < static_cast<uint32_t>(S)) emit(e, b0 + atomicAdd(&h[cl], 1));
+  }
   if (staged) {
-    __syncthreads();
-    for (int r = threadIdx.x; r < b1 - b0; r += kBlock) emit(stage[r], b0 + r);
+    for (int q0 = 0; q0 < nbin; q0 += kFineStage) {
+      __syncthreads();  // the previous round has read the stage
+#pragma unroll
+      for (int u = 0; u < kFineU; ++u)
+        if (static_cast<uint32_t>(rv[u] - q0) < static_cast<uint32_t>(kFineStage)) stage[rv[u] - q0] = ev[u];
+      __syncthreads();
+      const int nr = min(kFineStage, nbin - q0);
+      for (int r = threadIdx.x; r < nr; r += kBlock) emit(stage[r], b0 + q0 + r);
+    }
   }
   if (bin == 0 && threadIdx.x == 0) w.hdr->built = kBuilt;
 }
