@@ -278,16 +278,20 @@ __device__ __forceinline__ bool in_box(int xi, int yi, const DevWs& w) {
          static_cast<uint32_t>(yi) < static_cast<uint32_t>(w.box);
 }
 
-// The two-level kernels take kCoarseP particles per workgroup, kCoarseU per
-// lane: every lane issues all its loads before its first LDS atomic, so that
-// a workgroup has its whole share in flight at once.  Consecutive blocks run
-// on one XCD: the pieces that blocks b, b + 1, ... write into a bin's range
-// (and into a row of the histogram) are adjacent, and meet in that XCD's L2
-// as whole lines.
-constexpr int kCoarseU = kCoarseP / kBlock;
+// The two-level kernels take kCoarseP particles per workgroup of kT lanes,
+// kCoarseP / kT per lane: every lane issues all its loads before its first
+// LDS atomic, so that a workgroup has its whole share in flight at once.
+// The single-system launches take kCoarseT lanes (four waves per SIMD on the
+// one workgroup a CU holds); the batched stages, whose kernels also run the
+// one-level bodies, take kBlock.  Consecutive blocks run on one XCD: the
+// pieces that blocks b, b + 1, ... write into a bin's range (and into a row
+// of the histogram) are adjacent, and meet in that XCD's L2 as whole lines.
+constexpr int kCoarseT = 1024;
 
+template <int kT>
 __device__ __forceinline__ void coarse_count_body(const int32_t* __restrict__ x,
                                                   const int32_t* __restrict__ y, const DevWs& w, int b) {
+  constexpr int kU = kCoarseP / kT;
   __shared__ int h[kCoarseBins];
   if (b == 0) {
     reset_scan(w.scan_h, w.nb_scan_h);
@@ -297,18 +301,18 @@ __device__ __forceinline__ void coarse_count_body(const int32_t* __restrict__ x,
     }
   }
   const int i0 = b * kCoarseP + threadIdx.x, i1 = min((b + 1) * kCoarseP, w.n);
-  int xv[kCoarseU], yv[kCoarseU];
+  int xv[kU], yv[kU];
 #pragma unroll
-  for (int u = 0; u < kCoarseU; ++u) {
-    const int i = i0 + u * kBlock;
+  for (int u = 0; u < kU; ++u) {
+    const int i = i0 + u * kT;
     xv[u] = i < i1 ? x[i] : 0;
     yv[u] = i < i1 ? y[i] : 0;
   }
-  for (int t = threadIdx.x; t < w.nbins; t += kBlock) h[t] = 0;
+  for (int t = threadIdx.x; t < w.nbins; t += kT) h[t] = 0;
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < kCoarseU; ++u) {
-    if (i0 + u * kBlock >= i1) break;
+  for (int u = 0; u < kU; ++u) {
+    if (i0 + u * kT >= i1) break;
     if (!in_box(xv[u], yv[u], w)) {
       set_err(w.hdr, NM_E_RANGE);
       continue;
@@ -317,36 +321,37 @@ __device__ __forceinline__ void coarse_count_body(const int32_t* __restrict__ x,
     atomicAdd(&h[static_cast<int>(c >> w.sb)], 1);
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < w.nbins; t += kBlock)
+  for (int t = threadIdx.x; t < w.nbins; t += kT)
     w.hist[static_cast<int64_t>(t) * w.nblk + b] = h[t];
 }
 
-__global__ __launch_bounds__(kBlock) void k_coarse_count(const int32_t* __restrict__ x,
+__global__ __launch_bounds__(kCoarseT) void k_coarse_count(const int32_t* __restrict__ x,
                                                          const int32_t* __restrict__ y, DevWs w) {
-  coarse_count_body(x, y, w, xcd_tile(blockIdx.x, gridDim.x));
+  coarse_count_body<kCoarseT>(x, y, w, xcd_tile(blockIdx.x, gridDim.x));
 }
 
-template <bool kFused>
+template <bool kFused, int kT>
 __device__ __forceinline__ void coarse_scatter_body(const int32_t* __restrict__ x,
                                                     const int32_t* __restrict__ y,
                                                     const float* __restrict__ theta, const DevWs& w,
                                                     int b) {
+  constexpr int kU = kCoarseP / kT;
   __shared__ int cur[kCoarseBins];
   if (!ws_header_ok(w)) return;
   const int i0 = b * kCoarseP + threadIdx.x, i1 = min((b + 1) * kCoarseP, w.n);
-  int xv[kCoarseU], yv[kCoarseU], tv[kCoarseU];
+  int xv[kU], yv[kU], tv[kU];
 #pragma unroll
-  for (int u = 0; u < kCoarseU; ++u) {
-    const int i = i0 + u * kBlock;
+  for (int u = 0; u < kU; ++u) {
+    const int i = i0 + u * kT;
     xv[u] = i < i1 ? x[i] : 0;
     yv[u] = i < i1 ? y[i] : 0;
     tv[u] = (kFused && i < i1) ? __float_as_int(theta[i]) : 0;
   }
-  for (int t = threadIdx.x; t < w.nbins; t += kBlock) cur[t] = w.hist[static_cast<int64_t>(t) * w.nblk + b];
+  for (int t = threadIdx.x; t < w.nbins; t += kT) cur[t] = w.hist[static_cast<int64_t>(t) * w.nblk + b];
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < kCoarseU; ++u) {
-    const int i = i0 + u * kBlock;
+  for (int u = 0; u < kU; ++u) {
+    const int i = i0 + u * kT;
     if (i >= i1) break;
     if (!in_box(xv[u], yv[u], w)) continue;
     const int64_t c = static_cast<int64_t>(yv[u] >> w.log2_w) * w.G + (xv[u] >> w.log2_w);
@@ -360,10 +365,10 @@ __device__ __forceinline__ void coarse_scatter_body(const int32_t* __restrict__ 
 }
 
 template <bool kFused>
-__global__ __launch_bounds__(kBlock) void k_coarse_scatter(const int32_t* __restrict__ x,
+__global__ __launch_bounds__(kCoarseT) void k_coarse_scatter(const int32_t* __restrict__ x,
                                                            const int32_t* __restrict__ y,
                                                            const float* __restrict__ theta, DevWs w) {
-  coarse_scatter_body<kFused>(x, y, theta, w, xcd_tile(blockIdx.x, gridDim.x));
+  coarse_scatter_body<kFused, kCoarseT>(x, y, theta, w, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Per bin: counting sort of its particles by cell in LDS.  The first
@@ -570,7 +575,7 @@ __global__ __launch_bounds__(kBlock) void k_bb_count(BatchRef b) {
     int li;
     const BatchSys& d = batch_item(b, kStCount, it, li);
     if (d.w.nbins > 0)
-      coarse_count_body(d.x[d.parity], d.y[d.parity], d.w, li);
+      coarse_count_body<kBlock>(d.x[d.parity], d.y[d.parity], d.w, li);
     else
       bin_count_body(d.x[d.parity], d.y[d.parity], d.w, li);
     __syncthreads();  // the next item's LDS histogram
@@ -599,7 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_bb_scatter(BatchRef b) {
     const BatchSys& d = batch_item(b, kStScatter, it, li);
     const int p = d.parity;
     if (d.w.nbins > 0)
-      coarse_scatter_body<true>(d.x[p], d.y[p], d.th[p], d.w, li);
+      coarse_scatter_body<true, kBlock>(d.x[p], d.y[p], d.th[p], d.w, li);
     else
       scatter_body<true>(d.x[p], d.y[p], d.th[p], d.w, li, d.step_lo, d.step_hi, d.sys_id,
                          d.seed_lo, d.seed_hi);
@@ -630,19 +635,19 @@ hipError_t launch_build(const DevWs& w, const int32_t* x, const int32_t* y, cons
                         const nm_params* p, uint64_t step, hipStream_t s) {
   const bool fused = theta != nullptr && p != nullptr;
   if (w.nbins > 0 && w.n >= kCoarseMinN) {  // two-level
-    hipLaunchKernelGGL(k_coarse_count, dim3(w.nblk), dim3(kBlock), 0, s, x, y, w);
+    hipLaunchKernelGGL(k_coarse_count, dim3(w.nblk), dim3(kCoarseT), 0, s, x, y, w);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t m = static_cast<int64_t>(w.nbins) * w.nblk;
     e = launch_scan_rows(w.hist, m, w.scan_h, static_cast<int>((m + kScanTile - 1) / kScanTile), w.hdr, s);
     if (e != hipSuccess) return e;
     if (fused) {
-      hipLaunchKernelGGL(k_coarse_scatter<true>, dim3(w.nblk), dim3(kBlock), 0, s, x, y, theta, w);
+      hipLaunchKernelGGL(k_coarse_scatter<true>, dim3(w.nblk), dim3(kCoarseT), 0, s, x, y, theta, w);
       hipLaunchKernelGGL(k_fine_sort<true>, dim3(w.nbins), dim3(kBlock), 0, s, w,
                          static_cast<uint32_t>(step), static_cast<uint32_t>(step >> 32), p->sys_id,
                          static_cast<uint32_t>(p->seed), static_cast<uint32_t>(p->seed >> 32));
     } else {
-      hipLaunchKernelGGL(k_coarse_scatter<false>, dim3(w.nblk), dim3(kBlock), 0, s, x, y, theta, w);
+      hipLaunchKernelGGL(k_coarse_scatter<false>, dim3(w.nblk), dim3(kCoarseT), 0, s, x, y, theta, w);
       hipLaunchKernelGGL(k_fine_sort<false>, dim3(w.nbins), dim3(kBlock), 0, s, w, 0u, 0u, 0u, 0u, 0u);
     }
     return hipGetLastError();
