@@ -417,6 +417,54 @@ def test_two_level_binning_sampled(kind, w):
     assert np.array_equal(np.concatenate([idx_np[offs_np[r]:offs_np[r + 1]] for r in rows]), ri)
 
 
+def _coarse_bin_sizes(x, y, n, w):
+    """Particles per coarse bin under the workspace's sizing rule: at most 1024
+    bins of 2^sb cells, grown towards 1024 particles at the mean density, at
+    most 4096 cells."""
+    g = L // w
+    c = g * g
+    sb = 0
+    while (c >> sb) > 1024:
+        sb += 1
+    while (1 << sb) < 4096 and (n << sb) < 1024 * c:
+        sb += 1
+    lw = w.bit_length() - 1
+    cell = (y.astype(np.int64) >> lw) * g + (x.astype(np.int64) >> lw)
+    return np.bincount(cell >> sb)
+
+
+def test_fine_sort_stage_rounds_clustered():
+    # The fine sort writes a bin through its LDS stage of 1280 ranks, in two
+    # rounds for bins of 1281-2048 particles, and bins of more than 2048
+    # directly.  Three grids of one clustered system cover all three; the
+    # lists are exact, so every grid must give the same lists and the same
+    # fused step, which must match the oracle on sampled rows.
+    n, k = (1 << 18) + 77, 7
+    x, y, th = workloads.clustered(n)
+    sizes = {w: _coarse_bin_sizes(x, y, n, w) for w in (1024, 4096, 8192)}
+    assert ((sizes[1024] > 1280) & (sizes[1024] <= 2048)).any()
+    assert (sizes[8192] > 2048).any()
+    p = nm.make_params(L, v0=64, eta=0.2, seed=workloads.NOISE_SEED)
+    xd, yd = _dev(x, torch.int32), _dev(y, torch.int32)
+    outs = []
+    for w in sizes:
+        sysm = nm.System.create(x, y, th, k, p, cell_w=w)
+        sysm.step()
+        assert nm.check(sysm.ws) == 0
+        _device_invariants(xd, yd, sysm.nbr, k)
+        outs.append([t.cpu().numpy() for t in (sysm.nbr, sysm.x, sysm.y, sysm.theta)])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+    rows = np.concatenate([_sample_rows(n, 200, 5), [0, n - 1]]).astype(np.int32)
+    rn, _ = oracle.knn(x, y, L, k, rows=rows, with_d2=False)
+    assert np.array_equal(outs[0][0][rows], rn)
+    rx, ry, rt = oracle.align_step(x, y, th, L, nbr=rn, v0=64, eta=0.2, seed=workloads.NOISE_SEED,
+                                   rows=rows)
+    assert np.array_equal(outs[0][1][rows], rx) and np.array_equal(outs[0][2][rows], ry)
+    assert _angle_err(outs[0][3][rows], rt).max() <= TOL
+
+
 def test_two_level_binning_reports_range_error():
     n = (1 << 17) + 5
     x, y, th = workloads.uniform(n)
